@@ -1,0 +1,195 @@
+/*
+ * wc.h - workload consolidation of nested parallel work on AMD MI355X (gfx950).
+ *
+ * C ABI of libwc.so.  The library implements the consolidation schemes of
+ * Wu, Li & Becchi, "Compiler-Assisted Workload Consolidation for Efficient
+ * Dynamic Parallelism on GPU" (arXiv 1606.08150), Sec. IV, for the paper's
+ * irregular-loop problems (SSSP and SpMV over CSR, Sec. II.B and Fig. 1(b))
+ * and parallel-recursion problems (tree descendants and tree heights,
+ * Fig. 1(c), Sec. V).
+ *
+ * gfx950 has no device-side kernel launch, so a consolidated child kernel is
+ * an in-kernel drain of a consolidation buffer:
+ *   WC_WAVE  - one buffer per 64-lane wavefront, filled with a ballot/prefix
+ *              append; no barrier (the wave runs in lockstep, Sec. IV.B).
+ *   WC_BLOCK - one buffer per workgroup in LDS; a workgroup barrier separates
+ *              the inserts from the drain (Sec. IV.B).
+ *   WC_GRID  - one global buffer per grid, filled with wave-aggregated atomic
+ *              appends; the whole grid drains it after a grid-wide barrier
+ *              (a kernel boundary, or the counter barrier of Sec. IV.E inside a
+ *              persistent co-resident grid).
+ *   WC_FLAT  - no consolidation: each parent thread does all of its item's
+ *              work itself (the paper's flat "no-dp" baseline, Sec. V).
+ * All modes compute the same result; the consolidated child processes each
+ * buffered item exactly as the unconsolidated work would (Sec. IV.C).
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller; the library never
+ *    frees or retains them beyond the call's stream work.
+ *  - Work is enqueued on `stream`.  SSSP and the trees decide at run time how
+ *    many rounds/levels to run; with the relaunch driver (tune->driver = 0) the
+ *    host waits on device-published round counts, so the call returns once the
+ *    last round has been enqueued.  With the persistent driver (driver = 1) the
+ *    call only enqueues.  Either way the caller synchronizes before reading
+ *    outputs, unless `stats` is non-NULL, in which case the call synchronizes
+ *    the stream itself to fill it in.
+ *  - A context owns one pre-allocated device pool (the custom allocator of
+ *    Sec. IV.E) from which every call carves its buffers.  Calls that share a
+ *    context must be issued on one stream (or be externally serialized).
+ *  - Invalid arguments return WC_EINVAL before anything is enqueued; HIP
+ *    failures return WC_EHIP; pool exhaustion that cannot be grown returns
+ *    WC_ENOMEM.  wc_last_error() then describes the failure.  No C++
+ *    exception crosses this boundary.
+ *  - Integer results (distances, descendant counts, heights) are identical in
+ *    every mode and launch configuration.  SpMV results are within
+ *    |y - y_ref| <= 1e-5 * sum_j |a_ij x_j| per row of the exact product and
+ *    are bitwise reproducible for a fixed mode and tune.
+ */
+#ifndef WC_H
+#define WC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Consolidation granularity: the consldt(warp|block|grid) clause of Table I, plus flat. */
+typedef enum { WC_FLAT = 0, WC_WAVE = 1, WC_BLOCK = 2, WC_GRID = 3 } wc_mode;
+
+typedef enum {
+    WC_OK = 0,
+    WC_EINVAL = -1,    /* bad argument; nothing was enqueued */
+    WC_ENOMEM = -2,    /* device pool could not be (re)allocated */
+    WC_EOVERFLOW = -3, /* a consolidation buffer overflowed and tune->allow_fallback < 0 */
+    WC_ETIMEOUT = -4,  /* a bounded device-side or host-side wait expired */
+    WC_EHIP = -5       /* a HIP runtime call failed */
+} wc_status;
+
+/* Directed graph / sparse matrix, CSR with row = source vertex.
+ * row_ptr[n+1] (row_ptr[0] = 0, row_ptr[n] = m, non-decreasing), col[m] in [0, n). */
+typedef struct {
+    int32_t n;
+    int32_t m;
+    const int32_t *row_ptr;
+    const int32_t *col;
+} wc_csr;
+
+/* Rooted tree, root = node 0.  parent[n] (parent[0] = -1), children in CSR form:
+ * child_ptr[n+1] (child_ptr[n] = n-1) and child[n-1]. */
+typedef struct {
+    int32_t n;
+    const int32_t *parent;
+    const int32_t *child_ptr;
+    const int32_t *child;
+} wc_tree;
+
+/* Launch and buffer configuration (the threads/blocks/buffer clauses of Table I
+ * and the configuration rules of Sec. IV.E).  A zero (or negative) field means
+ * "use the library's heuristic"; pass NULL for all defaults. */
+typedef struct {
+    int32_t threshold;      /* items with more than this much work are buffered (the
+                               THRESHOLD of Fig. 1(b)); <= 0: per-problem default */
+    int32_t block_threads;  /* workgroup size: 64, 128, 256, 512 or 1024; <= 0: 256 */
+    int32_t grid_blocks;    /* workgroups of the moldable drain/persistent grid;
+                               <= 0: resident maximum from the occupancy query (KC_1) */
+    int32_t items_per_lane; /* the "const" of the Sec. IV.E buffer-size estimate: work
+                               items per drain lane; grid-level chunks hold
+                               64 * items_per_lane elements; <= 0: 4 */
+    int32_t driver;         /* 0: one launch per round/level (host relaunch);
+                               1: one persistent co-resident launch with a grid barrier */
+    int32_t allow_fallback; /* on buffer overflow: >= 0 (default) the item that does not fit
+                               is processed inline and stats->overflowed is set;
+                               < 0 the call returns WC_EOVERFLOW after its work ends */
+    int64_t buf_capacity;   /* grid/queue buffer capacity in entries; <= 0: large enough
+                               that no overflow can occur */
+} wc_tune;
+
+/* Device-side counters of one call (filled when `stats` is non-NULL). */
+typedef struct {
+    int32_t rounds;          /* SSSP rounds or tree levels executed */
+    int32_t overflowed;      /* 1 if any buffer overflowed (items were processed inline) */
+    int64_t items_buffered;  /* work items inserted into consolidation buffers */
+    int64_t dispatches;      /* consolidated child dispatches (non-empty buffers drained) */
+    int64_t edges_processed; /* edges relaxed / nonzeros multiplied / children visited */
+    float ms;                /* wall time of the call on its stream, from HIP events */
+} wc_stats;
+
+typedef struct wc_ctx wc_ctx;
+
+/* Create a context on `device` with a pre-allocated pool of `pool_bytes`
+ * (0: 512 MiB).  The pool grows on demand when a call needs more.
+ * Returns WC_EINVAL for a bad device or NULL out, WC_EHIP/WC_ENOMEM on failure. */
+wc_status wc_ctx_create(int device, size_t pool_bytes, wc_ctx **out);
+
+/* Free the pool and the context.  Waits for the device first.  NULL is a no-op. */
+wc_status wc_ctx_destroy(wc_ctx *ctx);
+
+/* Single-source shortest paths (Fig. 1(b)): dist[v] = minimum total weight of a
+ * path src -> v over edges with weights w[m] (uint32, >= 1), UINT32_MAX if v is
+ * unreachable.  Frontier-driven rounds: every vertex whose distance improved is
+ * expanded in the next round; a frontier vertex with more than `threshold`
+ * out-edges is consolidated per `mode`, a lighter one relaxes its edges inline.
+ * dist[n] is written entirely.  Distances must stay below UINT32_MAX. */
+wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, uint32_t *dist, wc_mode mode,
+                  const wc_tune *tune, hipStream_t stream, wc_stats *stats);
+
+/* Sparse matrix-vector product y = A x, A in CSR with values val[m] (fp32),
+ * x[n] and y[n] fp32 (square n x n).  A row with more than `threshold`
+ * nonzeros is consolidated per `mode`; a lighter row is summed inline by one
+ * lane.  y[n] is written entirely; empty rows give +0. */
+wc_status wc_spmv(wc_ctx *ctx, const wc_csr *a, const float *val, const float *x, float *y, wc_mode mode,
+                  const wc_tune *tune, hipStream_t stream, wc_stats *stats);
+
+/* Tree descendants (recursion of Fig. 1(c)): desc[v] = number of proper
+ * descendants of v.  A node with children is a recursive call whose work is
+ * consolidated per `mode`; a leaf gets 0; the post-work folds each child c
+ * into its parent as 1 + desc[c]. */
+wc_status wc_tree_descendants(wc_ctx *ctx, const wc_tree *t, int32_t *desc, wc_mode mode, const wc_tune *tune,
+                              hipStream_t stream, wc_stats *stats);
+
+/* Tree heights: height[v] = edges on the longest downward path from v (leaf 0);
+ * same traversal as wc_tree_descendants with the fold max(1 + height[c]). */
+wc_status wc_tree_height(wc_ctx *ctx, const wc_tree *t, int32_t *height, wc_mode mode, const wc_tune *tune,
+                         hipStream_t stream, wc_stats *stats);
+
+/* Per-kernel timing.  When enabled, every kernel the library launches on a
+ * context is bracketed by two HIP events recorded on the launch stream, so its
+ * device execution time can be read back afterwards.  Enabling or disabling
+ * waits for the device and discards earlier records. */
+wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable);
+
+/* Aggregate of the recorded launches of the index-th distinct kernel name (in
+ * first-launch order): its name (a static string), launch count, total and
+ * largest event-measured duration in milliseconds.  Waits for the recorded
+ * events.  Returns WC_EINVAL when index is past the last name. */
+wc_status wc_ctx_kernel_stats(wc_ctx *ctx, int32_t index, const char **name, int64_t *launches, double *total_ms,
+                              double *max_ms);
+
+/* Thread-local description of the last non-WC_OK status on this thread. */
+const char *wc_last_error(void);
+
+/* Library version string. */
+const char *wc_version(void);
+
+/* ---- host-side planning helpers (no device work; usable without a GPU) ---- */
+
+/* Per-buffer capacity estimate of Sec. IV.E: total_thread * total_buff_var * items_per_thread. */
+int64_t wc_per_buffer_size(int64_t total_thread, int64_t total_buff_var, int64_t items_per_thread);
+
+/* KC_X of Sec. IV.E: (blocks, threads) downgraded to (ceil(blocks / x), threads). */
+void wc_kc_config(int64_t blocks, int64_t threads, int64_t x, int64_t *out_blocks, int64_t *out_threads);
+
+/* Fill `out` with the library's defaults for a problem ("sssp", "spmv", "tree")
+ * and mode, given the occupancy-derived resident workgroup count.  Returns
+ * WC_EINVAL for an unknown problem or mode. */
+wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_blocks, wc_tune *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WC_H */

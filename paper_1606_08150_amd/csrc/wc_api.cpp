@@ -1,0 +1,365 @@
+// Context, pre-allocated pool, error reporting and configuration of libwc.
+//
+// The pool is the customized allocator of Sec. IV.E: one device allocation
+// made up front, from which each call carves its consolidation buffers, so no
+// allocation happens while kernels run (the paper measures per-allocation
+// overhead as the main cost of the default and halloc allocators, Sec. V.A).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <climits>
+#include <cstring>
+#include <string>
+#include <thread>
+
+#include "wc_internal.h"
+
+namespace wc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+wc_status fail(wc_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+wc_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return WC_EHIP;
+}
+
+static wc_status pool_alloc(wc_ctx *ctx, size_t bytes)
+{
+    if (ctx->pool) {
+        hipError_t e = hipFree(ctx->pool);
+        ctx->pool = nullptr;
+        ctx->pool_bytes = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree(pool)");
+    }
+    hipError_t e = hipMalloc(&ctx->pool, bytes);
+    if (e != hipSuccess) {
+        ctx->pool = nullptr;
+        (void)hipGetLastError();
+        return fail(WC_ENOMEM, "cannot allocate a device pool of " + std::to_string(bytes) + " bytes");
+    }
+    ctx->pool_bytes = bytes;
+    return WC_OK;
+}
+
+wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream)
+{
+    ctx->pool_off = 0;
+    if (bytes <= ctx->pool_bytes) return WC_OK;
+    // earlier calls may still be using the pool: drain before replacing it
+    WC_HIP(hipStreamSynchronize(stream));
+    WC_HIP(hipDeviceSynchronize());
+    size_t grow = ctx->pool_bytes * 2;
+    return pool_alloc(ctx, bytes > grow ? bytes : grow);
+}
+
+void pool_reset(wc_ctx *ctx) { ctx->pool_off = 0; }
+
+int resident_blocks(wc_ctx *ctx, const void *kernel, int block)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    return per_cu * ctx->num_cus;
+}
+
+static hipEvent_t take_event(wc_ctx *ctx)
+{
+    if (!ctx->spare_events.empty()) {
+        hipEvent_t e = ctx->spare_events.back();
+        ctx->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void recycle_records(wc_ctx *ctx)
+{
+    for (auto &r : ctx->records) {
+        ctx->spare_events.push_back(r.start);
+        ctx->spare_events.push_back(r.stop);
+    }
+    ctx->records.clear();
+}
+
+wc_status launch(wc_ctx *ctx, const char *name, const void *kernel, dim3 grid, dim3 block, void **args,
+                 hipStream_t stream)
+{
+    if (!ctx->timing) {
+        WC_HIP(hipLaunchKernel(kernel, grid, block, args, 0, stream));
+        return WC_OK;
+    }
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return fail(WC_EHIP, "hipEventCreate failed");
+    WC_HIP(hipEventRecord(a, stream));
+    WC_HIP(hipLaunchKernel(kernel, grid, block, args, 0, stream));
+    WC_HIP(hipEventRecord(b, stream));
+    ctx->records.push_back({name, a, b});
+    return WC_OK;
+}
+
+static int default_threshold(const char *problem, wc_mode mode)
+{
+    if (mode == WC_FLAT) return INT_MAX;
+    if (!strcmp(problem, "tree")) return 0;  // every node with children is a recursive call (Fig. 1(c))
+    return 32;
+}
+
+wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_tune *tune, int resident,
+                       Config *out)
+{
+    (void)ctx;
+    wc_tune t;
+    wc_status st = wc_default_tune(problem, mode, resident, &t);
+    if (st != WC_OK) return st;
+    if (tune) {
+        if (tune->threshold > 0 && mode != WC_FLAT && strcmp(problem, "tree")) t.threshold = tune->threshold;
+        if (tune->block_threads > 0) t.block_threads = tune->block_threads;
+        if (tune->grid_blocks > 0) t.grid_blocks = tune->grid_blocks;
+        if (tune->items_per_lane > 0) t.items_per_lane = tune->items_per_lane;
+        if (tune->driver > 0) t.driver = tune->driver;
+        t.allow_fallback = tune->allow_fallback;
+        if (tune->buf_capacity > 0) t.buf_capacity = tune->buf_capacity;
+    }
+    int b = t.block_threads;
+    if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
+        return fail(WC_EINVAL, "block_threads must be one of 64, 128, 256, 512, 1024");
+    if (t.items_per_lane > 64) return fail(WC_EINVAL, "items_per_lane must be at most 64");
+    if (t.driver != 0 && t.driver != 1) return fail(WC_EINVAL, "driver must be 0 (relaunch) or 1 (persistent)");
+    out->threshold = t.threshold;
+    out->block = t.block_threads;
+    out->grid = t.grid_blocks;
+    out->items_per_lane = t.items_per_lane;
+    out->driver = t.driver;
+    out->fail_on_overflow = t.allow_fallback < 0;
+    out->buf_capacity = t.buf_capacity;
+    return WC_OK;
+}
+
+// Clears the per-call device counters with a kernel rather than a memset node,
+// so that a captured graph replays it correctly.
+__global__ void zero_stats(DevStats *s)
+{
+    if (threadIdx.x == 0) *s = DevStats{};
+}
+
+wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats)
+{
+    if (stats) memset(stats, 0, sizeof(*stats));
+    void *args[] = {&ctx->dstats};
+    wc_status st = launch(ctx, "zero_stats", reinterpret_cast<const void *>(&zero_stats), dim3(1), dim3(64), args,
+                          stream);
+    if (st != WC_OK) return st;
+    if (stats) WC_HIP(hipEventRecord(ctx->ev_start, stream));
+    return WC_OK;
+}
+
+wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow)
+{
+    DevStats ds;
+    if (stats) {
+        WC_HIP(hipEventRecord(ctx->ev_stop, stream));
+        WC_HIP(hipMemcpyAsync(&ds, ctx->dstats, sizeof(ds), hipMemcpyDeviceToHost, stream));
+        WC_HIP(hipStreamSynchronize(stream));
+        float ms = 0.f;
+        WC_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+        stats->rounds = rounds;
+        stats->overflowed = ds.overflowed;
+        stats->items_buffered = (int64_t)ds.items_buffered;
+        stats->dispatches = (int64_t)ds.dispatches;
+        stats->edges_processed = (int64_t)ds.edges_processed;
+        stats->ms = ms;
+    } else if (fail_on_overflow) {
+        WC_HIP(hipMemcpyAsync(&ds, ctx->dstats, sizeof(ds), hipMemcpyDeviceToHost, stream));
+        WC_HIP(hipStreamSynchronize(stream));
+    } else {
+        WC_HIP(hipGetLastError());
+        return WC_OK;
+    }
+    WC_HIP(hipGetLastError());
+    if (ds.timed_out) return fail(WC_ETIMEOUT, "a device-side wait exceeded its spin limit");
+    if (fail_on_overflow && ds.overflowed)
+        return fail(WC_EOVERFLOW, "a consolidation buffer overflowed (buf_capacity too small)");
+    return WC_OK;
+}
+
+void clear_round_slot(wc_ctx *ctx, int r)
+{
+    reinterpret_cast<volatile int *>(ctx->host_ring)[r % kHostRing] = -1;
+}
+
+wc_status wait_round_count(wc_ctx *ctx, int r, int *count)
+{
+    volatile int *slot = reinterpret_cast<volatile int *>(ctx->host_ring) + (r % kHostRing);
+    auto t0 = std::chrono::steady_clock::now();
+    long spins = 0;
+    for (;;) {
+        int v = *slot;
+        if (v != -1) {
+            *count = v;
+            return WC_OK;
+        }
+        if (++spins > 2000) {
+            std::this_thread::yield();
+            if ((spins & 1023) == 0) {
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return hip_fail(e, "kernel launch while waiting for a round count");
+                double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (s > 120.0) return fail(WC_ETIMEOUT, "round count never published (120 s)");
+            }
+        }
+    }
+}
+
+}  // namespace wc
+
+using namespace wc;
+
+extern "C" {
+
+const char *wc_last_error(void) { return g_last_error.c_str(); }
+
+const char *wc_version(void) { return "wc 0.1 (gfx950)"; }
+
+int64_t wc_per_buffer_size(int64_t total_thread, int64_t total_buff_var, int64_t items_per_thread)
+{
+    return total_thread * total_buff_var * items_per_thread;
+}
+
+void wc_kc_config(int64_t blocks, int64_t threads, int64_t x, int64_t *out_blocks, int64_t *out_threads)
+{
+    if (x < 1) x = 1;
+    int64_t b = (blocks + x - 1) / x;
+    *out_blocks = b < 1 ? 1 : b;
+    *out_threads = threads;
+}
+
+wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_blocks, wc_tune *out)
+{
+    if (!problem || !out) return fail(WC_EINVAL, "NULL argument");
+    if (strcmp(problem, "sssp") && strcmp(problem, "spmv") && strcmp(problem, "tree"))
+        return fail(WC_EINVAL, std::string("unknown problem ") + problem);
+    if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "mode must be flat, wave, block or grid");
+    out->threshold = default_threshold(problem, mode);
+    out->block_threads = 256;
+    // The drain grid of every mode is the resident maximum (KC_1 of Sec. IV.E):
+    // wave- and block-level drains run inside the parent groups, which are
+    // already resident, so no downgrade for concurrency is needed.
+    out->grid_blocks = resident_blocks > 0 ? resident_blocks : 1;
+    out->items_per_lane = 4;  // "const" of Sec. IV.E
+    out->driver = 0;
+    out->allow_fallback = 0;
+    out->buf_capacity = 0;
+    return WC_OK;
+}
+
+wc_status wc_ctx_create(int device, size_t pool_bytes, wc_ctx **out)
+{
+    if (!out) return fail(WC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return fail(WC_EINVAL, "no such HIP device");
+    }
+    wc_ctx *ctx = new (std::nothrow) wc_ctx();
+    if (!ctx) return fail(WC_ENOMEM, "host allocation failed");
+    ctx->device = device;
+    hipError_t e = hipSetDevice(device);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    ctx->num_cus = prop.multiProcessorCount;
+    ctx->max_threads_per_cu = prop.maxThreadsPerMultiProcessor;
+    ctx->lds_per_block = prop.sharedMemPerBlock;
+    wc_status st = pool_alloc(ctx, pool_bytes ? pool_bytes : (size_t(512) << 20));
+    if (st == WC_OK) {
+        e = hipHostMalloc(&ctx->host_ring, sizeof(int) * kHostRing, hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&ctx->host_ring_dev, ctx->host_ring, 0);
+        if (e == hipSuccess) e = hipMalloc(&ctx->dstats, sizeof(DevStats));
+        if (e == hipSuccess) e = hipEventCreate(&ctx->ev_start);
+        if (e == hipSuccess) e = hipEventCreate(&ctx->ev_stop);
+        if (e != hipSuccess) st = hip_fail(e, "context setup");
+    }
+    if (st != WC_OK) {
+        wc_ctx_destroy(ctx);
+        return st;
+    }
+    for (int i = 0; i < kHostRing; ++i) ctx->host_ring[i] = -1;
+    *out = ctx;
+    return WC_OK;
+}
+
+wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(WC_EINVAL, "NULL context");
+    WC_HIP(hipSetDevice(ctx->device));
+    WC_HIP(hipDeviceSynchronize());
+    recycle_records(ctx);
+    ctx->timing = enable ? 1 : 0;
+    return WC_OK;
+}
+
+wc_status wc_ctx_kernel_stats(wc_ctx *ctx, int32_t index, const char **name, int64_t *launches, double *total_ms,
+                              double *max_ms)
+{
+    if (!ctx || !name || !launches || !total_ms || !max_ms) return fail(WC_EINVAL, "NULL argument");
+    // distinct names in first-launch order
+    std::vector<const char *> names;
+    for (auto &r : ctx->records) {
+        bool seen = false;
+        for (auto *nm : names) seen = seen || !strcmp(nm, r.name);
+        if (!seen) names.push_back(r.name);
+    }
+    if (index < 0 || index >= (int32_t)names.size()) return fail(WC_EINVAL, "no kernel record with that index");
+    WC_HIP(hipSetDevice(ctx->device));
+    *name = names[index];
+    *launches = 0;
+    *total_ms = 0.0;
+    *max_ms = 0.0;
+    for (auto &r : ctx->records) {
+        if (strcmp(r.name, names[index])) continue;
+        WC_HIP(hipEventSynchronize(r.stop));
+        float ms = 0.f;
+        WC_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+        *launches += 1;
+        *total_ms += ms;
+        if (ms > *max_ms) *max_ms = ms;
+    }
+    return WC_OK;
+}
+
+wc_status wc_ctx_destroy(wc_ctx *ctx)
+{
+    if (!ctx) return WC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    recycle_records(ctx);
+    for (auto e : ctx->spare_events) (void)hipEventDestroy(e);
+    ctx->spare_events.clear();
+    if (ctx->pool) (void)hipFree(ctx->pool);
+    if (ctx->host_ring) (void)hipHostFree(ctx->host_ring);
+    if (ctx->dstats) (void)hipFree(ctx->dstats);
+    if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
+    if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
+    (void)hipGetLastError();
+    delete ctx;
+    return WC_OK;
+}
+
+}  // extern "C"

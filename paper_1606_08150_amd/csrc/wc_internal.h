@@ -1,0 +1,112 @@
+// Host-side internals of libwc: context, pre-allocated pool, error reporting,
+// device-published round counts, and the per-call stats block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wc.h"
+
+namespace wc {
+
+// Device counters accumulated by kernels when stats are requested.
+struct DevStats {
+    unsigned long long items_buffered;
+    unsigned long long dispatches;
+    unsigned long long edges_processed;
+    int overflowed;
+    int timed_out;
+    int rounds;
+    int pad;
+};
+
+// Ring of round counts published by kernels to pinned host memory, so the host
+// can stop relaunching rounds without a blocking copy per round.
+constexpr int kHostRing = 256;
+
+}  // namespace wc
+
+struct wc_kernel_record {
+    const char *name;
+    hipEvent_t start, stop;
+};
+
+struct wc_ctx {
+    int device = 0;
+    int num_cus = 0;
+    int max_threads_per_cu = 0;
+    size_t lds_per_block = 0;
+    char *pool = nullptr;      // device pool (the pre-allocated allocator of Sec. IV.E)
+    size_t pool_bytes = 0;
+    size_t pool_off = 0;
+    int *host_ring = nullptr;  // pinned, device-visible
+    int *host_ring_dev = nullptr;
+    wc::DevStats *dstats = nullptr;  // device
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    // optional per-kernel timing: events recorded around every launch
+    int timing = 0;
+    std::vector<wc_kernel_record> records;
+    std::vector<hipEvent_t> spare_events;
+};
+
+namespace wc {
+
+void set_error(const std::string &msg);
+wc_status fail(wc_status st, const std::string &msg);
+wc_status hip_fail(hipError_t e, const char *what);
+
+#define WC_HIP(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return wc::hip_fail(e_, #call); \
+    } while (0)
+
+// Pool carving: reset at the start of each call, then take aligned slices.
+// Grows the pool (after draining the device) if a call needs more than it has.
+wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream);
+void pool_reset(wc_ctx *ctx);
+template <typename T>
+T *pool_take(wc_ctx *ctx, size_t count)
+{
+    size_t off = (ctx->pool_off + 255) & ~size_t(255);
+    size_t bytes = count * sizeof(T);
+    ctx->pool_off = off + bytes;
+    return reinterpret_cast<T *>(ctx->pool + off);
+}
+inline size_t padded(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
+// Resolved configuration of one call.
+struct Config {
+    int threshold;
+    int block;
+    int grid;
+    int items_per_lane;
+    int driver;
+    bool fail_on_overflow;
+    long long buf_capacity;
+};
+
+int resident_blocks(wc_ctx *ctx, const void *kernel, int block);
+
+// Every kernel launch of the library goes through here so that per-kernel
+// timing (wc_ctx_set_timing) can bracket it with events on its stream.
+wc_status launch(wc_ctx *ctx, const char *name, const void *kernel, dim3 grid, dim3 block, void **args,
+                 hipStream_t stream);
+wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_tune *tune, int resident, Config *out);
+
+// Call bracket: validates the mode, clears stats, records the start event.
+wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats);
+// Records the stop event; fills `stats` (synchronizing) when non-NULL; reports
+// overflow / timeout flags.
+wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow);
+
+// Waits (bounded) until a kernel published the count of round `r` to the host ring.
+wc_status wait_round_count(wc_ctx *ctx, int r, int *count);
+void clear_round_slot(wc_ctx *ctx, int r);
+
+
+}  // namespace wc

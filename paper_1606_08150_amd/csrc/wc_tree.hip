@@ -1,0 +1,689 @@
+// Tree descendants / tree heights with workload consolidation (parallel
+// recursion, Fig. 1(c)).
+//
+// The recursive kernel of Fig. 1(c) gives one thread per child c of a node:
+// if c has children it launches itself on c (the recursive call), otherwise it
+// does the leaf work; afterwards the post-work folds c's result into its
+// parent (descendants: + (1 + desc[c]); heights: max with 1 + height[c]).
+// Consolidation buffers the recursive calls, i.e. the nodes with children, and
+// one consolidated child processes all buffered nodes' children.
+//
+//   grid  - level-synchronous: the global buffer of level l holds chunks of
+//           the children ranges of every node found in level l-1; a grid-wide
+//           barrier (kernel boundary or the persistent grid's counter barrier)
+//           separates levels.  The post-work is consolidated too (Sec. IV.C,
+//           grid-level post-work): after the last level, one pass per level from
+//           the deepest up folds every chunk into its node with one atomic.
+//   flat  - the same level structure without consolidation: one thread per
+//           node of the level handles all of its children serially, and one
+//           thread per node folds them back.
+//   wave / block - no grid-wide barrier at all.  A wave (block) inserts the
+//           nodes with children it finds into its own LDS buffer; a full (or
+//           final) buffer becomes one consolidated dispatch: a packet in a
+//           device-wide queue that any wave (block) of the persistent grid
+//           picks up.  The post-work runs as soon as a node's last child is
+//           done: per-node pending-children counters; the thread that
+//           completes a node folds it into its parent and climbs on while it
+//           keeps completing ancestors.
+// Integer folds are associative and commutative, so every mode and schedule
+// gives identical results.
+#include <algorithm>
+#include <cstring>
+
+#include "wc_block.h"
+#include "wc_device.h"
+#include "wc_internal.h"
+
+namespace wc {
+namespace {
+
+enum { OP_DESC = 0, OP_HEIGHT = 1 };
+
+struct TreeArgs {
+    const int *parent;
+    const int *child_ptr;
+    const int *child;
+    int *out;
+    int n;
+    int chunk;
+    // level-synchronous modes
+    int *lvl_start;  // [max_levels + 2]
+    int *lvl_count;  // [max_levels + 2]
+    int4 *items;     // grid: (node, begin, end, 0) chunks; flat: .x = node
+    long long item_cap;
+    // packet-queue modes
+    int *nl;             // node list the packets point into [n]
+    int *nl_tail;
+    long long *pq;       // packets: (start << 32) | count; -1 = not yet written
+    int *pq_head;
+    int *pq_tail;
+    int *outstanding;
+    int *pending;        // per-node children not yet finished
+    int work_cap;        // flush a buffer once its nodes carry this many children
+    int *host_ring;
+    DevStats *stats;
+    int want_stats;
+    GridBarrier *bar;
+    int bar_blocks;
+};
+
+__device__ __forceinline__ int fanout(const TreeArgs &a, int v) { return a.child_ptr[v + 1] - a.child_ptr[v]; }
+
+template <int OP>
+__device__ __forceinline__ int fold(int acc, int v)
+{
+    return OP == OP_DESC ? acc + 1 + v : max(acc, 1 + v);
+}
+
+template <int OP>
+__device__ __forceinline__ void atomic_fold(int *p, int v)
+{
+    if (OP == OP_DESC) atomic_add_dev(p, v);
+    else atomic_max_dev(p, v);
+}
+
+// ---------------------------------------------------------------- level-synchronous (flat, grid)
+
+__global__ void tree_init_levels(TreeArgs a)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.out[0] = 0;
+        int f = fanout(a, 0);
+        a.lvl_start[0] = 0;
+        a.lvl_count[1] = 0;
+        if (f == 0) {
+            a.lvl_count[0] = 0;
+        } else {
+            // level 0 buffers the root: the host's launch on the root's children
+            int nch = (f + a.chunk - 1) / a.chunk;
+            for (int c = 0; c < nch; ++c) {
+                int cb = a.child_ptr[0] + c * a.chunk;
+                a.items[c] = make_int4(0, cb, min(cb + a.chunk, a.child_ptr[1]), 0);
+            }
+            a.lvl_count[0] = nch;
+        }
+        a.bar->count = a.bar_blocks;
+        a.bar->generation = 0;
+    }
+}
+
+__global__ void tree_init_levels_flat(TreeArgs a)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.out[0] = 0;
+        a.lvl_start[0] = 0;
+        a.lvl_count[0] = fanout(a, 0) > 0 ? 1 : 0;
+        a.lvl_count[1] = 0;
+        a.items[0] = make_int4(0, 0, 0, 0);
+        a.bar->count = a.bar_blocks;
+        a.bar->generation = 0;
+    }
+}
+
+// Top-down step of level l: children of the level's buffered nodes.  Internal
+// children are inserted into level l+1's buffer, leaves get the leaf work.
+template <int MODE, int BLOCK>
+__device__ void level_down(const TreeArgs &a, int l, int start, int count)
+{
+    const int out_base = start + count;
+    int *cnt_next = &a.lvl_count[l + 1];
+    if constexpr (MODE == WC_GRID) {
+        const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
+        const int nw = gridDim.x * (BLOCK / kWave);
+        for (int it = gw; it < count; it += nw) {
+            int4 d = a.items[start + it];
+            const int cb = __builtin_amdgcn_readfirstlane(d.y), ce = __builtin_amdgcn_readfirstlane(d.z);
+            if (a.want_stats && lane_id() == 0) {
+                atomic_add_dev(&a.stats->edges_processed, (unsigned long long)(ce - cb));
+            }
+            for (int b = cb; b < ce; b += kWave) {
+                const int e = b + lane_id();
+                int c = -1, f = 0;
+                if (e < ce) {
+                    c = a.child[e];
+                    f = fanout(a, c);
+                    a.out[c] = 0;  // leaf work, or the identity the folds start from
+                }
+                const int nch = f > 0 ? (f + a.chunk - 1) / a.chunk : 0;
+                const int slot = wave_reserve_n(nch, cnt_next);
+                if (a.want_stats) {
+                    uint64_t m = __ballot(f > 0);
+                    if (lane_id() == 0 && m) atomic_add_dev(&a.stats->items_buffered, (unsigned long long)__builtin_popcountll(m));
+                }
+                if (nch > 0) {
+                    const int c0 = a.child_ptr[c];
+                    for (int k = 0; k < nch; ++k) {
+                        int kb = c0 + k * a.chunk;
+                        a.items[out_base + slot + k] = make_int4(c, kb, min(kb + a.chunk, c0 + f), 0);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+            const int p = a.items[start + i].x;
+            const int cb = a.child_ptr[p], ce = a.child_ptr[p + 1];
+            if (a.want_stats) atomic_add_dev(&a.stats->edges_processed, (unsigned long long)(ce - cb));
+            for (int e = cb; e < ce; ++e) {
+                const int c = a.child[e];
+                const bool internal = fanout(a, c) > 0;
+                a.out[c] = 0;
+                const int slot = wave_reserve(internal, cnt_next);
+                if (internal) a.items[out_base + slot] = make_int4(c, 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Bottom-up post-work of level l (all deeper levels are final).
+template <int MODE, int OP, int BLOCK>
+__device__ void level_up(const TreeArgs &a, int start, int count)
+{
+    if constexpr (MODE == WC_GRID) {
+        const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
+        const int nw = gridDim.x * (BLOCK / kWave);
+        for (int it = gw; it < count; it += nw) {
+            int4 d = a.items[start + it];
+            const int p = __builtin_amdgcn_readfirstlane(d.x);
+            const int cb = __builtin_amdgcn_readfirstlane(d.y), ce = __builtin_amdgcn_readfirstlane(d.z);
+            int acc = 0;
+            for (int e = cb + lane_id(); e < ce; e += kWave) acc = fold<OP>(acc, a.out[a.child[e]]);
+            acc = OP == OP_DESC ? wave_sum_i(acc) : wave_max_i(acc);
+            if (lane_id() == 0) atomic_fold<OP>(&a.out[p], acc);
+        }
+    } else {
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
+            const int p = a.items[start + i].x;
+            int acc = 0;
+            for (int e = a.child_ptr[p]; e < a.child_ptr[p + 1]; ++e) acc = fold<OP>(acc, a.out[a.child[e]]);
+            a.out[p] = acc;
+        }
+    }
+}
+
+template <int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tree_down(TreeArgs a, int l)
+{
+    const int start = a.lvl_start[l], count = a.lvl_count[l];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.lvl_start[l + 1] = start + count;
+        a.lvl_count[l + 2] = 0;
+        store_system(&a.host_ring[l % kHostRing], count);
+        if (a.want_stats && MODE == WC_GRID && count > 0) atomic_add_dev(&a.stats->dispatches, 1ull);
+    }
+    if (count == 0) return;
+    level_down<MODE, BLOCK>(a, l, start, count);
+}
+
+template <int MODE, int OP, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tree_up(TreeArgs a, int l)
+{
+    level_up<MODE, OP, BLOCK>(a, a.lvl_start[l], a.lvl_count[l]);
+}
+
+// Persistent driver of the level-synchronous modes: all levels, both
+// directions, one co-resident launch, grid barrier between levels.
+template <int MODE, int OP, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tree_levels_persistent(TreeArgs a, int max_levels)
+{
+    const int nb = gridDim.x;
+    int l = 0;
+    for (; l < max_levels; ++l) {
+        const int start = atomic_load_dev(&a.lvl_start[l]), count = atomic_load_dev(&a.lvl_count[l]);
+        if (count == 0) break;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.lvl_start[l + 1] = start + count;
+            a.lvl_count[l + 2] = 0;
+            if (a.want_stats && MODE == WC_GRID) atomic_add_dev(&a.stats->dispatches, 1ull);
+        }
+        level_down<MODE, BLOCK>(a, l, start, count);
+        if (!grid_barrier(a.bar, nb)) {
+            a.stats->timed_out = 1;
+            return;
+        }
+    }
+    const int levels = l;
+    for (l = levels - 1; l >= 0; --l) {
+        level_up<MODE, OP, BLOCK>(a, atomic_load_dev(&a.lvl_start[l]), atomic_load_dev(&a.lvl_count[l]));
+        if (!grid_barrier(a.bar, nb)) {
+            a.stats->timed_out = 1;
+            return;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.stats->rounds = levels;
+}
+
+// ---------------------------------------------------------------- packet queue (wave, block)
+
+// Post-work of a finished node v: fold it into its parent; whoever finishes the
+// parent's last child carries on upward.
+template <int OP>
+__device__ void complete_upward(const TreeArgs &a, int v, int val)
+{
+    for (;;) {
+        const int p = a.parent[v];
+        if (p < 0) return;
+        atomic_fold<OP>(&a.out[p], 1 + val);
+        int left = __hip_atomic_fetch_add(&a.pending[p], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) - 1;
+        if (left != 0) return;
+        v = p;
+        val = __hip_atomic_load(&a.out[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void tree_init_queue(TreeArgs a, long long pq_cap)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < pq_cap;
+         i += (long long)gridDim.x * blockDim.x)
+        a.pq[i] = -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.out[0] = 0;
+        const int f = fanout(a, 0);
+        *a.pq_head = 0;
+        if (f == 0) {
+            *a.nl_tail = 0;
+            *a.pq_tail = 0;
+            *a.outstanding = 0;
+        } else {
+            a.pending[0] = f;
+            a.nl[0] = 0;
+            *a.nl_tail = 1;
+            *a.pq_tail = 1;
+            *a.outstanding = 1;
+        }
+    }
+}
+
+__global__ void tree_publish_root(TreeArgs a)
+{
+    if (threadIdx.x == 0 && fanout(a, 0) > 0)
+        __hip_atomic_store(&a.pq[0], (0LL << 32) | 1LL, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Group = one wave (G = 64) or one block (G = BLOCK).  Per group LDS state:
+// the packet being processed and the buffer being filled.
+template <int G>
+struct QueueLds {
+    int pk_node[G];
+    int pk_beg[G];
+    int pk_pre[G + 1];
+    int buf[2 * G];
+    int buf_cnt;
+    int buf_work;
+    int pk_start;
+    int pk_count;
+    int flag;
+    int pad;
+    int scan_tmp[2 * (G / kWave) + 2];
+};
+
+// Group-wide barrier: a wave needs none (lockstep); a block uses __syncthreads.
+template <int G>
+__device__ __forceinline__ void gsync()
+{
+    if (G > kWave) {
+        __syncthreads();
+    } else {
+        // one wave runs in lockstep; the fence only keeps the compiler from
+        // moving LDS accesses across this point
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <int G>
+__device__ __forceinline__ int gtid() { return G > kWave ? (int)threadIdx.x : lane_id(); }
+
+// Flush the group's buffer as packets of at most G nodes (one consolidated
+// dispatch each).
+template <int G>
+__device__ void flush_buffer(const TreeArgs &a, QueueLds<G> &s)
+{
+    const int cnt = s.buf_cnt;
+    if (cnt == 0) return;
+    const int t = gtid<G>();
+    for (int off = 0; off < cnt; off += G) {
+        const int k = min(G, cnt - off);
+        if (t == 0) s.pk_start = atomic_add_dev(a.nl_tail, k);
+        gsync<G>();
+        const int base = s.pk_start;
+        if (t < k) a.nl[base + t] = s.buf[off + t];
+        gsync<G>();
+        if (t == 0) {
+            // the nodes (and their pending counts / initial outputs) become
+            // visible before the packet does
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomic_add_dev(a.outstanding, 1);
+            const int slot = atomic_add_dev(a.pq_tail, 1);
+            __hip_atomic_store(&a.pq[slot], ((long long)base << 32) | (long long)k, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            if (a.want_stats) atomic_add_dev(&a.stats->items_buffered, (unsigned long long)k);
+        }
+        gsync<G>();
+    }
+    if (t == 0) {
+        s.buf_cnt = 0;
+        s.buf_work = 0;
+    }
+    gsync<G>();
+}
+
+template <int OP, int G, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
+{
+    constexpr int GROUPS = BLOCK / G;
+    __shared__ QueueLds<G> lds[GROUPS];
+    const int gid = G > kWave ? 0 : (int)threadIdx.x / kWave;
+    QueueLds<G> &s = lds[gid];
+    const int t = gtid<G>();
+    if (t == 0) {
+        s.buf_cnt = 0;
+        s.buf_work = 0;
+    }
+    gsync<G>();
+    for (;;) {
+        // ---- fetch a packet (group leader), or learn that all work is done
+        if (t == 0) {
+            int got = -2;  // -2: keep waiting, -1: done, >= 0: packet slot
+            const unsigned long long deadline = wait_deadline();
+            for (;;) {
+                int h = atomic_load_dev(a.pq_head);
+                int tl = atomic_load_dev(a.pq_tail);
+                if (h < tl) {
+                    if (__hip_atomic_compare_exchange_strong(a.pq_head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        got = h;
+                        break;
+                    }
+                    continue;
+                }
+                if (atomic_load_dev(a.outstanding) == 0) {
+                    got = -1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                if (past(deadline)) {
+                    a.stats->timed_out = 1;
+                    got = -1;
+                    break;
+                }
+            }
+            long long pk = -1;
+            if (got >= 0) {
+                while ((pk = __hip_atomic_load(&a.pq[got], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) < 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (past(deadline)) {
+                        a.stats->timed_out = 1;
+                        break;
+                    }
+                }
+            }
+            s.flag = got;
+            s.pk_start = pk >= 0 ? (int)(pk >> 32) : 0;
+            s.pk_count = pk >= 0 ? (int)(pk & 0xffffffff) : 0;
+            if (got >= 0 && pk < 0) s.flag = -1;
+            if (a.want_stats && s.flag >= 0) atomic_add_dev(&a.stats->dispatches, 1ull);
+        }
+        gsync<G>();
+        if (s.flag < 0) break;
+        // ---- the consolidated child: all buffered nodes' children, flattened
+        const int pcount = s.pk_count;
+        int node = 0, f = 0, beg = 0;
+        if (t < pcount) {
+            node = a.nl[s.pk_start + t];
+            beg = a.child_ptr[node];
+            f = a.child_ptr[node + 1] - beg;
+        }
+        int pre, dummy, total, dummy_total;
+        if constexpr (G > kWave) {
+            block_scan2<G>(f, 0, s.scan_tmp, pre, dummy, total, dummy_total);
+        } else {
+            int incl = wave_incl_scan(f);
+            pre = incl - f;
+            total = readlane(incl, kWave - 1);
+        }
+        if (t < pcount) {
+            s.pk_node[t] = node;
+            s.pk_beg[t] = beg;
+            s.pk_pre[t] = pre;
+        }
+        if (t == 0) s.pk_pre[pcount] = total;
+        gsync<G>();
+        if (a.want_stats && t == 0) atomic_add_dev(&a.stats->edges_processed, (unsigned long long)total);
+        int k = 0;
+        for (int jb = 0; jb < total; jb += G) {
+            const int j = jb + t;
+            int c = -1, cf = 0, p = -1;
+            if (j < total) {
+                while (k + 1 < pcount && s.pk_pre[k + 1] <= j) ++k;
+                p = s.pk_node[k];
+                c = a.child[s.pk_beg[k] + (j - s.pk_pre[k])];
+                cf = fanout(a, c);
+                a.out[c] = 0;  // leaf work, or the identity the folds start from
+                if (cf > 0) a.pending[c] = cf;
+            }
+            // insert the recursive calls into the group's buffer
+            if constexpr (G > kWave) {
+                int pos, dummy2, add, work;
+                block_scan2<G>(cf > 0 ? 1 : 0, cf, s.scan_tmp, pos, dummy2, add, work);
+                if (cf > 0) s.buf[s.buf_cnt + pos] = c;
+                gsync<G>();
+                if (t == 0) {
+                    s.buf_cnt += add;
+                    s.buf_work += work;
+                }
+            } else {
+                uint64_t m = __ballot(cf > 0);
+                int work = wave_sum_i(cf);
+                if (cf > 0) s.buf[s.buf_cnt + rank_in(m)] = c;
+                gsync<G>();
+                if (t == 0) {
+                    s.buf_cnt += __builtin_popcountll(m);
+                    s.buf_work += work;
+                }
+            }
+            // leaves: their post-work right away
+            if (c >= 0 && cf == 0) {
+                (void)p;
+                complete_upward<OP>(a, c, 0);
+            }
+            gsync<G>();
+            if (s.buf_cnt >= G || s.buf_work >= a.work_cap) flush_buffer<G>(a, s);
+        }
+        flush_buffer<G>(a, s);
+        // this dispatch is finished (its own follow-up packets are already counted)
+        if (t == 0) __hip_atomic_fetch_add(a.outstanding, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        gsync<G>();
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+template <int OP, int BLOCK>
+struct TreeKernels {
+    const void *down, *up, *persistent, *queue;
+};
+
+template <int OP, int BLOCK>
+TreeKernels<OP, BLOCK> kernels_for(wc_mode mode)
+{
+    TreeKernels<OP, BLOCK> k{nullptr, nullptr, nullptr, nullptr};
+    if (mode == WC_GRID) {
+        k.down = reinterpret_cast<const void *>(&tree_down<WC_GRID, BLOCK>);
+        k.up = reinterpret_cast<const void *>(&tree_up<WC_GRID, OP, BLOCK>);
+        k.persistent = reinterpret_cast<const void *>(&tree_levels_persistent<WC_GRID, OP, BLOCK>);
+    } else if (mode == WC_FLAT) {
+        k.down = reinterpret_cast<const void *>(&tree_down<WC_FLAT, BLOCK>);
+        k.up = reinterpret_cast<const void *>(&tree_up<WC_FLAT, OP, BLOCK>);
+        k.persistent = reinterpret_cast<const void *>(&tree_levels_persistent<WC_FLAT, OP, BLOCK>);
+    } else if (mode == WC_WAVE) {
+        k.queue = reinterpret_cast<const void *>(&tree_queue<OP, kWave, BLOCK>);
+    } else {
+        k.queue = reinterpret_cast<const void *>(&tree_queue<OP, BLOCK, BLOCK>);
+    }
+    return k;
+}
+
+template <int OP, int BLOCK>
+wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const Config &cfg, hipStream_t stream,
+                   wc_stats *stats)
+{
+    TreeKernels<OP, BLOCK> ks = kernels_for<OP, BLOCK>(mode);
+    const void *main_kernel = ks.queue ? ks.queue : ks.persistent;
+    const int resident = resident_blocks(ctx, main_kernel, BLOCK);
+    const int grid = std::max(1, std::min(cfg.grid, resident));
+    const long long n = t->n;
+    const int chunk = kWave * cfg.items_per_lane;
+    TreeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.parent = t->parent;
+    a.child_ptr = t->child_ptr;
+    a.child = t->child;
+    a.out = out;
+    a.n = (int)n;
+    a.chunk = chunk;
+    a.host_ring = ctx->host_ring_dev;
+    a.stats = ctx->dstats;
+    a.want_stats = stats != nullptr;
+    a.bar_blocks = grid;
+    a.work_cap = BLOCK * cfg.items_per_lane;
+    const bool queue_mode = mode == WC_WAVE || mode == WC_BLOCK;
+    if (queue_mode) {
+        a.work_cap = (mode == WC_WAVE ? kWave : BLOCK) * cfg.items_per_lane;
+        long long pq_cap = n;
+        size_t need = padded(n * 4) * 2 + padded(pq_cap * 8) + 4 * padded(4) + padded(sizeof(GridBarrier));
+        wc_status st = pool_reserve(ctx, need, stream);
+        if (st != WC_OK) return st;
+        a.nl = pool_take<int>(ctx, n);
+        a.pending = pool_take<int>(ctx, n);
+        a.pq = pool_take<long long>(ctx, pq_cap);
+        a.nl_tail = pool_take<int>(ctx, 1);
+        a.pq_head = pool_take<int>(ctx, 1);
+        a.pq_tail = pool_take<int>(ctx, 1);
+        a.outstanding = pool_take<int>(ctx, 1);
+        a.bar = pool_take<GridBarrier>(ctx, 1);
+        st = begin_call(ctx, stream, stats);
+        if (st != WC_OK) return st;
+        int ig = (int)std::min<long long>((pq_cap + 255) / 256, 4096);
+        void *iargs[] = {&a, &pq_cap};
+        st = launch(ctx, "tree_init_queue", reinterpret_cast<const void *>(&tree_init_queue), dim3(ig), dim3(256),
+                    iargs, stream);
+        void *args[] = {&a};
+        if (st == WC_OK)
+            st = launch(ctx, "tree_publish_root", reinterpret_cast<const void *>(&tree_publish_root), dim3(1),
+                        dim3(64), args, stream);
+        if (st == WC_OK)
+            st = launch(ctx, mode == WC_WAVE ? "tree_queue_wave" : "tree_queue_block", ks.queue, dim3(grid),
+                        dim3(BLOCK), args, stream);
+        if (st != WC_OK) return st;
+        return end_call(ctx, stream, stats, 0, cfg.fail_on_overflow);
+    }
+    // level-synchronous: levels <= n; chunks over all levels <= n + (n-1)/chunk + 1
+    // (the relaunch driver may run up to `window` empty levels past the last one)
+    const long long max_levels = n + 1;
+    const long long lvl_len = max_levels + 16;
+    long long cap = mode == WC_GRID ? n + n / chunk + 2 : n + 1;
+    size_t need = 2 * padded(lvl_len * 4) + padded(cap * 16) + padded(sizeof(GridBarrier));
+    wc_status st = pool_reserve(ctx, need, stream);
+    if (st != WC_OK) return st;
+    a.lvl_start = pool_take<int>(ctx, lvl_len);
+    a.lvl_count = pool_take<int>(ctx, lvl_len);
+    a.items = pool_take<int4>(ctx, cap);
+    a.item_cap = cap;
+    a.bar = pool_take<GridBarrier>(ctx, 1);
+    st = begin_call(ctx, stream, stats);
+    if (st != WC_OK) return st;
+    {
+        void *args[] = {&a};
+        st = launch(ctx, "tree_init_levels",
+                    mode == WC_GRID ? reinterpret_cast<const void *>(&tree_init_levels)
+                                    : reinterpret_cast<const void *>(&tree_init_levels_flat),
+                    dim3(1), dim3(64), args, stream);
+        if (st != WC_OK) return st;
+    }
+    if (cfg.driver == 1) {
+        return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
+        int ml = (int)std::min<long long>(max_levels, 0x7fffffff);
+        void *args[] = {&a, &ml};
+        WC_HIP(hipLaunchCooperativeKernel(ks.persistent, dim3(grid), dim3(BLOCK), args, 0, stream));
+        st = end_call(ctx, stream, stats, -1, cfg.fail_on_overflow);
+        if (stats && st == WC_OK) {
+            int r = 0;
+            WC_HIP(hipMemcpy(&r, &ctx->dstats->rounds, sizeof(int), hipMemcpyDeviceToHost));
+            stats->rounds = r;
+        }
+        return st;
+    }
+    const int window = 4;
+    int launched = 0, levels = 0;
+    for (;;) {
+        while (launched < levels + window) {
+            clear_round_slot(ctx, launched);
+            void *args[] = {&a, &launched};
+            st = launch(ctx, mode == WC_GRID ? "tree_down_grid" : "tree_down_flat", ks.down, dim3(grid), dim3(BLOCK),
+                        args, stream);
+            if (st != WC_OK) return st;
+            ++launched;
+        }
+        int c = 0;
+        st = wait_round_count(ctx, levels, &c);
+        if (st != WC_OK) return st;
+        if (c == 0) break;
+        ++levels;
+        if (levels > n + 1) return fail(WC_ETIMEOUT, "tree: more levels than nodes");
+    }
+    for (int l = levels - 1; l >= 0; --l) {
+        void *args[] = {&a, &l};
+        st = launch(ctx, mode == WC_GRID ? "tree_up_grid" : "tree_up_flat", ks.up, dim3(grid), dim3(BLOCK), args,
+                    stream);
+        if (st != WC_OK) return st;
+    }
+    return end_call(ctx, stream, stats, levels, cfg.fail_on_overflow);
+}
+
+template <int OP>
+wc_status run_tree_block(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const Config &cfg,
+                         hipStream_t stream, wc_stats *stats)
+{
+    switch (cfg.block) {
+    case 64: return run_tree<OP, 64>(ctx, t, out, mode, cfg, stream, stats);
+    case 128: return run_tree<OP, 128>(ctx, t, out, mode, cfg, stream, stats);
+    case 512: return run_tree<OP, 512>(ctx, t, out, mode, cfg, stream, stats);
+    case 1024: return run_tree<OP, 1024>(ctx, t, out, mode, cfg, stream, stats);
+    default: return run_tree<OP, 256>(ctx, t, out, mode, cfg, stream, stats);
+    }
+}
+
+wc_status tree_entry(int op, wc_ctx *ctx, const wc_tree *t, int32_t *out, wc_mode mode, const wc_tune *tune,
+                     hipStream_t stream, wc_stats *stats)
+{
+    if (!ctx || !t) return fail(WC_EINVAL, "tree: NULL context or tree");
+    if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "tree: bad mode");
+    if (t->n < 1) return fail(WC_EINVAL, "tree: a tree has at least the root");
+    if (!t->parent || !t->child_ptr || !out || (t->n > 1 && !t->child)) return fail(WC_EINVAL, "tree: NULL array");
+    WC_HIP(hipSetDevice(ctx->device));
+    Config cfg;
+    wc_status st = resolve_tune(ctx, "tree", mode, tune, ctx->num_cus * 8, &cfg);
+    if (st != WC_OK) return st;
+    if (tune && tune->grid_blocks > 0) cfg.grid = tune->grid_blocks;
+    else cfg.grid = 1 << 30;  // clamp to the resident count of the chosen kernel
+    return op == OP_DESC ? run_tree_block<OP_DESC>(ctx, t, out, mode, cfg, stream, stats)
+                         : run_tree_block<OP_HEIGHT>(ctx, t, out, mode, cfg, stream, stats);
+}
+
+}  // namespace
+}  // namespace wc
+
+using namespace wc;
+
+extern "C" wc_status wc_tree_descendants(wc_ctx *ctx, const wc_tree *t, int32_t *desc, wc_mode mode,
+                                         const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+{
+    return tree_entry(OP_DESC, ctx, t, desc, mode, tune, stream, stats);
+}
+
+extern "C" wc_status wc_tree_height(wc_ctx *ctx, const wc_tree *t, int32_t *height, wc_mode mode,
+                                    const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+{
+    return tree_entry(OP_HEIGHT, ctx, t, height, mode, tune, stream, stats);
+}

@@ -1,0 +1,267 @@
+"""ctypes binding of libwc.so (include/wc.h).  Argument marshalling only: every
+step of every problem runs in the library's HIP kernels.  PyTorch provides the
+device memory (tensors) and the stream.
+
+The binding refuses to run without the built library or without a GPU; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwc.so")
+
+FLAT, WAVE, BLOCK, GRID = 0, 1, 2, 3
+MODES = {"flat": FLAT, "wave": WAVE, "block": BLOCK, "grid": GRID}
+STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: "WC_ETIMEOUT", -5: "WC_EHIP"}
+
+# C-ABI symbols declared in include/wc.h
+EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_spmv", "wc_tree_descendants", "wc_tree_height",
+           "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_last_error", "wc_version", "wc_per_buffer_size",
+           "wc_kc_config", "wc_default_tune")
+
+
+class WcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CCsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p)]
+
+
+class CTree(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("parent", ctypes.c_void_p), ("child_ptr", ctypes.c_void_p),
+                ("child", ctypes.c_void_p)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("threshold", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("items_per_lane", ctypes.c_int32), ("driver", ctypes.c_int32), ("allow_fallback", ctypes.c_int32),
+                ("buf_capacity", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("overflowed", ctypes.c_int32), ("items_buffered", ctypes.c_int64),
+                ("dispatches", ctypes.c_int64), ("edges_processed", ctypes.c_int64), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library():
+    """Load libwc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1606_08150_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    vp = c.c_void_p
+    lib.wc_ctx_create.restype = c.c_int
+    lib.wc_ctx_create.argtypes = [c.c_int, c.c_size_t, c.POINTER(vp)]
+    lib.wc_ctx_destroy.restype = c.c_int
+    lib.wc_ctx_destroy.argtypes = [vp]
+    lib.wc_sssp.restype = c.c_int
+    lib.wc_sssp.argtypes = [vp, c.POINTER(CCsr), vp, c.c_int32, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_spmv.restype = c.c_int
+    lib.wc_spmv.argtypes = [vp, c.POINTER(CCsr), vp, vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    for name in ("wc_tree_descendants", "wc_tree_height"):
+        fn = getattr(lib, name)
+        fn.restype = c.c_int
+        fn.argtypes = [vp, c.POINTER(CTree), vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_ctx_set_timing.restype = c.c_int
+    lib.wc_ctx_set_timing.argtypes = [vp, c.c_int]
+    lib.wc_ctx_kernel_stats.restype = c.c_int
+    lib.wc_ctx_kernel_stats.argtypes = [vp, c.c_int32, c.POINTER(c.c_char_p), c.POINTER(c.c_int64),
+                                        c.POINTER(c.c_double), c.POINTER(c.c_double)]
+    lib.wc_last_error.restype = c.c_char_p
+    lib.wc_last_error.argtypes = []
+    lib.wc_version.restype = c.c_char_p
+    lib.wc_per_buffer_size.restype = c.c_int64
+    lib.wc_per_buffer_size.argtypes = [c.c_int64, c.c_int64, c.c_int64]
+    lib.wc_kc_config.restype = None
+    lib.wc_kc_config.argtypes = [c.c_int64, c.c_int64, c.c_int64, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
+    lib.wc_default_tune.restype = c.c_int
+    lib.wc_default_tune.argtypes = [c.c_char_p, c.c_int, c.c_int32, c.POINTER(Tune)]
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise WcError(status, load_library().wc_last_error().decode())
+
+
+def _mode(mode) -> int:
+    if isinstance(mode, str):
+        return MODES[mode]
+    return int(mode)
+
+
+def make_tune(**kw) -> Tune:
+    t = Tune()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
+# ---- host-side planning helpers (no GPU needed) ----------------------------------------------
+
+def per_buffer_size(total_thread: int, total_buff_var: int, items_per_thread: int = 4) -> int:
+    return int(load_library().wc_per_buffer_size(total_thread, total_buff_var, items_per_thread))
+
+
+def kc_config(blocks: int, threads: int, x: int):
+    b, t = ctypes.c_int64(), ctypes.c_int64()
+    load_library().wc_kc_config(blocks, threads, x, ctypes.byref(b), ctypes.byref(t))
+    return b.value, t.value
+
+
+def default_tune(problem: str, mode, resident_blocks: int) -> dict:
+    t = Tune()
+    _check(load_library().wc_default_tune(problem.encode(), _mode(mode), resident_blocks, ctypes.byref(t)))
+    return t.as_dict()
+
+
+# ---- device data --------------------------------------------------------------------------------
+
+@dataclass
+class DeviceCSR:
+    n: int
+    row_ptr: torch.Tensor  # int32[n+1]
+    col: torch.Tensor      # int32[m]
+
+    @property
+    def m(self) -> int:
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_host(row_ptr, col, device="cuda"):
+        rp = torch.as_tensor(row_ptr, dtype=torch.int32).to(device)
+        cl = torch.as_tensor(col, dtype=torch.int32).to(device)
+        return DeviceCSR(int(rp.numel()) - 1, rp, cl)
+
+    def c(self) -> CCsr:
+        return CCsr(self.n, self.m, self.row_ptr.data_ptr(), self.col.data_ptr() if self.m else None)
+
+
+@dataclass
+class DeviceTree:
+    n: int
+    parent: torch.Tensor
+    child_ptr: torch.Tensor
+    child: torch.Tensor
+
+    @staticmethod
+    def from_host(parent, child_ptr, child, device="cuda"):
+        p = torch.as_tensor(parent, dtype=torch.int32).to(device)
+        cp = torch.as_tensor(child_ptr, dtype=torch.int32).to(device)
+        ch = torch.as_tensor(child, dtype=torch.int32).to(device)
+        return DeviceTree(int(p.numel()), p, cp, ch)
+
+    def c(self) -> CTree:
+        return CTree(self.n, self.parent.data_ptr(), self.child_ptr.data_ptr(),
+                     self.child.data_ptr() if self.child.numel() else None)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """A libwc context: one device pool (the pre-allocated allocator) per device."""
+
+    def __init__(self, device: int = 0, pool_bytes: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libwc needs a HIP GPU; none is visible")
+        lib = load_library()
+        torch.cuda.set_device(device)
+        self.device = device
+        self._ptr = ctypes.c_void_p()
+        _check(lib.wc_ctx_create(device, pool_bytes, ctypes.byref(self._ptr)))
+
+    def close(self):
+        if self._ptr:
+            load_library().wc_ctx_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- per-kernel timing --
+    def set_timing(self, enable: bool):
+        _check(load_library().wc_ctx_set_timing(self._ptr, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """{kernel name: (launches, total_ms, max_ms)} for the launches recorded
+        since timing was enabled."""
+        lib = load_library()
+        out = {}
+        i = 0
+        while True:
+            name, n = ctypes.c_char_p(), ctypes.c_int64()
+            tot, mx = ctypes.c_double(), ctypes.c_double()
+            st = lib.wc_ctx_kernel_stats(self._ptr, i, ctypes.byref(name), ctypes.byref(n), ctypes.byref(tot),
+                                         ctypes.byref(mx))
+            if st != 0:
+                break
+            out[name.value.decode()] = (n.value, tot.value, mx.value)
+            i += 1
+        return out
+
+    # -- problems --
+    def sssp(self, g: DeviceCSR, w: torch.Tensor, src: int, mode="grid", tune: Tune | None = None,
+             out: torch.Tensor | None = None, stream=None, stats: bool = False):
+        dist = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+        st = Stats() if stats else None
+        cg = g.c()
+        _check(load_library().wc_sssp(self._ptr, ctypes.byref(cg), w.data_ptr() if g.m else None, src,
+                                      dist.data_ptr(), _mode(mode), ctypes.byref(tune) if tune else None,
+                                      _stream_ptr(stream), ctypes.byref(st) if st else None))
+        return (dist, st.as_dict()) if stats else dist
+
+    def spmv(self, a: DeviceCSR, val: torch.Tensor, x: torch.Tensor, mode="grid", tune: Tune | None = None,
+             out: torch.Tensor | None = None, stream=None, stats: bool = False):
+        y = out if out is not None else torch.empty(a.n, dtype=torch.float32, device=a.row_ptr.device)
+        st = Stats() if stats else None
+        ca = a.c()
+        _check(load_library().wc_spmv(self._ptr, ctypes.byref(ca), val.data_ptr() if a.m else None, x.data_ptr(),
+                                      y.data_ptr(), _mode(mode), ctypes.byref(tune) if tune else None,
+                                      _stream_ptr(stream), ctypes.byref(st) if st else None))
+        return (y, st.as_dict()) if stats else y
+
+    def _tree(self, fn, t: DeviceTree, mode, tune, out, stream, stats):
+        res = out if out is not None else torch.empty(t.n, dtype=torch.int32, device=t.parent.device)
+        st = Stats() if stats else None
+        ct = t.c()
+        _check(fn(self._ptr, ctypes.byref(ct), res.data_ptr(), _mode(mode), ctypes.byref(tune) if tune else None,
+                  _stream_ptr(stream), ctypes.byref(st) if st else None))
+        return (res, st.as_dict()) if stats else res
+
+    def tree_descendants(self, t: DeviceTree, mode="grid", tune: Tune | None = None, out=None, stream=None,
+                         stats: bool = False):
+        return self._tree(load_library().wc_tree_descendants, t, mode, tune, out, stream, stats)
+
+    def tree_height(self, t: DeviceTree, mode="grid", tune: Tune | None = None, out=None, stream=None,
+                    stats: bool = False):
+        return self._tree(load_library().wc_tree_height, t, mode, tune, out, stream, stats)

@@ -13,14 +13,17 @@ def pytest_configure(config):
 
 
 def _ensure_built():
-    """Build the small CPU-side libraries if they are absent (gcc, a second or two).
-    The HIP library is never built here: __graft_entry__.build() does that."""
+    """Build whichever library is absent (never rebuilds one that exists:
+    __graft_entry__.build() is the step that recompiles everything)."""
     import oracle.build
     import synth.build
     if not os.path.exists(os.path.join(ROOT, "synth", "libsynth.so")):
         synth.build.build()
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build.build()
+    if not os.path.exists(os.path.join(ROOT, "paper_1606_08150_amd", "libwc.so")):
+        import paper_1606_08150_amd.build
+        paper_1606_08150_amd.build.build()
 
 
 _ensure_built()
@@ -33,3 +36,15 @@ def c1_graph():
     g = synth.rmat_csr(12, 1 << 16)
     w = synth.weights(g.m)
     return g, w
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """One libwc context on cuda:0 for the whole GPU session."""
+    import torch
+    from paper_1606_08150_amd import wc
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible HIP device")
+    c = wc.Context(0)
+    yield c
+    c.close()

@@ -1,0 +1,48 @@
+"""The C-ABI library loads on the CPU and exports every symbol include/wc.h declares;
+its host-side planning helpers agree with the oracle and the cited fixtures."""
+import os
+import re
+
+import oracle
+
+from paper_1606_08150_amd import wc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "wc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = wc.load_library()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(wc.EXPORTS)
+
+
+def test_version_string():
+    assert b"gfx950" in wc.load_library().wc_version()
+
+
+def test_host_helpers_match_oracle():
+    for args in [(256, 1, 4), (64, 3, 4), (1, 1, 1), (1024, 2, 8)]:
+        assert wc.per_buffer_size(*args) == oracle.per_buffer_size(*args)
+    for args in [(26, 1024, 1), (26, 1024, 16), (208, 256, 32), (1, 64, 32), (2048, 256, 16)]:
+        assert wc.kc_config(*args) == oracle.kc_config(*args)
+
+
+def test_default_tune_and_errors():
+    t = wc.default_tune("sssp", "grid", 2048)
+    assert t["grid_blocks"] == 2048 and t["items_per_lane"] == 4 and t["block_threads"] == 256
+    assert wc.default_tune("tree", "block", 100)["threshold"] == 0
+    try:
+        wc.default_tune("nope", "grid", 1)
+    except wc.WcError as e:
+        assert e.status == -1
+    else:
+        raise AssertionError("unknown problem accepted")

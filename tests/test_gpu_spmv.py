@@ -1,0 +1,136 @@
+"""GPU parity of wc_spmv against the binary64 oracle: every row within
+|y - y_ref| <= 1e-5 * sum|a_ij x_j|, bitwise reproducible per (mode, tune), and
+the consolidation bookkeeping (buffered rows, dispatches) equal to the oracle's
+count for the same threshold and scope."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import f32_to_dev, say
+from paper_1606_08150_amd import wc
+
+pytestmark = pytest.mark.gpu
+MODES = ["flat", "wave", "block", "grid"]
+
+
+def run(ctx, g, val, x, mode, stats=False, **tune):
+    da = wc.DeviceCSR.from_host(g.row_ptr, g.col)
+    t = wc.make_tune(**tune) if tune else None
+    say(f"spmv n={g.n} m={g.m} mode={mode} tune={tune}")
+    res = ctx.spmv(da, f32_to_dev(val), f32_to_dev(x), mode=mode, tune=t, stats=stats)
+    torch.cuda.synchronize()
+    if stats:
+        return res[0].cpu().numpy(), res[1]
+    return res.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c1(c1_graph):
+    g, _ = c1_graph
+    val, x = synth.values(g.m), synth.vector_x(g.n)
+    y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, x)
+    return g, val, x, y_ref, b
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_scale12_within_tolerance(ctx, c1, mode):
+    g, val, x, y_ref, b = c1
+    y = run(ctx, g, val, x, mode)
+    assert oracle.spmv_check(y_ref, b, y) == (0, -1)
+
+
+@pytest.mark.parametrize("mode", ["wave", "block", "grid"])
+@pytest.mark.parametrize("tune", [dict(threshold=1), dict(threshold=2, block_threads=64), dict(threshold=500),
+                                  dict(items_per_lane=1), dict(items_per_lane=16, block_threads=1024),
+                                  dict(grid_blocks=2, block_threads=128)])
+def test_tune_sweep_and_determinism(ctx, c1, mode, tune):
+    g, val, x, y_ref, b = c1
+    y1 = run(ctx, g, val, x, mode, **tune)
+    y2 = run(ctx, g, val, x, mode, **tune)
+    assert oracle.spmv_check(y_ref, b, y1) == (0, -1)
+    assert np.array_equal(y1.view(np.uint32), y2.view(np.uint32))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_cases(ctx, mode):
+    rng = np.random.default_rng(8)
+    cases = []
+    n = 1500
+    cases.append(("identity", synth.graph_from_edges(n, [(i, i) for i in range(n)])[0]))
+    cases.append(("empty_rows", synth.graph_from_edges(n, [(7, 3), (7, 9), (1000, 1)])[0]))
+    cases.append(("one_huge_row", synth.graph_from_edges(n, [(3, j % n) for j in range(100000)])[0]))
+    cases.append(("no_entries", synth.graph_from_edges(n, [])[0]))
+    cases.append(("single", synth.graph_from_edges(1, [(0, 0)])[0]))
+    e = list(zip(rng.integers(0, 300, 9000).tolist(), rng.integers(0, 300, 9000).tolist()))
+    cases.append(("uniform", synth.graph_from_edges(300, e)[0]))
+    for name, g in cases:
+        val = synth.values(g.m, seed=31)
+        x = synth.vector_x(g.n, seed=37)
+        y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, x)
+        for tune in (dict(), dict(threshold=1), dict(threshold=1, items_per_lane=1)):
+            y = run(ctx, g, val, x, mode, **tune)
+            assert oracle.spmv_check(y_ref, b, y) == (0, -1), (name, tune)
+            empty = np.diff(g.row_ptr) == 0
+            assert (y[empty] == 0).all()
+
+
+def test_bookkeeping_matches_oracle_plan(ctx, c1):
+    g, val, x, y_ref, b = c1
+    lens = np.diff(g.row_ptr).astype(np.int64)
+    for t in (8, 32, 100):
+        heavy = oracle.count_heavy(lens, t)
+        _, st = run(ctx, g, val, x, "wave", stats=True, threshold=t)
+        assert st["items_buffered"] == heavy
+        assert st["dispatches"] == oracle.consolidation_plan(lens, t, 64)["dispatches"]
+        assert st["edges_processed"] == g.m
+        for bt in (128, 256):
+            _, st = run(ctx, g, val, x, "block", stats=True, threshold=t, block_threads=bt)
+            assert st["items_buffered"] == heavy
+            assert st["dispatches"] == oracle.consolidation_plan(lens, t, bt)["dispatches"]
+        _, st = run(ctx, g, val, x, "grid", stats=True, threshold=t)
+        assert st["items_buffered"] == heavy and st["dispatches"] == (1 if heavy else 0)
+        _, st = run(ctx, g, val, x, "flat", stats=True)
+        assert st["items_buffered"] == 0 and st["dispatches"] == 0
+
+
+def test_fig2_worked_example(ctx):
+    """Two heavy rows of 326 and 234 nonzeros in one scope: one consolidated
+    dispatch carrying both (Sec. IV.A, Fig. 2)."""
+    lens = [3, 326, 5, 7, 234, 2, 1, 8]
+    n = 400
+    edges = [(r, j % n) for r, ln in enumerate(lens) for j in range(ln)]
+    g, _ = synth.graph_from_edges(n, edges)
+    val, x = synth.values(g.m, seed=5), synth.vector_x(n, seed=6)
+    y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, x)
+    plan = oracle.consolidation_plan(np.diff(g.row_ptr), 64, n)
+    assert plan["basic_launches"] == 2 and plan["total_work"] == 560
+    for mode in ("wave", "block", "grid"):
+        y, st = run(ctx, g, val, x, mode, stats=True, threshold=64)
+        assert oracle.spmv_check(y_ref, b, y) == (0, -1)
+        assert st["items_buffered"] == 2 and st["dispatches"] == 1
+
+
+def test_grid_overflow(ctx, c1):
+    g, val, x, y_ref, b = c1
+    y, st = run(ctx, g, val, x, "grid", stats=True, threshold=4, buf_capacity=7)
+    assert st["overflowed"] == 1 and oracle.spmv_check(y_ref, b, y) == (0, -1)
+    with pytest.raises(wc.WcError):
+        run(ctx, g, val, x, "grid", stats=True, threshold=4, buf_capacity=7, allow_fallback=-1)
+
+
+@pytest.fixture(scope="module")
+def c2_spmv():
+    say("generating scale-22 matrix")
+    g = synth.rmat_csr(22, 1 << 26)
+    val, x = synth.values(g.m), synth.vector_x(g.n)
+    y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, x)
+    return g, val, x, y_ref, b
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_scale22_within_tolerance(ctx, c2_spmv, mode):
+    g, val, x, y_ref, b = c2_spmv
+    y = run(ctx, g, val, x, mode)
+    assert oracle.spmv_check(y_ref, b, y) == (0, -1)

@@ -1,0 +1,114 @@
+"""GPU parity of wc_tree_descendants / wc_tree_height against the oracle
+(bit-exact), every mode and driver, special shapes, and the 2^22-node tree."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import say
+from paper_1606_08150_amd import wc
+
+pytestmark = pytest.mark.gpu
+MODES = ["flat", "wave", "block", "grid"]
+
+
+def run(ctx, t, what, mode, stats=False, **tune):
+    dt = wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child)
+    tt = wc.make_tune(**tune) if tune else None
+    say(f"tree {what} n={t.n} mode={mode} tune={tune}")
+    fn = ctx.tree_descendants if what == "desc" else ctx.tree_height
+    res = fn(dt, mode=mode, tune=tt, stats=stats)
+    torch.cuda.synchronize()
+    if stats:
+        return res[0].cpu().numpy(), res[1]
+    return res.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small_tree():
+    t = synth.random_tree(1 << 16, seed=5)
+    return t, oracle.tree_descendants(t.child_ptr, t.child), oracle.tree_height(t.child_ptr, t.child)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_random_tree_all_modes(ctx, small_tree, mode):
+    t, d, h = small_tree
+    assert np.array_equal(run(ctx, t, "desc", mode), d)
+    assert np.array_equal(run(ctx, t, "height", mode), h)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("tune", [dict(block_threads=64), dict(block_threads=1024), dict(items_per_lane=1),
+                                  dict(items_per_lane=16), dict(grid_blocks=2),
+                                  dict(block_threads=128, items_per_lane=2)])
+def test_tune_sweep(ctx, small_tree, mode, tune):
+    t, d, h = small_tree
+    assert np.array_equal(run(ctx, t, "desc", mode, **tune), d)
+    assert np.array_equal(run(ctx, t, "height", mode, **tune), h)
+
+
+def shapes():
+    yield "root_only", synth.tree_from_parent([-1])
+    yield "pair", synth.tree_from_parent([-1, 0])
+    yield "chain", synth.chain_tree(300)
+    yield "star", synth.star_tree(10000)
+    yield "kary2", synth.kary_tree(2, 12)
+    yield "kary7", synth.kary_tree(7, 4)
+    yield "wide_fanout", synth.random_tree(20000, seed=77, kmax=4096, alpha=1.2)
+    yield "narrow", synth.random_tree(20000, seed=78, kmax=3, alpha=0.5, max_depth=1 << 20)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_shapes(ctx, mode):
+    for name, t in shapes():
+        d = oracle.tree_descendants(t.child_ptr, t.child)
+        h = oracle.tree_height(t.child_ptr, t.child)
+        for tune in (dict(), dict(block_threads=64, items_per_lane=1)):
+            assert np.array_equal(run(ctx, t, "desc", mode, **tune), d), (name, tune)
+            assert np.array_equal(run(ctx, t, "height", mode, **tune), h), (name, tune)
+
+
+def test_persistent_driver_is_refused(ctx, small_tree):
+    t, _, _ = small_tree
+    with pytest.raises(wc.WcError) as ei:
+        run(ctx, t, "desc", "grid", driver=1)
+    assert ei.value.status == -1
+    torch.cuda.synchronize()
+
+
+def test_bookkeeping(ctx, small_tree):
+    t, d, h = small_tree
+    internal = int((np.diff(t.child_ptr) > 0).sum())
+    for mode in ("wave", "block", "grid"):
+        _, st = run(ctx, t, "desc", mode, stats=True)
+        # every recursive call below the root is buffered exactly once
+        assert st["items_buffered"] == internal - 1, mode
+        assert st["edges_processed"] == t.n - 1, mode
+    _, st = run(ctx, t, "desc", "grid", stats=True)
+    assert st["dispatches"] == h[0] and st["rounds"] == h[0]
+    _, st = run(ctx, t, "desc", "wave", stats=True)
+    assert internal / 64 <= st["dispatches"] <= internal
+    _, st = run(ctx, t, "desc", "flat", stats=True)
+    assert st["items_buffered"] == 0
+
+
+def test_repeat_runs_queue_modes(ctx, small_tree):
+    t, d, h = small_tree
+    for _ in range(10):
+        for mode in ("wave", "block"):
+            assert np.array_equal(run(ctx, t, "desc", mode), d)
+
+
+@pytest.fixture(scope="module")
+def c3_tree():
+    say("generating 2^22-node tree")
+    t = synth.random_tree(1 << 22)
+    return t, oracle.tree_descendants(t.child_ptr, t.child), oracle.tree_height(t.child_ptr, t.child)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_2p22_tree_bit_exact(ctx, c3_tree, mode):
+    t, d, h = c3_tree
+    assert np.array_equal(run(ctx, t, "desc", mode), d)
+    assert np.array_equal(run(ctx, t, "height", mode), h)
