@@ -42,25 +42,138 @@ def parse():
     p.add_argument("--no-modes", action="store_true", help="skip the flat/wave/block/grid side-by-side table")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-reps", type=int, default=5)
+    p.add_argument("--calibrate-copy-mb", type=int, default=0,
+                   help="first run a plain device-to-device copy of this many MiB three times (a known-size "
+                        "kernel for scaling hardware byte counters)")
     return p.parse_args()
 
 
-def algorithmic_bytes(kernel: str, info: dict) -> tuple[float, str] | None:
-    """Algorithmic bytes a launch of `kernel` must move (read once), from the
-    per-unit figures: SpMV 12 B per nonzero (col, val, x gather) + 8 B per row
-    (row_ptr, y); SSSP 16 B per edge (col, w, dist read-modify-write) + 20 B per
-    frontier vertex (row_ptr pair, dist, frontier in/out)."""
+def algorithmic_bytes(kernel: str, info: dict, launches: int) -> tuple[float, str] | None:
+    """Algorithmic bytes per launch of `kernel` (each datum read or written once),
+    from the per-unit figures: SpMV 12 B per nonzero (col, val, x gather) + 8 B
+    per row (row_ptr, y); SSSP 16 B per edge relaxation (col, w, dist read and
+    write).  For kernels launched once per round the units are the per-call
+    totals spread over that call's launches (empty trailing rounds included)."""
     if kernel == "spmv_drain":
-        return 12.0 * info["nnz_heavy"] + 4.0 * info["rows_heavy"], "nnz in buffered rows x 12 B + rows x 4 B"
-    if kernel.startswith("spmv_parent"):
+        return 12.0 * info["nnz_heavy"] + 4.0 * info["rows_heavy"], "12 B x nonzeros of buffered rows + 4 B x rows"
+    if kernel == "spmv_parent_grid":
         return (12.0 * info["nnz_light"] + 8.0 * info["n"],
-                "nnz in inline rows x 12 B + rows x 8 B (row_ptr, y)")
-    if kernel in ("sssp_drain",) or kernel.startswith("sssp_round"):
-        return None
+                "12 B x nonzeros of inline rows + 8 B x rows (row_ptr, y)")
+    if kernel == "sssp_drain":
+        per_call = info["sssp_edges_buffered"] * 16.0
+        return per_call * info["sssp_calls"] / launches, "16 B x edges relaxed by the drain (col, w, dist r+w)"
+    if kernel.startswith("sssp_round"):
+        inline = info["sssp_edges"] - info["sssp_edges_buffered"]
+        per_call = 16.0 * inline + 4.0 * info["n"] * info["sssp_rounds"]
+        return (per_call * info["sssp_calls"] / launches,
+                "16 B x inline edges + 4 B x vertices scanned per round")
     return None
 
 
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/<kernel>_<workload>_pmc.json (FETCH_SIZE and WRITE_SIZE scaled by the
+    copy calibration), or None when absent or taken on different kernel sources."""
+    symbol = {"sssp_round_grid": "sssp_round"}.get(kernel, kernel)  # counter files use the kernel symbol
+    path = os.path.join(ROOT, "profiles", f"{symbol}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1606_08150_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def _short_kernel(name: str) -> str:
+    import re
+    m = re.search(r"(\w+)(<[^()]*>)?\(", name.replace("(anonymous namespace)", "anon"))
+    return m.group(1) if m else name
+
+
+def summarize_kernel_stats(stats_csv, workload, command, out_name):
+    """profiles/<out_name>.md from a rocprofv3 --kernel-trace --stats csv."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# Kernel statistics: {workload}", "", "Command:", "", "```", command, "```", "",
+             "| kernel (symbol) | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {_short_kernel(r['Name'])} `{r['Name'][:70]}` | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def summarize_profiles(fetch_dir, write_dir, copy_mb, workload, command):
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; csv output) of
+    `command` into profiles/<kernel>_<workload>_pmc.json files: KiB per dispatch
+    scaled by what the same counters read for the calibration copy (a plain
+    device copy of known size run first by the same command)."""
+    import collections
+    import csv
+
+    def load(d, counter):
+        per = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] == counter:
+                key = "calibration_copy" if "bitwise_not" in r["Kernel_Name"] else _short_kernel(r["Kernel_Name"])
+                per[key].append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copies = fetch["calibration_copy"]
+    known = 3 * copy_mb * 1024.0 * 1024.0 / len(copies)  # bytes read (and written) per copy dispatch
+    f_scale = known / (np.mean(copies) * 1024.0)
+    w_scale = known / (np.mean(write["calibration_copy"]) * 1024.0)
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    out = {}
+    for k in sorted(set(fetch) & set(write)):
+        if k.startswith(("sssp_", "spmv_", "tree_")):
+            fb = float(np.mean(fetch[k])) * 1024.0 * f_scale
+            wb = float(np.mean(write[k])) * 1024.0 * w_scale
+            rec = {"kernel": k, "workload": workload, "dispatches": len(fetch[k]),
+                   "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+                   "hbm_bytes_per_launch": round(fb + wb), "fetch_scale": round(f_scale, 4),
+                   "write_scale": round(w_scale, 4),
+                   "calibration": f"{copy_mb} MiB elementwise copy (bitwise_not) x3, {len(copies)} dispatches "
+                                  f"of {known / 2**20:.0f} MiB read + written each",
+                   "command": command, "source_hash": source_hash()}
+            with open(os.path.join(ROOT, "profiles", f"{k}_{workload}_pmc.json"), "w") as f:
+                json.dump(rec, f, indent=1)
+            out[k] = rec
+    print(json.dumps(out, indent=1))
+
+
 def main():
+    if "--summarize-profiles" in sys.argv:
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--summarize-profiles", action="store_true")
+        sp.add_argument("--fetch-dir", required=True)
+        sp.add_argument("--write-dir", required=True)
+        sp.add_argument("--copy-mb", type=int, required=True)
+        sp.add_argument("--workload", default="rmat22")
+        sp.add_argument("--command", required=True)
+        sp.add_argument("--stats-csv", default=None)
+        sp.add_argument("--stats-command", default=None)
+        sp.add_argument("--stats-name", default=None)
+        a = sp.parse_args()
+        summarize_profiles(a.fetch_dir, a.write_dir, a.copy_mb, a.workload, a.command)
+        if a.stats_csv:
+            summarize_kernel_stats(a.stats_csv, a.workload, a.stats_command, a.stats_name)
+        return
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design note, "
@@ -80,6 +193,19 @@ def main():
     w = synth.weights(g.m)
     val, x = synth.values(g.m), synth.vector_x(g.n)
     print(f"[bench] inputs generated in {time.time() - t0:.1f}s (n={g.n}, m={g.m})", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy_mb > 0:
+        # a plain elementwise copy with a unique kernel name (bitwise_not: one
+        # 4-byte read and one 4-byte write per element)
+        nb = args.calibrate_copy_mb << 20
+        src_buf = torch.zeros(nb // 4, dtype=torch.int32, device="cuda")
+        dst_buf = torch.empty_like(src_buf)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.bitwise_not(src_buf, out=dst_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
+        print(f"[bench] calibration copy: 3 x {args.calibrate_copy_mb} MiB", file=sys.stderr, flush=True)
 
     ctx = wc.Context(0)
     dg = wc.DeviceCSR.from_host(g.row_ptr, g.col)
@@ -102,6 +228,8 @@ def main():
     reached_mask = dist != -1  # INF as int32
     m_reached = int(deg[reached_mask].sum().item())
     n_reached = int(reached_mask.sum().item())
+    # per-call work counters (outside the timed region)
+    _, sst = ctx.sssp(dg, dw, 0, mode=args.mode, out=dist, stats=True)
 
     # ---- timed region: K steps of (SSSP + SpMV), per-kernel events on the launch stream
     for _ in range(args.warmup):
@@ -138,25 +266,29 @@ def main():
     thr = wc.default_tune("spmv", args.mode, 1)["threshold"]
     heavy = lens > thr
     info = dict(n=g.n, nnz_heavy=int(lens[heavy].sum()), rows_heavy=int(heavy.sum()),
-                nnz_light=int(lens[~heavy].sum()))
+                nnz_light=int(lens[~heavy].sum()), sssp_edges=sst["edges_processed"],
+                sssp_edges_buffered=sst["edges_buffered"], sssp_rounds=sst["rounds"], sssp_calls=args.steps)
+    workload_tag = f"rmat{scale}"
     dominant = max(ktimes.items(), key=lambda kv: kv[1][1])
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
                for k, v in sorted(ktimes.items(), key=lambda kv: -kv[1][1])}
-    roofline = None
-    # the largest kernel with an algorithmic-byte model
-    for name, (launches, total, _) in sorted(ktimes.items(), key=lambda kv: -kv[1][1]):
-        ab = algorithmic_bytes(name, info)
+    def roof(name):
+        launches, total, _ = ktimes[name]
+        ab = algorithmic_bytes(name, info, launches)
         if ab is None:
-            continue
+            return None
         bytes_per_launch, what = ab
         avg_s = total / launches * 1e-3
         achieved = bytes_per_launch / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "bytes_per_launch": bytes_per_launch, "bytes_model": what,
-                    "avg_launch_ms": round(total / launches, 5), "dominant_kernel": dominant[0],
-                    "is_dominant": name == dominant[0]}
-        break
+        traffic = counter_traffic(name, workload_tag)
+        return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic is not None else None,
+                "bytes_per_launch": round(bytes_per_launch), "bytes_model": what,
+                "launches": launches, "avg_launch_ms": round(total / launches, 5)}
+
+    roofline = roof(dominant[0])
+    spmv_roofline = roof("spmv_drain") if "spmv_drain" in ktimes else None
 
     # ---- flat / wave / block / grid side by side (1 timed run each after 1 warm-up)
     modes = {}
@@ -215,6 +347,9 @@ def main():
         "spmv_gbs": round(spmv_gbs, 1),
         "spmv_frac_hbm": round(spmv_gbs / HBM_PEAK_GBS, 4),
         "roofline": roofline,
+        "spmv_roofline": spmv_roofline,
+        "sssp_work": {"edges_relaxed": sst["edges_processed"], "edges_by_consolidated_child": sst["edges_buffered"],
+                      "rounds": sst["rounds"], "items_buffered": sst["items_buffered"]},
         "kernels": kernels,
         "modes": modes,
         "cpu_baseline": cpu,

@@ -115,6 +115,7 @@ typedef struct {
     int64_t items_buffered;  /* work items inserted into consolidation buffers */
     int64_t dispatches;      /* consolidated child dispatches (non-empty buffers drained) */
     int64_t edges_processed; /* edges relaxed / nonzeros multiplied / children visited */
+    int64_t edges_buffered;  /* the part of edges_processed handled by consolidated children */
     float ms;                /* wall time of the call on its stream, from HIP events */
 } wc_stats;
 

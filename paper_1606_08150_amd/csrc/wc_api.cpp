@@ -114,6 +114,9 @@ static int default_threshold(const char *problem, wc_mode mode)
 {
     if (mode == WC_FLAT) return INT_MAX;
     if (!strcmp(problem, "tree")) return 0;  // every node with children is a recursive call (Fig. 1(c))
+    // grid level drains with lane groups sized to each item, so only very short
+    // items stay inline; wave and block levels drain with whole groups
+    if (mode == WC_GRID) return !strcmp(problem, "spmv") ? 4 : 8;
     return 32;
 }
 
@@ -152,7 +155,8 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
 // so that a captured graph replays it correctly.
 __global__ void zero_stats(DevStats *s)
 {
-    if (threadIdx.x == 0) *s = DevStats{};
+    unsigned int *w = reinterpret_cast<unsigned int *>(s);
+    for (unsigned i = threadIdx.x; i < sizeof(DevStats) / 4; i += blockDim.x) w[i] = 0u;
 }
 
 wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats)
@@ -177,9 +181,12 @@ wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds,
         WC_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
         stats->rounds = rounds;
         stats->overflowed = ds.overflowed;
-        stats->items_buffered = (int64_t)ds.items_buffered;
-        stats->dispatches = (int64_t)ds.dispatches;
-        stats->edges_processed = (int64_t)ds.edges_processed;
+        for (int r = 0; r < kStatReps; ++r) {
+            stats->items_buffered += (int64_t)ds.rep[r].items_buffered;
+            stats->dispatches += (int64_t)ds.rep[r].dispatches;
+            stats->edges_processed += (int64_t)ds.rep[r].edges_processed;
+            stats->edges_buffered += (int64_t)ds.rep[r].edges_buffered;
+        }
         stats->ms = ms;
     } else if (fail_on_overflow) {
         WC_HIP(hipMemcpyAsync(&ds, ctx->dstats, sizeof(ds), hipMemcpyDeviceToHost, stream));

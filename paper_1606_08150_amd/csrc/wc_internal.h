@@ -13,11 +13,20 @@
 
 namespace wc {
 
-// Device counters accumulated by kernels when stats are requested.
-struct DevStats {
+// Device counters accumulated by kernels when stats are requested.  Each
+// workgroup adds its totals to one of kStatReps replicas (on separate cache
+// lines) so the counting itself does not serialize on a few addresses; the
+// host sums the replicas.
+constexpr int kStatReps = 64;
+struct StatRep {
     unsigned long long items_buffered;
     unsigned long long dispatches;
     unsigned long long edges_processed;
+    unsigned long long edges_buffered;
+    unsigned long long pad[12];
+};
+struct DevStats {
+    StatRep rep[kStatReps];
     int overflowed;
     int timed_out;
     int rounds;

@@ -8,23 +8,34 @@
 //   block - thread-ordered LDS buffer, then the workgroup barrier.  Rows longer
 //           than BLOCK * items_per_lane are summed by the whole block (fixed
 //           block reduction); the others are shared out to the block's waves.
-//   grid  - global buffer of row chunks of 64 * items_per_lane nonzeros; after
-//           the grid-wide barrier one wave sums each chunk.  A row split into
-//           several chunks also gets an entry in a second buffer, and its chunk
-//           partials are combined in chunk order (deterministic).
+//   grid  - global buffers and a grid-wide barrier (kernel boundary).  The
+//           child-work thread-count heuristic sizes the group of lanes that
+//           sums one buffered row: g = the power of two >= len / items_per_lane,
+//           so each lane takes about items_per_lane nonzeros.  Rows are binned by
+//           g (1..64) and one wave sums 64 / g rows of a bin at once; a row
+//           longer than 64 * items_per_lane is split into chunks of that size,
+//           one wave each, and its chunk partials are combined in chunk order.
+//           A counting pass sizes the bins before the parent pass fills them.
 //   flat  - every row is summed by its own lane.
-// All sums use fp32 fused multiply-adds in a fixed order per mode and tune, so
-// results are bitwise reproducible; each stays within 1e-5 of the row's
-// magnitude sum of the exact product.
-#include <cstring>
+// All sums are fp32 fused multiply-adds whose order depends only on the row
+// length, the mode and the tune, so results are bitwise reproducible; each
+// stays within 1e-5 of the row's magnitude sum of the exact product.
 #include <algorithm>
+#include <cstring>
 
 #include "wc_block.h"
 #include "wc_device.h"
 #include "wc_internal.h"
+#include "wc_stats.h"
 
 namespace wc {
 namespace {
+
+constexpr int kBins = 7;      // group sizes 1, 2, 4, ..., 64 lanes
+constexpr int kChunkBin = 7;  // rows split into whole-wave chunks
+constexpr int kUnroll = 4;    // nonzeros in flight per lane
+constexpr int kMultiCol = 8;  // column of the per-block counts holding split rows
+constexpr int kCols = 9;
 
 struct SpmvArgs {
     const int *row_ptr;
@@ -34,31 +45,67 @@ struct SpmvArgs {
     float *y;
     int n;
     int threshold;
-    int chunk;
+    int ipl;           // items per lane
+    int chunk;         // 64 * ipl
     int big;           // block mode: rows longer than this use the whole block
-    int4 *chunks;      // (row, begin, end, 1 if the row has several chunks)
+    // grid mode
+    int *blk_count;    // [grid * kCols]: per parent block, rows per bin 0..6, chunks, split rows
+    int *blk_off;      // [grid * kCols]: exclusive offsets of each block within its column
+    int *bin_total;    // [kCols]: column totals
+    int4 *rows_buf;    // binned rows: (row, begin, end, 0), bins laid out by prefix of totals
+    long long rows_cap;
+    int4 *chunks;      // (row, begin, end, 0)
     long long chunk_cap;
-    int *chunk_tail;
     int4 *multi;       // (row, first chunk, chunk count, 0)
-    int *multi_tail;
+    long long multi_cap;
     float *partials;   // one per chunk slot
     DevStats *stats;
     int want_stats;
 };
 
-__device__ __forceinline__ float dot_lane(const SpmvArgs &a, int beg, int end)
+// Sum of val[e] * x[col[e]] over e = first + k * stride (k >= 0, e < end), in
+// order of k, kUnroll loads in flight.
+__device__ __forceinline__ float dot_strided(const SpmvArgs &a, int first, int stride, int end)
 {
     float s = 0.f;
-    for (int e = beg; e < end; ++e) s = fmaf(a.val[e], a.x[a.col[e]], s);
+    for (int e0 = first; e0 < end; e0 += kUnroll * stride) {
+        int c[kUnroll];
+        float v[kUnroll], xv[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            const int e = e0 + k * stride;
+            const bool ok = e < end;
+            c[k] = ok ? a.col[e] : -1;
+            v[k] = ok ? a.val[e] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) xv[k] = c[k] >= 0 ? a.x[c[k]] : 0.f;
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k)
+            if (c[k] >= 0) s = fmaf(v[k], xv[k], s);
+    }
     return s;
 }
 
-// Whole-wave dot product of [beg, end) (uniform arguments); every lane gets the sum.
 __device__ __forceinline__ float dot_wave(const SpmvArgs &a, int beg, int end)
 {
-    float s = 0.f;
-    for (int e = beg + lane_id(); e < end; e += kWave) s = fmaf(a.val[e], a.x[a.col[e]], s);
-    return wave_sum(s);
+    return wave_sum(dot_strided(a, beg + lane_id(), kWave, end));
+}
+
+// Sum over aligned groups of g lanes (g a power of two <= 64), fixed order.
+__device__ __forceinline__ float group_sum(float v, int g)
+{
+    for (int d = g >> 1; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int bin_of(int len, int ipl)
+{
+    // g = smallest power of two with g * ipl >= len, as a bin index (log2 g)
+    int need = (len + ipl - 1) / ipl;
+    int b = 0;
+    while ((1 << b) < need) ++b;
+    return b;
 }
 
 template <int BLOCK>
@@ -70,10 +117,20 @@ struct SpmvBlockBuf {
     float red[BLOCK / kWave];
 };
 
+__device__ __forceinline__ void count_stats(StatAcc &acc, int len, bool heavy, bool wave_dispatch)
+{
+    acc.edges += len;
+    acc.buffered += heavy ? len : 0;
+    acc.items += heavy ? 1 : 0;
+    if (wave_dispatch && __ballot(heavy) && lane_id() == 0) acc.dispatches += 1;
+}
+
+// Parent kernel of the flat, wave and block modes.
 template <int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void spmv_parent(SpmvArgs a)
 {
     const int lane = lane_id();
+    StatAcc acc;
     for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {
         const int r = base + threadIdx.x;
         const bool valid = r < a.n;
@@ -84,16 +141,8 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent(SpmvArgs a)
         }
         const int len = end - beg;
         const bool heavy = MODE != WC_FLAT && len > a.threshold;
-        if (a.want_stats) {
-            int s = wave_sum_i(len);
-            uint64_t hm = __ballot(heavy);
-            if (lane == 0) {
-                atomic_add_dev(&a.stats->edges_processed, (unsigned long long)s);
-                atomic_add_dev(&a.stats->items_buffered, (unsigned long long)__builtin_popcountll(hm));
-                if (MODE == WC_WAVE && hm) atomic_add_dev(&a.stats->dispatches, 1ull);
-            }
-        }
-        if (valid && !heavy) a.y[r] = dot_lane(a, beg, end);
+        if (a.want_stats) count_stats(acc, len, heavy, MODE == WC_WAVE);
+        if (valid && !heavy) a.y[r] = dot_strided(a, beg, 1, end);
 
         if constexpr (MODE == WC_WAVE) {
             uint64_t mask = __ballot(heavy);
@@ -113,14 +162,13 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent(SpmvArgs a)
                 sb.beg[k] = beg;
                 sb.end[k] = end;
             }
-            if (threadIdx.x == 0 && a.want_stats && nb) atomic_add_dev(&a.stats->dispatches, 1ull);
+            if (threadIdx.x == 0 && a.want_stats && nb) acc.dispatches += 1;
             __syncthreads();  // the "synchronize" between inserts and the child
             // rows too long for one wave: the whole block, one row at a time
             for (int it = 0; it < nb; ++it) {
                 const int rb = sb.beg[it], re = sb.end[it];
                 if (re - rb <= a.big) continue;
-                float s = 0.f;
-                for (int e = rb + (int)threadIdx.x; e < re; e += BLOCK) s = fmaf(a.val[e], a.x[a.col[e]], s);
+                float s = dot_strided(a, rb + (int)threadIdx.x, BLOCK, re);
                 s = block_sum<BLOCK>(s, sb.red);
                 if (threadIdx.x == 0) a.y[sb.row[it]] = s;
             }
@@ -133,48 +181,186 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent(SpmvArgs a)
                 if (lane == 0) a.y[sb.row[it]] = s;
             }
             __syncthreads();  // LDS buffer is reused by the next window
-        } else if constexpr (MODE == WC_GRID) {
-            const int nch = heavy ? (len + a.chunk - 1) / a.chunk : 0;
-            const int slot = wave_reserve_n(nch, a.chunk_tail);
-            const bool fits = heavy && (long long)slot + nch <= a.chunk_cap;
-            const int mslot = wave_reserve(fits && nch > 1, a.multi_tail);
-            if (heavy) {
-                if (fits) {
-                    for (int c = 0; c < nch; ++c) {
-                        int cb = beg + c * a.chunk;
-                        a.chunks[slot + c] = make_int4(r, cb, min(end, cb + a.chunk), nch > 1 ? 1 : 0);
-                    }
-                    if (nch > 1) a.multi[mslot] = make_int4(r, slot, nch, 0);
+        }
+    }
+    if (a.want_stats) stat_flush(a.stats, acc);
+}
+
+// ---- grid mode --------------------------------------------------------------------------------
+
+// Counting pass: each parent block counts, over exactly the rows it will take
+// in the parent pass, its rows per bin, its chunks of split rows and its split
+// rows.  No atomics: one row of counts per block.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void spmv_classify(SpmvArgs a)
+{
+    __shared__ int cnt[kCols];
+    if (threadIdx.x < kCols) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int mine[kCols];
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) mine[c] = 0;
+    for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {
+        const int r = base + threadIdx.x;
+        if (r < a.n) {
+            const int len = a.row_ptr[r + 1] - a.row_ptr[r];
+            if (len > a.threshold) {
+                if (len > a.chunk) {
+                    mine[kChunkBin] += (len + a.chunk - 1) / a.chunk;
+                    mine[kMultiCol] += 1;
                 } else {
-                    // buffer full: mark the reserved slots that exist as empty and
-                    // sum the row inline (fallback)
-                    for (int c = 0; c < nch; ++c)
-                        if ((long long)slot + c < a.chunk_cap) a.chunks[slot + c] = make_int4(-1, 0, 0, 0);
-                    a.stats->overflowed = 1;
-                    a.y[r] = dot_lane(a, beg, end);
+                    const int b = bin_of(len, a.ipl);
+#pragma unroll
+                    for (int c = 0; c < kBins; ++c) mine[c] += c == b;
                 }
             }
         }
     }
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+        int v = wave_sum_i(mine[c]);
+        if (lane_id() == 0 && v) atomicAdd(&cnt[c], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCols) a.blk_count[blockIdx.x * kCols + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// Consolidated child of grid-level consolidation: one wave per chunk.
+// Exclusive scan of the per-block counts down each column (one workgroup).
+__global__ __launch_bounds__(1024) void spmv_scan(SpmvArgs a, int nblocks)
+{
+    __shared__ int tmp[2 * (1024 / kWave)];
+    for (int c = 0; c < kCols; ++c) {
+        int carry = 0;
+        for (int b0 = 0; b0 < nblocks; b0 += 1024) {
+            const int b = b0 + threadIdx.x;
+            const int v = b < nblocks ? a.blk_count[b * kCols + c] : 0;
+            int excl, d0, tot, d1;
+            block_scan2<1024>(v, 0, tmp, excl, d0, tot, d1);
+            if (b < nblocks) a.blk_off[b * kCols + c] = carry + excl;
+            carry += tot;
+        }
+        if (threadIdx.x == 0) a.bin_total[c] = carry;
+    }
+}
+
+// Parent pass of grid mode: light rows inline, heavy rows written into their
+// bin at the offsets the scan gave this block.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
+{
+    __shared__ int cur[kCols], binoff[kBins], cnt[kCols];
+    StatAcc acc;
+    if (threadIdx.x < kCols) cur[threadIdx.x] = a.blk_off[blockIdx.x * kCols + threadIdx.x];
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int b = 0; b < kBins; ++b) {
+            binoff[b] = o;
+            o += a.bin_total[b];
+        }
+    }
+    for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {
+        if (threadIdx.x < kCols) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const int r = base + threadIdx.x;
+        const bool valid = r < a.n;
+        int beg = 0, end = 0;
+        if (valid) {
+            beg = a.row_ptr[r];
+            end = a.row_ptr[r + 1];
+        }
+        const int len = end - beg;
+        const bool heavy = len > a.threshold;
+        if (a.want_stats) count_stats(acc, len, heavy, false);
+        if (valid && !heavy) a.y[r] = dot_strided(a, beg, 1, end);
+        int bin = -1, local = 0, nch = 0, mlocal = 0;
+        if (heavy) {
+            if (len > a.chunk) {
+                bin = kChunkBin;
+                nch = (len + a.chunk - 1) / a.chunk;
+                local = atomicAdd(&cnt[kChunkBin], nch);
+                mlocal = atomicAdd(&cnt[kMultiCol], 1);
+            } else {
+                bin = bin_of(len, a.ipl);
+                local = atomicAdd(&cnt[bin], 1);
+            }
+        }
+        __syncthreads();
+        if (bin >= 0 && bin < kBins) {
+            const long long pos = (long long)binoff[bin] + cur[bin] + local;
+            if (pos < a.rows_cap) a.rows_buf[pos] = make_int4(r, beg, end, 0);
+        } else if (bin == kChunkBin) {
+            const int slot = cur[kChunkBin] + local;
+            const long long mpos = (long long)cur[kMultiCol] + mlocal;
+            if ((long long)slot + nch <= a.chunk_cap) {
+                for (int c = 0; c < nch; ++c) {
+                    int cb = beg + c * a.chunk;
+                    a.chunks[slot + c] = make_int4(r, cb, min(end, cb + a.chunk), 0);
+                }
+                if (mpos < a.multi_cap) a.multi[mpos] = make_int4(r, slot, nch, 0);
+            } else {
+                // buffer full: mark the reserved slots that exist as empty and
+                // sum the row inline (fallback); its split-row entry combines nothing
+                for (int c = 0; c < nch; ++c)
+                    if ((long long)slot + c < a.chunk_cap) a.chunks[slot + c] = make_int4(-1, 0, 0, 0);
+                a.stats->overflowed = 1;
+                a.y[r] = dot_strided(a, beg, 1, end);
+                if (mpos < a.multi_cap) a.multi[mpos] = make_int4(-1, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kCols) cur[threadIdx.x] += cnt[threadIdx.x];
+    }
+    if (a.want_stats) stat_flush(a.stats, acc);
+}
+
+// Consolidated child of grid mode.  Wave tasks: for bin b (g = 2^b lanes per
+// row) a task is 64 / g consecutive rows of the bin; then one task per chunk.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void spmv_drain(SpmvArgs a)
 {
-    const int tail = *a.chunk_tail;
-    const int total = (long long)tail < a.chunk_cap ? tail : (int)a.chunk_cap;
+    __shared__ int s_cnt[8], s_off[8], s_task[9];
+    if (threadIdx.x == 0) {
+        int o = 0, t = 0;
+        for (int b = 0; b < 8; ++b) {
+            int c = a.bin_total[b];
+            if (b == kChunkBin) c = (long long)c < a.chunk_cap ? c : (int)a.chunk_cap;
+            s_cnt[b] = c;
+            s_off[b] = o;
+            if (b < kBins) o += c;
+            s_task[b] = t;
+            t += b < kBins ? (c + (kWave >> b) - 1) / (kWave >> b) : c;
+        }
+        s_task[8] = t;
+        if (a.want_stats && blockIdx.x == 0 && t > 0) atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
+    }
+    __syncthreads();
+    const int total = s_task[8];
     const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
     const int nw = gridDim.x * (BLOCK / kWave);
-    if (a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0) atomic_add_dev(&a.stats->dispatches, 1ull);
-    for (int c = gw; c < total; c += nw) {
-        int4 d = a.chunks[c];
-        int row = __builtin_amdgcn_readfirstlane(d.x);
-        if (row < 0) continue;
-        float s = dot_wave(a, __builtin_amdgcn_readfirstlane(d.y), __builtin_amdgcn_readfirstlane(d.z));
-        if (lane_id() == 0) {
-            if (d.w) a.partials[c] = s;
-            else a.y[row] = s;
+    const int lane = lane_id();
+    for (int t = gw; t < total; t += nw) {
+        int b = 0;
+        while (b < 7 && s_task[b + 1] <= t) ++b;
+        if (b < kBins) {
+            const int g = 1 << b;
+            const int i = (t - s_task[b]) * (kWave >> b) + (lane >> b);
+            const int sub = lane & (g - 1);
+            float s = 0.f;
+            int row = -1;
+            if (i < s_cnt[b]) {
+                int4 d = a.rows_buf[s_off[b] + i];
+                row = d.x;
+                s = dot_strided(a, d.y + sub, g, d.z);
+            }
+            s = group_sum(s, g);
+            if (row >= 0 && sub == 0) a.y[row] = s;
+        } else {
+            const int c = t - s_task[kChunkBin];
+            int4 d = a.chunks[c];
+            const int row = __builtin_amdgcn_readfirstlane(d.x);
+            if (row < 0) continue;
+            float s = dot_wave(a, __builtin_amdgcn_readfirstlane(d.y), __builtin_amdgcn_readfirstlane(d.z));
+            if (lane == 0) a.partials[c] = s;
         }
     }
 }
@@ -183,41 +369,37 @@ __global__ __launch_bounds__(BLOCK) void spmv_drain(SpmvArgs a)
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void spmv_combine(SpmvArgs a)
 {
-    const int total = *a.multi_tail;
+    const int total = (int)min((long long)a.bin_total[kMultiCol], a.multi_cap);
     const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
     const int nw = gridDim.x * (BLOCK / kWave);
     for (int i = gw; i < total; i += nw) {
         int4 d = a.multi[i];
+        const int row = __builtin_amdgcn_readfirstlane(d.x);
+        if (row < 0) continue;
         int first = __builtin_amdgcn_readfirstlane(d.y), cnt = __builtin_amdgcn_readfirstlane(d.z);
         float s = 0.f;
         for (int c = lane_id(); c < cnt; c += kWave) s += a.partials[first + c];
         s = wave_sum(s);
-        if (lane_id() == 0) a.y[d.x] = s;
-    }
-}
-
-__global__ void spmv_reset(SpmvArgs a)
-{
-    if (threadIdx.x == 0) {
-        *a.chunk_tail = 0;
-        *a.multi_tail = 0;
+        if (lane_id() == 0) a.y[row] = s;
     }
 }
 
 struct SpmvKernels {
-    const void *parent, *drain, *combine;
+    const void *parent, *classify, *parent_grid, *drain, *combine;
 };
 
 template <int BLOCK>
 SpmvKernels pick_block(wc_mode mode)
 {
-    SpmvKernels k{nullptr, reinterpret_cast<const void *>(&spmv_drain<BLOCK>),
+    SpmvKernels k{nullptr, reinterpret_cast<const void *>(&spmv_classify<BLOCK>),
+                  reinterpret_cast<const void *>(&spmv_parent_grid<BLOCK>),
+                  reinterpret_cast<const void *>(&spmv_drain<BLOCK>),
                   reinterpret_cast<const void *>(&spmv_combine<BLOCK>)};
     switch (mode) {
     case WC_FLAT: k.parent = reinterpret_cast<const void *>(&spmv_parent<WC_FLAT, BLOCK>); break;
     case WC_WAVE: k.parent = reinterpret_cast<const void *>(&spmv_parent<WC_WAVE, BLOCK>); break;
     case WC_BLOCK: k.parent = reinterpret_cast<const void *>(&spmv_parent<WC_BLOCK, BLOCK>); break;
-    default: k.parent = reinterpret_cast<const void *>(&spmv_parent<WC_GRID, BLOCK>); break;
+    default: k.parent = k.parent_grid; break;
     }
     return k;
 }
@@ -264,11 +446,15 @@ extern "C" wc_status wc_spmv(wc_ctx *ctx, const wc_csr *g, const float *val, con
     const int chunk = kWave * cfg.items_per_lane;
     long long cap_full = n + m / chunk + 1;
     long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    long long mcap = mode == WC_GRID ? cap / 2 + 1 : 1;
-    size_t need = padded(cap * 16) + padded(cap * 4) + padded(mcap * 16) + 2 * padded(4);
+    long long rows_cap = mode == WC_GRID ? n : 1;
+    long long mcap = mode == WC_GRID ? n : 1;
+    const int grid = (int)std::max<long long>(1, std::min<long long>(cfg.grid, (n + cfg.block - 1) / cfg.block));
+    size_t need = 2 * padded((size_t)grid * kCols * 4) + padded(kCols * 4) + padded(rows_cap * 16) +
+                  padded(cap * 16) + padded(cap * 4) + padded(mcap * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     SpmvArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.row_ptr = g->row_ptr;
     a.col = g->col;
     a.val = val;
@@ -276,34 +462,40 @@ extern "C" wc_status wc_spmv(wc_ctx *ctx, const wc_csr *g, const float *val, con
     a.y = y;
     a.n = (int)n;
     a.threshold = cfg.threshold;
+    a.ipl = cfg.items_per_lane;
     a.chunk = chunk;
     a.big = cfg.block * cfg.items_per_lane;
+    a.blk_count = pool_take<int>(ctx, (size_t)grid * kCols);
+    a.blk_off = pool_take<int>(ctx, (size_t)grid * kCols);
+    a.bin_total = pool_take<int>(ctx, kCols);
+    a.rows_buf = pool_take<int4>(ctx, rows_cap);
+    a.rows_cap = rows_cap;
     a.chunks = pool_take<int4>(ctx, cap);
     a.chunk_cap = cap;
     a.partials = pool_take<float>(ctx, cap);
     a.multi = pool_take<int4>(ctx, mcap);
-    a.chunk_tail = pool_take<int>(ctx, 1);
-    a.multi_tail = pool_take<int>(ctx, 1);
+    a.multi_cap = mcap;
     a.stats = ctx->dstats;
     a.want_stats = stats != nullptr;
 
     st = begin_call(ctx, stream, stats);
     if (st != WC_OK) return st;
-    const int grid = (int)std::max<long long>(1, std::min<long long>(cfg.grid, (n + cfg.block - 1) / cfg.block));
     void *args[] = {&a};
-    static const char *parent_names[] = {"spmv_parent_flat", "spmv_parent_wave", "spmv_parent_block",
-                                         "spmv_parent_grid"};
-    if (mode == WC_GRID) {
-        st = launch(ctx, "spmv_reset", reinterpret_cast<const void *>(&spmv_reset), dim3(1), dim3(64), args, stream);
+    if (mode != WC_GRID) {
+        static const char *names[] = {"spmv_parent_flat", "spmv_parent_wave", "spmv_parent_block"};
+        st = launch(ctx, names[mode], ks.parent, dim3(grid), dim3(cfg.block), args, stream);
         if (st != WC_OK) return st;
+        return end_call(ctx, stream, stats, 1, cfg.fail_on_overflow);
     }
-    st = launch(ctx, parent_names[mode], ks.parent, dim3(grid), dim3(cfg.block), args, stream);
+    const int dgrid = std::max(1, std::min(cfg.grid, resident));
+    int nblocks = grid;
+    void *sargs[] = {&a, &nblocks};
+    st = launch(ctx, "spmv_classify", ks.classify, dim3(grid), dim3(cfg.block), args, stream);
+    if (st == WC_OK)
+        st = launch(ctx, "spmv_scan", reinterpret_cast<const void *>(&spmv_scan), dim3(1), dim3(1024), sargs, stream);
+    if (st == WC_OK) st = launch(ctx, "spmv_parent_grid", ks.parent_grid, dim3(grid), dim3(cfg.block), args, stream);
+    if (st == WC_OK) st = launch(ctx, "spmv_drain", ks.drain, dim3(dgrid), dim3(cfg.block), args, stream);
+    if (st == WC_OK) st = launch(ctx, "spmv_combine", ks.combine, dim3(dgrid), dim3(cfg.block), args, stream);
     if (st != WC_OK) return st;
-    if (mode == WC_GRID) {
-        const int dgrid = std::max(1, std::min(cfg.grid, resident));
-        st = launch(ctx, "spmv_drain", ks.drain, dim3(dgrid), dim3(cfg.block), args, stream);
-        if (st == WC_OK) st = launch(ctx, "spmv_combine", ks.combine, dim3(dgrid), dim3(cfg.block), args, stream);
-        if (st != WC_OK) return st;
-    }
     return end_call(ctx, stream, stats, 1, cfg.fail_on_overflow);
 }

@@ -26,20 +26,22 @@
 #include "wc_block.h"
 #include "wc_device.h"
 #include "wc_internal.h"
+#include "wc_stats.h"
 
 namespace wc {
 namespace {
+
+constexpr int kPad = 32;  // ring entries live on separate 128-byte lines
+constexpr int kUnroll = 4;  // edges in flight per lane
 
 struct SsspArgs {
     const int *row_ptr;
     const int *col;
     const uint32_t *w;
     uint32_t *dist;
-    int *stamp;
-    int *frontier0;
-    int *frontier1;
-    int *counts;      // ring of 3 frontier sizes
-    int *chunk_tail;  // ring of 3 grid-buffer tails
+    int *stamp;       // stamp[v] == r: v is a frontier vertex of round r
+    int *active;      // ring of 3 flags (stride kPad): round r has a frontier
+    int *chunk_tail;  // ring of 3 grid-buffer tails (stride kPad)
     int4 *chunks;     // grid consolidation buffer: (u, begin, end, 0)
     long long chunk_cap;
     int n;
@@ -48,21 +50,7 @@ struct SsspArgs {
     int *host_ring;
     DevStats *stats;
     int want_stats;
-    GridBarrier *bar;
-    int bar_blocks;
 };
-
-__device__ __forceinline__ int *frontier_of(const SsspArgs &a, int r) { return (r & 1) ? a.frontier1 : a.frontier0; }
-
-// One relaxation; true when v must join the next frontier (first improvement
-// of v in this round).
-__device__ __forceinline__ bool relax_one(const SsspArgs &a, int v, uint32_t nd, int next)
-{
-    if (nd >= a.dist[v]) return false;  // a stale read is only ever too high
-    uint32_t old = atomic_min_dev(&a.dist[v], nd);
-    if (nd >= old) return false;
-    return atomic_exch_dev(&a.stamp[v], next) != next;
-}
 
 __device__ __forceinline__ uint32_t add_sat(uint32_t du, uint32_t w)
 {
@@ -70,28 +58,61 @@ __device__ __forceinline__ uint32_t add_sat(uint32_t du, uint32_t w)
     return s < du ? kInf : s;
 }
 
-// Inline "work" of Fig. 1(b): the lane relaxes edges [beg, end) of its vertex.
-__device__ __forceinline__ void relax_lane(const SsspArgs &a, int beg, int end, uint32_t du, int *fout,
-                                           int *cnt, int next)
+// Relaxes edge e of a vertex at distance du: atomicMin on dist[v]; a vertex
+// that improved is stamped into the next round's frontier.  The plain read of
+// dist[v] filters most edges; a stale read is only ever too high, so it can
+// cost an extra atomic but never hide an improvement.
+__device__ __forceinline__ bool relax_loaded(const SsspArgs &a, int v, uint32_t nd, uint32_t dv, int next)
 {
-    for (int e = beg; e < end; ++e) {
-        int v = a.col[e];
-        bool enq = relax_one(a, v, add_sat(du, a.w[e]), next);
-        int slot = wave_reserve(enq, cnt);
-        if (enq) fout[slot] = v;
+    if (nd >= dv) return false;
+    uint32_t old = atomic_min_dev(&a.dist[v], nd);
+    if (nd >= old) return false;
+    a.stamp[v] = next;
+    return true;
+}
+
+// kUnroll edges per lane at once: e_k = first + k * stride (valid while < end).
+// Loads are issued for all k before any relaxation, for memory-level parallelism.
+__device__ __forceinline__ bool relax_batch(const SsspArgs &a, int first, int stride, int end, uint32_t du,
+                                            int next)
+{
+    int v[kUnroll];
+    uint32_t wt[kUnroll], dv[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+        const int e = first + k * stride;
+        const bool ok = e < end;
+        v[k] = ok ? a.col[e] : -1;
+        wt[k] = ok ? a.w[e] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k)
+        if (v[k] >= 0) any |= relax_loaded(a, v[k], add_sat(du, wt[k]), dv[k], next);
+    return any;
+}
+
+// Inline "work" of Fig. 1(b): the lane relaxes edges [beg, end) of its vertex.
+__device__ __forceinline__ bool relax_lane(const SsspArgs &a, int beg, int end, uint32_t du, int next)
+{
+    bool any = false;
+    for (int e = beg; e < end; e += kUnroll) any |= relax_batch(a, e, 1, end, du, next);
+    return any;
 }
 
 // The wave cooperatively relaxes edges [beg, end) of one vertex (uniform arguments).
-__device__ __forceinline__ void relax_wave(const SsspArgs &a, int beg, int end, uint32_t du, int *fout, int *cnt,
-                                           int next)
+__device__ __forceinline__ bool relax_wave(const SsspArgs &a, int beg, int end, uint32_t du, int next)
 {
-    for (int e = beg + lane_id(); e < end; e += kWave) {
-        int v = a.col[e];
-        bool enq = relax_one(a, v, add_sat(du, a.w[e]), next);
-        int slot = wave_reserve(enq, cnt);
-        if (enq) fout[slot] = v;
-    }
+    bool any = false;
+    for (int b = beg; b < end; b += kWave * kUnroll) any |= relax_batch(a, b + lane_id(), kWave, end, du, next);
+    return any;
+}
+
+__device__ __forceinline__ void mark_active(const SsspArgs &a, int r, bool any)
+{
+    if (__ballot(any) && lane_id() == 0) a.active[((r + 1) % 3) * kPad] = 1;
 }
 
 template <int BLOCK>
@@ -100,25 +121,31 @@ struct BlockBuf {
     uint32_t du[BLOCK];
     int pre[BLOCK + 1];
     int scan_tmp[2 * (BLOCK / kWave)];
+    int base;
 };
 
-// Parent phase of round r over the whole frontier (grid-stride windows of
-// BLOCK items; every thread of a block runs the same number of windows).
+// Parent kernel of round r: thread i takes vertex i (Fig. 1(b)); the vertices
+// stamped r form the frontier.  Grid-stride windows of BLOCK vertices; every
+// thread of a block runs the same number of windows.
 template <int MODE, int BLOCK>
-__device__ void parent_phase(const SsspArgs &a, int r, int count)
+__global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
 {
-    const int *fin = frontier_of(a, r);
-    int *fout = frontier_of(a, r + 1);
-    int *cnt = &a.counts[(r + 1) % 3];
+    const int act = a.active[(r % 3) * kPad];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.active[((r + 2) % 3) * kPad] = 0;
+        if (MODE == WC_GRID) a.chunk_tail[((r + 1) % 3) * kPad] = 0;
+        store_system(&a.host_ring[r % kHostRing], act);
+    }
+    if (!act) return;
     const int next = r + 1;
     const int lane = lane_id();
-    for (int base = blockIdx.x * BLOCK; base < count; base += gridDim.x * BLOCK) {
-        const int i = base + threadIdx.x;
-        const bool valid = i < count;
-        int u = 0, beg = 0, end = 0;
+    StatAcc acc;
+    for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {
+        const int u = base + threadIdx.x;
+        const bool member = u < a.n && a.stamp[u] == r;
+        int beg = 0, end = 0;
         uint32_t du = 0;
-        if (valid) {
-            u = fin[i];
+        if (member) {
             beg = a.row_ptr[u];
             end = a.row_ptr[u + 1];
             du = a.dist[u];
@@ -126,16 +153,13 @@ __device__ void parent_phase(const SsspArgs &a, int r, int count)
         const int deg = end - beg;
         const bool heavy = MODE != WC_FLAT && deg > a.threshold;
         if (a.want_stats) {
-            int s = wave_sum_i(deg);
-            uint64_t hm = __ballot(heavy);
-            if (lane == 0) {
-                atomic_add_dev(&a.stats->edges_processed, (unsigned long long)s);
-                atomic_add_dev(&a.stats->items_buffered, (unsigned long long)__builtin_popcountll(hm));
-                if (MODE == WC_WAVE && hm) atomic_add_dev(&a.stats->dispatches, 1ull);
-            }
+            acc.edges += deg;
+            acc.buffered += heavy ? deg : 0;
+            acc.items += heavy ? 1 : 0;
+            if (MODE == WC_WAVE && __ballot(heavy) && lane == 0) acc.dispatches += 1;
         }
         // work: light items relax inline
-        relax_lane(a, beg, heavy ? beg : end, du, fout, cnt, next);
+        bool any = relax_lane(a, beg, heavy ? beg : end, du, next);
 
         if constexpr (MODE == WC_WAVE) {
             // insert_buffer = ballot; the mask is the wave's buffer; no barrier needed
@@ -143,7 +167,7 @@ __device__ void parent_phase(const SsspArgs &a, int r, int count)
             while (mask) {
                 int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                relax_wave(a, readlane(beg, b), readlane(end, b), readlane_u(du, b), fout, cnt, next);
+                any |= relax_wave(a, readlane(beg, b), readlane(end, b), readlane_u(du, b), next);
             }
         } else if constexpr (MODE == WC_BLOCK) {
             __shared__ BlockBuf<BLOCK> sb;
@@ -156,24 +180,43 @@ __device__ void parent_phase(const SsspArgs &a, int r, int count)
             }
             if (threadIdx.x == 0) {
                 sb.pre[nb] = total;
-                if (a.want_stats && nb) atomic_add_dev(&a.stats->dispatches, 1ull);
+                if (a.want_stats && nb) acc.dispatches += 1;
             }
             __syncthreads();  // the "synchronize" between inserts and the child
-            if (nb) {
-                int it = 0;
-                for (int j = threadIdx.x; j < total; j += BLOCK) {
-                    while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
-                    int e = sb.beg[it] + (j - sb.pre[it]);
-                    int v = a.col[e];
-                    bool enq = relax_one(a, v, add_sat(sb.du[it], a.w[e]), next);
-                    int slot = wave_reserve(enq, cnt);
-                    if (enq) fout[slot] = v;
+            // the block relaxes the concatenated edge ranges, kUnroll edges per
+            // thread in flight: flattened index j -> (item, edge) by a cursor
+            int it = 0;
+            for (int j0 = threadIdx.x; j0 < total; j0 += BLOCK * kUnroll) {
+                int v[kUnroll];
+                uint32_t nd[kUnroll], dv[kUnroll];
+#pragma unroll
+                for (int q = 0; q < kUnroll; ++q) {
+                    const int j = j0 + q * BLOCK;
+                    v[q] = -1;
+                    nd[q] = 0;
+                    if (j < total) {
+                        while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
+                        const int e = sb.beg[it] + (j - sb.pre[it]);
+                        v[q] = a.col[e];
+                        nd[q] = add_sat(sb.du[it], a.w[e]);
+                    }
                 }
+#pragma unroll
+                for (int q = 0; q < kUnroll; ++q) dv[q] = v[q] >= 0 ? a.dist[v[q]] : 0u;
+#pragma unroll
+                for (int q = 0; q < kUnroll; ++q)
+                    if (v[q] >= 0) any |= relax_loaded(a, v[q], nd[q], dv[q], next);
             }
             __syncthreads();  // LDS buffer is reused by the next window
         } else if constexpr (MODE == WC_GRID) {
+            __shared__ int s_tmp[2 * (BLOCK / kWave)];
+            __shared__ int s_base;
             const int nch = heavy ? (deg + a.chunk - 1) / a.chunk : 0;
-            const int slot = wave_reserve_n(nch, &a.chunk_tail[r % 3]);
+            int excl, d0, tot, d1;
+            block_scan2<BLOCK>(nch, 0, s_tmp, excl, d0, tot, d1);
+            if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
+            __syncthreads();
+            const int slot = s_base + excl;
             if (heavy) {
                 for (int c = 0; c < nch; ++c) {
                     int cb = beg + c * a.chunk;
@@ -183,36 +226,40 @@ __device__ void parent_phase(const SsspArgs &a, int r, int count)
                     } else {
                         // buffer full: this chunk is processed inline (fallback)
                         a.stats->overflowed = 1;
-                        relax_lane(a, cb, ce, du, fout, cnt, next);
+                        any |= relax_lane(a, cb, ce, du, next);
                     }
                 }
             }
+            __syncthreads();  // s_base is rewritten by the next window
         }
+        mark_active(a, r, any);
     }
+    if (a.want_stats) stat_flush(a.stats, acc);
 }
 
 // Consolidated child of grid-level consolidation: one wave per chunk, chunks
 // fetched grid-stride until the buffer is exhausted (moldable).
 template <int BLOCK>
-__device__ void drain_phase(const SsspArgs &a, int r)
+__global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
 {
-    const int tail = a.chunk_tail[r % 3];
+    if (!a.active[(r % 3) * kPad]) return;
+    const int tail = a.chunk_tail[(r % 3) * kPad];
     const int total = (long long)tail < a.chunk_cap ? tail : (int)a.chunk_cap;
-    int *fout = frontier_of(a, r + 1);
-    int *cnt = &a.counts[(r + 1) % 3];
     const int next = r + 1;
     const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
     const int nw = gridDim.x * (BLOCK / kWave);
     if (a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0)
-        atomic_add_dev(&a.stats->dispatches, 1ull);
+        atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
+    bool any = false;
     for (int c = gw; c < total; c += nw) {
         int4 d = a.chunks[c];
         int u = __builtin_amdgcn_readfirstlane(d.x);
         int cb = __builtin_amdgcn_readfirstlane(d.y);
         int ce = __builtin_amdgcn_readfirstlane(d.z);
         uint32_t du = a.dist[u];
-        relax_wave(a, cb, ce, du, fout, cnt, next);
+        any |= relax_wave(a, cb, ce, du, next);
     }
+    mark_active(a, r, any);
 }
 
 __global__ void sssp_init(SsspArgs a, int src)
@@ -222,91 +269,27 @@ __global__ void sssp_init(SsspArgs a, int src)
         a.dist[i] = i == src ? 0u : kInf;
         a.stamp[i] = i == src ? 0 : -1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.frontier0[0] = src;
-        a.counts[0] = 1;
-        a.counts[1] = 0;
-        a.counts[2] = 0;
-        a.chunk_tail[0] = a.chunk_tail[1] = a.chunk_tail[2] = 0;
-        a.bar->count = a.bar_blocks;
-        a.bar->generation = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 3) {
+        a.active[threadIdx.x * kPad] = threadIdx.x == 0 ? 1 : 0;
+        a.chunk_tail[threadIdx.x * kPad] = 0;
     }
-}
-
-template <int MODE, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
-{
-    const int count = a.counts[r % 3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.counts[(r + 2) % 3] = 0;
-        if (MODE == WC_GRID) a.chunk_tail[(r + 1) % 3] = 0;
-        store_system(&a.host_ring[r % kHostRing], count);
-    }
-    if (count == 0) return;
-    parent_phase<MODE, BLOCK>(a, r, count);
-}
-
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
-{
-    if (a.counts[r % 3] == 0) return;
-    drain_phase<BLOCK>(a, r);
-}
-
-// Persistent driver: every round in one co-resident launch; the grid barrier
-// of Sec. IV.E separates inserts from the drain and one round from the next.
-template <int MODE, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void sssp_persistent(SsspArgs a, int max_rounds)
-{
-    const int nb = gridDim.x;
-    int r = 0;
-    for (; r < max_rounds; ++r) {
-        const int count = atomic_load_dev(&a.counts[r % 3]);
-        if (count == 0) break;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.counts[(r + 2) % 3] = 0;
-            if (MODE == WC_GRID) a.chunk_tail[(r + 1) % 3] = 0;
-        }
-        parent_phase<MODE, BLOCK>(a, r, count);
-        if (!grid_barrier(a.bar, nb)) {
-            a.stats->timed_out = 1;
-            return;
-        }
-        if constexpr (MODE == WC_GRID) {
-            drain_phase<BLOCK>(a, r);
-            if (!grid_barrier(a.bar, nb)) {
-                a.stats->timed_out = 1;
-                return;
-            }
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.stats->rounds = r;
 }
 
 // ---- host side --------------------------------------------------------------------------------
 
-template <int MODE, int BLOCK>
-struct SsspKernels {
-    static const void *round() { return reinterpret_cast<const void *>(&sssp_round<MODE, BLOCK>); }
-    static const void *drain() { return reinterpret_cast<const void *>(&sssp_drain<BLOCK>); }
-    static const void *persistent() { return reinterpret_cast<const void *>(&sssp_persistent<MODE, BLOCK>); }
-};
-
 struct KernelSet {
-    const void *round, *drain, *persistent;
+    const void *round, *drain;
 };
 
 template <int BLOCK>
 KernelSet pick_block(wc_mode mode)
 {
+    const void *drain = reinterpret_cast<const void *>(&sssp_drain<BLOCK>);
     switch (mode) {
-    case WC_FLAT: return {SsspKernels<WC_FLAT, BLOCK>::round(), nullptr, SsspKernels<WC_FLAT, BLOCK>::persistent()};
-    case WC_WAVE: return {SsspKernels<WC_WAVE, BLOCK>::round(), nullptr, SsspKernels<WC_WAVE, BLOCK>::persistent()};
-    case WC_BLOCK:
-        return {SsspKernels<WC_BLOCK, BLOCK>::round(), nullptr, SsspKernels<WC_BLOCK, BLOCK>::persistent()};
-    default:
-        return {SsspKernels<WC_GRID, BLOCK>::round(), SsspKernels<WC_GRID, BLOCK>::drain(),
-                SsspKernels<WC_GRID, BLOCK>::persistent()};
+    case WC_FLAT: return {reinterpret_cast<const void *>(&sssp_round<WC_FLAT, BLOCK>), nullptr};
+    case WC_WAVE: return {reinterpret_cast<const void *>(&sssp_round<WC_WAVE, BLOCK>), nullptr};
+    case WC_BLOCK: return {reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK>), nullptr};
+    default: return {reinterpret_cast<const void *>(&sssp_round<WC_GRID, BLOCK>), drain};
     }
 }
 
@@ -349,12 +332,14 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     Config cfg;
     int block = (tune && tune->block_threads > 0) ? tune->block_threads : 256;
     KernelSet ks = pick(mode, block);
-    int resident = resident_blocks(ctx, ks.persistent, block);
+    int resident = resident_blocks(ctx, ks.round, block);
     wc_status st = resolve_tune(ctx, "sssp", mode, tune, resident, &cfg);
     if (st != WC_OK) return st;
+    if (cfg.driver == 1)
+        return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
     if (cfg.block != block) {
         ks = pick(mode, cfg.block);
-        resident = resident_blocks(ctx, ks.persistent, cfg.block);
+        resident = resident_blocks(ctx, ks.round, cfg.block);
     }
     const long long n = g->n, m = g->m;
     const int chunk = kWave * cfg.items_per_lane;
@@ -362,7 +347,7 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     // ceil(deg / chunk) chunks, so n + m / chunk + 1 entries never overflow.
     long long cap_full = n + m / chunk + 1;
     long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    size_t need = padded(n * 4) * 3 + padded(3 * 4) * 2 + padded(cap * 16) + padded(sizeof(GridBarrier));
+    size_t need = padded(n * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     SsspArgs a;
@@ -371,12 +356,9 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     a.w = w;
     a.dist = dist;
     a.stamp = pool_take<int>(ctx, n);
-    a.frontier0 = pool_take<int>(ctx, n);
-    a.frontier1 = pool_take<int>(ctx, n);
-    a.counts = pool_take<int>(ctx, 3);
-    a.chunk_tail = pool_take<int>(ctx, 3);
+    a.active = pool_take<int>(ctx, 3 * kPad);
+    a.chunk_tail = pool_take<int>(ctx, 3 * kPad);
     a.chunks = pool_take<int4>(ctx, cap);
-    a.bar = pool_take<GridBarrier>(ctx, 1);
     a.chunk_cap = cap;
     a.n = (int)n;
     a.threshold = cfg.threshold;
@@ -385,8 +367,9 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     a.stats = ctx->dstats;
     a.want_stats = stats != nullptr;
 
-    const int grid = std::max(1, std::min(cfg.grid, resident));
-    a.bar_blocks = grid;  // the barrier counter starts at the number of blocks
+    const int windows = (int)((n + cfg.block - 1) / cfg.block);
+    const int grid = std::max(1, std::min(std::min(cfg.grid, resident), windows));
+    const int dgrid = std::max(1, std::min(cfg.grid, resident));
     st = begin_call(ctx, stream, stats);
     if (st != WC_OK) return st;
     int init_grid = (int)std::min<long long>((n + 255) / 256, 4096);
@@ -396,33 +379,19 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
                     stream);
         if (st != WC_OK) return st;
     }
-
-    int rounds = 0;
-    if (cfg.driver == 1) {
-        return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
-        int max_rounds = (int)std::min<long long>(n + 1, 0x7fffffff);
-        void *args[] = {&a, &max_rounds};
-        WC_HIP(hipLaunchCooperativeKernel(ks.persistent, dim3(grid), dim3(cfg.block), args, 0, stream));
-        st = end_call(ctx, stream, stats, -1, cfg.fail_on_overflow);
-        if (stats && st == WC_OK) {
-            int r = 0;
-            WC_HIP(hipMemcpy(&r, &ctx->dstats->rounds, sizeof(int), hipMemcpyDeviceToHost));
-            stats->rounds = r;
-        }
-        return st;
-    }
     // Relaunch driver: keep `window` rounds in flight; each round kernel
-    // publishes its input size to pinned host memory, and the first empty round
-    // ends the loop (later rounds already enqueued find empty frontiers).
+    // publishes whether its frontier is non-empty to pinned host memory, and the
+    // first empty round ends the loop (rounds already enqueued behind it find
+    // no frontier and return at once).
     const int window = 4;
-    int launched = 0;
+    int rounds = 0, launched = 0;
     for (;;) {
         while (launched < rounds + window) {
             clear_round_slot(ctx, launched);
             void *args[] = {&a, &launched};
             st = launch(ctx, round_name(mode), ks.round, dim3(grid), dim3(cfg.block), args, stream);
             if (st == WC_OK && mode == WC_GRID)
-                st = launch(ctx, "sssp_drain", ks.drain, dim3(grid), dim3(cfg.block), args, stream);
+                st = launch(ctx, "sssp_drain", ks.drain, dim3(dgrid), dim3(cfg.block), args, stream);
             if (st != WC_OK) return st;
             ++launched;
         }

@@ -1,0 +1,47 @@
+// Per-call work counters: each thread accumulates in registers; at the end of a
+// kernel the block reduces them (wave sums, then LDS) and adds them to one
+// replica of the device counters with a single atomic per counter.
+#pragma once
+
+#include "wc_device.h"
+#include "wc_internal.h"
+
+namespace wc {
+
+struct StatAcc {
+    unsigned long long items = 0, dispatches = 0, edges = 0, buffered = 0;
+};
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// All threads of the block must call this (it contains barriers).
+__device__ __forceinline__ void stat_flush(DevStats *s, const StatAcc &acc)
+{
+    __shared__ unsigned long long sh[4];
+    if (threadIdx.x < 4) sh[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long v[4] = {acc.items, acc.dispatches, acc.edges, acc.buffered};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = wave_sum_u64(v[k]);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (v[k]) atomicAdd(&sh[k], v[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && sh[threadIdx.x]) {
+        StatRep &r = s->rep[blockIdx.x % kStatReps];
+        unsigned long long *dst = threadIdx.x == 0   ? &r.items_buffered
+                                  : threadIdx.x == 1 ? &r.dispatches
+                                  : threadIdx.x == 2 ? &r.edges_processed
+                                                     : &r.edges_buffered;
+        atomic_add_dev(dst, sh[threadIdx.x]);
+    }
+}
+
+}  // namespace wc

@@ -33,6 +33,7 @@
 #include "wc_block.h"
 #include "wc_device.h"
 #include "wc_internal.h"
+#include "wc_stats.h"
 
 namespace wc {
 namespace {
@@ -123,7 +124,7 @@ __global__ void tree_init_levels_flat(TreeArgs a)
 // Top-down step of level l: children of the level's buffered nodes.  Internal
 // children are inserted into level l+1's buffer, leaves get the leaf work.
 template <int MODE, int BLOCK>
-__device__ void level_down(const TreeArgs &a, int l, int start, int count)
+__device__ void level_down(const TreeArgs &a, int l, int start, int count, StatAcc &acc)
 {
     const int out_base = start + count;
     int *cnt_next = &a.lvl_count[l + 1];
@@ -133,9 +134,7 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count)
         for (int it = gw; it < count; it += nw) {
             int4 d = a.items[start + it];
             const int cb = __builtin_amdgcn_readfirstlane(d.y), ce = __builtin_amdgcn_readfirstlane(d.z);
-            if (a.want_stats && lane_id() == 0) {
-                atomic_add_dev(&a.stats->edges_processed, (unsigned long long)(ce - cb));
-            }
+            if (a.want_stats && lane_id() == 0) acc.edges += ce - cb;
             for (int b = cb; b < ce; b += kWave) {
                 const int e = b + lane_id();
                 int c = -1, f = 0;
@@ -146,10 +145,7 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count)
                 }
                 const int nch = f > 0 ? (f + a.chunk - 1) / a.chunk : 0;
                 const int slot = wave_reserve_n(nch, cnt_next);
-                if (a.want_stats) {
-                    uint64_t m = __ballot(f > 0);
-                    if (lane_id() == 0 && m) atomic_add_dev(&a.stats->items_buffered, (unsigned long long)__builtin_popcountll(m));
-                }
+                if (a.want_stats) acc.items += f > 0 ? 1 : 0;
                 if (nch > 0) {
                     const int c0 = a.child_ptr[c];
                     for (int k = 0; k < nch; ++k) {
@@ -163,7 +159,7 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count)
         for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
             const int p = a.items[start + i].x;
             const int cb = a.child_ptr[p], ce = a.child_ptr[p + 1];
-            if (a.want_stats) atomic_add_dev(&a.stats->edges_processed, (unsigned long long)(ce - cb));
+            if (a.want_stats) acc.edges += ce - cb;
             for (int e = cb; e < ce; ++e) {
                 const int c = a.child[e];
                 const bool internal = fanout(a, c) > 0;
@@ -209,10 +205,12 @@ __global__ __launch_bounds__(BLOCK) void tree_down(TreeArgs a, int l)
         a.lvl_start[l + 1] = start + count;
         a.lvl_count[l + 2] = 0;
         store_system(&a.host_ring[l % kHostRing], count);
-        if (a.want_stats && MODE == WC_GRID && count > 0) atomic_add_dev(&a.stats->dispatches, 1ull);
+        if (a.want_stats && MODE == WC_GRID && count > 0) atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
     }
     if (count == 0) return;
-    level_down<MODE, BLOCK>(a, l, start, count);
+    StatAcc acc;
+    level_down<MODE, BLOCK>(a, l, start, count, acc);
+    if (a.want_stats) stat_flush(a.stats, acc);
 }
 
 template <int MODE, int OP, int BLOCK>
@@ -227,6 +225,7 @@ template <int MODE, int OP, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void tree_levels_persistent(TreeArgs a, int max_levels)
 {
     const int nb = gridDim.x;
+    StatAcc acc;
     int l = 0;
     for (; l < max_levels; ++l) {
         const int start = atomic_load_dev(&a.lvl_start[l]), count = atomic_load_dev(&a.lvl_count[l]);
@@ -234,9 +233,9 @@ __global__ __launch_bounds__(BLOCK) void tree_levels_persistent(TreeArgs a, int 
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.lvl_start[l + 1] = start + count;
             a.lvl_count[l + 2] = 0;
-            if (a.want_stats && MODE == WC_GRID) atomic_add_dev(&a.stats->dispatches, 1ull);
+            if (a.want_stats && MODE == WC_GRID) atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
         }
-        level_down<MODE, BLOCK>(a, l, start, count);
+        level_down<MODE, BLOCK>(a, l, start, count, acc);
         if (!grid_barrier(a.bar, nb)) {
             a.stats->timed_out = 1;
             return;
@@ -251,6 +250,7 @@ __global__ __launch_bounds__(BLOCK) void tree_levels_persistent(TreeArgs a, int 
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.stats->rounds = levels;
+    if (a.want_stats) stat_flush(a.stats, acc);
 }
 
 // ---------------------------------------------------------------- packet queue (wave, block)
@@ -337,7 +337,7 @@ __device__ __forceinline__ int gtid() { return G > kWave ? (int)threadIdx.x : la
 // Flush the group's buffer as packets of at most G nodes (one consolidated
 // dispatch each).
 template <int G>
-__device__ void flush_buffer(const TreeArgs &a, QueueLds<G> &s)
+__device__ void flush_buffer(const TreeArgs &a, QueueLds<G> &s, StatAcc &acc)
 {
     const int cnt = s.buf_cnt;
     if (cnt == 0) return;
@@ -357,7 +357,7 @@ __device__ void flush_buffer(const TreeArgs &a, QueueLds<G> &s)
             const int slot = atomic_add_dev(a.pq_tail, 1);
             __hip_atomic_store(&a.pq[slot], ((long long)base << 32) | (long long)k, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
-            if (a.want_stats) atomic_add_dev(&a.stats->items_buffered, (unsigned long long)k);
+            if (a.want_stats) acc.items += k;
         }
         gsync<G>();
     }
@@ -376,6 +376,7 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
     const int gid = G > kWave ? 0 : (int)threadIdx.x / kWave;
     QueueLds<G> &s = lds[gid];
     const int t = gtid<G>();
+    StatAcc acc;
     if (t == 0) {
         s.buf_cnt = 0;
         s.buf_work = 0;
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
             s.pk_start = pk >= 0 ? (int)(pk >> 32) : 0;
             s.pk_count = pk >= 0 ? (int)(pk & 0xffffffff) : 0;
             if (got >= 0 && pk < 0) s.flag = -1;
-            if (a.want_stats && s.flag >= 0) atomic_add_dev(&a.stats->dispatches, 1ull);
+            if (a.want_stats && s.flag >= 0) acc.dispatches += 1;
         }
         gsync<G>();
         if (s.flag < 0) break;
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
         }
         if (t == 0) s.pk_pre[pcount] = total;
         gsync<G>();
-        if (a.want_stats && t == 0) atomic_add_dev(&a.stats->edges_processed, (unsigned long long)total);
+        if (a.want_stats && t == 0) acc.edges += total;
         int k = 0;
         for (int jb = 0; jb < total; jb += G) {
             const int j = jb + t;
@@ -488,13 +489,14 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
                 complete_upward<OP>(a, c, 0);
             }
             gsync<G>();
-            if (s.buf_cnt >= G || s.buf_work >= a.work_cap) flush_buffer<G>(a, s);
+            if (s.buf_cnt >= G || s.buf_work >= a.work_cap) flush_buffer<G>(a, s, acc);
         }
-        flush_buffer<G>(a, s);
+        flush_buffer<G>(a, s, acc);
         // this dispatch is finished (its own follow-up packets are already counted)
         if (t == 0) __hip_atomic_fetch_add(a.outstanding, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         gsync<G>();
     }
+    if (a.want_stats) stat_flush(a.stats, acc);
 }
 
 // ---------------------------------------------------------------- host side

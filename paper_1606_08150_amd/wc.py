@@ -53,7 +53,8 @@ class Tune(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("overflowed", ctypes.c_int32), ("items_buffered", ctypes.c_int64),
-                ("dispatches", ctypes.c_int64), ("edges_processed", ctypes.c_int64), ("ms", ctypes.c_float)]
+                ("dispatches", ctypes.c_int64), ("edges_processed", ctypes.c_int64),
+                ("edges_buffered", ctypes.c_int64), ("ms", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
