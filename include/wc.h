@@ -157,6 +157,27 @@ wc_status wc_tree_descendants(wc_ctx *ctx, const wc_tree *t, int32_t *desc, wc_m
 wc_status wc_tree_height(wc_ctx *ctx, const wc_tree *t, int32_t *height, wc_mode mode, const wc_tune *tune,
                          hipStream_t stream, wc_stats *stats);
 
+/* Batched SSSP: `count` independent instances in one launch sequence
+ * (spec batching pattern; each instance is the problem of wc_sssp).
+ * graphs, w, src, dist are HOST arrays of `count` entries whose pointers are
+ * device arrays of each instance (dist[i] has graphs[i].n entries and is written
+ * entirely).  modes/tunes (nullable: grid mode, defaults) give each instance
+ * its own consolidation granularity, threshold and items_per_lane, as chosen
+ * per size bucket by an autotuner; block_threads must be equal across
+ * instances.  The instances share one grid: every round, one parent kernel
+ * scans all instances' vertices and each heavy vertex goes to its instance's
+ * wave, block or global buffer; the global buffer consolidates the heavy work
+ * of all grid-mode instances into one child.
+ * graph_rounds > 0: that many rounds are captured once into a HIP graph (its
+ * kernels return at once after convergence) and replayed as one graph launch
+ * on later calls with the same shape; rounds beyond it run as ordinary
+ * launches.  graph_rounds = 0: ordinary launches only.  Results are identical
+ * to wc_sssp on each instance.  The call returns after the device has
+ * published whether the rounds converged. */
+wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *graphs, const uint32_t *const *w,
+                        const int32_t *src, uint32_t *const *dist, const wc_mode *modes, const wc_tune *tunes,
+                        int32_t graph_rounds, hipStream_t stream, wc_stats *stats);
+
 /* Per-kernel timing.  When enabled, every kernel the library launches on a
  * context is bracketed by two HIP events recorded on the launch stream, so its
  * device execution time can be read back afterwards.  Enabling or disabling

@@ -6,6 +6,7 @@
 // overhead as the main cost of the default and halloc allocators, Sec. V.A).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cstring>
@@ -58,6 +59,11 @@ wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream)
     WC_HIP(hipStreamSynchronize(stream));
     WC_HIP(hipDeviceSynchronize());
     size_t grow = ctx->pool_bytes * 2;
+    if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+        ctx->graph_key = 0;
+    }
     return pool_alloc(ctx, bytes > grow ? bytes : grow);
 }
 
@@ -202,6 +208,27 @@ wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds,
     return WC_OK;
 }
 
+wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t stream)
+{
+    if (ctx->staging_pending) {
+        WC_HIP(hipEventSynchronize(ctx->staging_done));
+        ctx->staging_pending = false;
+    }
+    if (bytes > ctx->staging_bytes) {
+        if (ctx->staging) WC_HIP(hipHostFree(ctx->staging));
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        size_t sz = std::max<size_t>(bytes, 1 << 16);
+        WC_HIP(hipHostMalloc(&ctx->staging, sz, hipHostMallocDefault));
+        ctx->staging_bytes = sz;
+    }
+    std::memcpy(ctx->staging, src, bytes);
+    WC_HIP(hipMemcpyAsync(dst, ctx->staging, bytes, hipMemcpyHostToDevice, stream));
+    WC_HIP(hipEventRecord(ctx->staging_done, stream));
+    ctx->staging_pending = true;
+    return WC_OK;
+}
+
 void clear_round_slot(wc_ctx *ctx, int r)
 {
     reinterpret_cast<volatile int *>(ctx->host_ring)[r % kHostRing] = -1;
@@ -301,6 +328,10 @@ wc_status wc_ctx_create(int device, size_t pool_bytes, wc_ctx **out)
         if (e == hipSuccess) e = hipMalloc(&ctx->dstats, sizeof(DevStats));
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_start);
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_stop);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->graph_ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
         if (e != hipSuccess) st = hip_fail(e, "context setup");
     }
     if (st != WC_OK) {
@@ -364,6 +395,12 @@ wc_status wc_ctx_destroy(wc_ctx *ctx)
     if (ctx->dstats) (void)hipFree(ctx->dstats);
     if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
     if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
+    if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+    if (ctx->graph_ready) (void)hipEventDestroy(ctx->graph_ready);
+    if (ctx->graph_done) (void)hipEventDestroy(ctx->graph_done);
     (void)hipGetLastError();
     delete ctx;
     return WC_OK;

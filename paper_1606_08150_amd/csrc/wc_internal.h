@@ -60,6 +60,16 @@ struct wc_ctx {
     int timing = 0;
     std::vector<wc_kernel_record> records;
     std::vector<hipEvent_t> spare_events;
+    // pinned staging buffer for small host-to-device descriptor uploads
+    void *staging = nullptr;
+    size_t staging_bytes = 0;
+    hipEvent_t staging_done = nullptr;
+    bool staging_pending = false;
+    // batched SSSP: capture stream and the last instantiated round graph
+    hipStream_t capture_stream = nullptr;
+    hipEvent_t graph_ready = nullptr, graph_done = nullptr;
+    unsigned long long graph_key = 0;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace wc {
@@ -112,6 +122,10 @@ wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats);
 // Records the stop event; fills `stats` (synchronizing) when non-NULL; reports
 // overflow / timeout flags.
 wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow);
+
+// Copies `bytes` from host memory to device memory `dst` on `stream` through
+// the context's pinned staging buffer (waits for the previous staged copy).
+wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t stream);
 
 // Waits (bounded) until a kernel published the count of round `r` to the host ring.
 wc_status wait_round_count(wc_ctx *ctx, int r, int *count);

@@ -22,6 +22,7 @@ STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: 
 
 # C-ABI symbols declared in include/wc.h
 EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_spmv", "wc_tree_descendants", "wc_tree_height",
+           "wc_sssp_batch",
            "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_last_error", "wc_version", "wc_per_buffer_size",
            "wc_kc_config", "wc_default_tune")
 
@@ -85,6 +86,9 @@ def load_library():
         fn = getattr(lib, name)
         fn.restype = c.c_int
         fn.argtypes = [vp, c.POINTER(CTree), vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_sssp_batch.restype = c.c_int
+    lib.wc_sssp_batch.argtypes = [vp, c.c_int32, c.POINTER(CCsr), c.POINTER(vp), c.POINTER(c.c_int32), c.POINTER(vp),
+                                  c.POINTER(c.c_int), c.POINTER(Tune), c.c_int32, vp, c.POINTER(Stats)]
     lib.wc_ctx_set_timing.restype = c.c_int
     lib.wc_ctx_set_timing.argtypes = [vp, c.c_int]
     lib.wc_ctx_kernel_stats.restype = c.c_int
@@ -240,6 +244,25 @@ class Context:
                                       dist.data_ptr(), _mode(mode), ctypes.byref(tune) if tune else None,
                                       _stream_ptr(stream), ctypes.byref(st) if st else None))
         return (dist, st.as_dict()) if stats else dist
+
+    def sssp_batch(self, graphs, weights, sources, modes=None, tunes=None, outs=None, graph_rounds: int = 0,
+                   stream=None, stats: bool = False):
+        """Batched SSSP over independent instances (lists of DeviceCSR, weight
+        tensors, source ints; optional per-instance modes and Tune structs)."""
+        k = len(graphs)
+        outs = outs if outs is not None else [torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+                                              for g in graphs]
+        cg = (CCsr * k)(*[g.c() for g in graphs])
+        vp = ctypes.c_void_p
+        cw = (vp * k)(*[w.data_ptr() if g.m else None for g, w in zip(graphs, weights)])
+        cs = (ctypes.c_int32 * k)(*[int(s) for s in sources])
+        cd = (vp * k)(*[o.data_ptr() for o in outs])
+        cm = (ctypes.c_int * k)(*[_mode(m) for m in modes]) if modes is not None else None
+        ct = (Tune * k)(*tunes) if tunes is not None else None
+        st = Stats() if stats else None
+        _check(load_library().wc_sssp_batch(self._ptr, k, cg, cw, cs, cd, cm, ct, graph_rounds, _stream_ptr(stream),
+                                            ctypes.byref(st) if st else None))
+        return (outs, st.as_dict()) if stats else outs
 
     def spmv(self, a: DeviceCSR, val: torch.Tensor, x: torch.Tensor, mode="grid", tune: Tune | None = None,
              out: torch.Tensor | None = None, stream=None, stats: bool = False):

@@ -164,6 +164,32 @@ def random_tree(n: int, seed: int = SEED_TREE, kmax: int = 4096, alpha: float = 
     return Tree(n, parent, child_ptr, child, depth)
 
 
+# ---- batches of independent instances ----------------------------------------------------------
+
+def batch_sizes(count: int, lo_log2: float = 10.0, hi_log2: float = 18.0, seed: int = SEED_GRAPH,
+                stream: int = 300) -> np.ndarray:
+    """Vertex counts log-uniform in [2^lo, 2^hi]: n_i = floor(2^U), U uniform (one draw per instance)."""
+    r = rand_u64(seed, stream, count)
+    u = (r >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.floor(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u)).astype(np.int64)
+
+
+def batch_instances(count: int, degree: int = 16, lo_log2: float = 10.0, hi_log2: float = 18.0,
+                    seed: int = SEED_GRAPH):
+    """`count` independent R-MAT instances: instance i has n_i vertices (batch_sizes)
+    and degree * n_i edges, drawn at scale ceil(log2 n_i) with out-of-range
+    endpoints rejected; graph seed (seed, i) and weight seed (SEED_WEIGHT, i) are
+    folded into one 64-bit seed each.  Returns a list of (CSR, weights)."""
+    sizes = batch_sizes(count, lo_log2, hi_log2, seed)
+    out = []
+    for i, n in enumerate(sizes.tolist()):
+        gseed = int(_load().syn_rand(seed, 301, i))
+        wseed = int(_load().syn_rand(SEED_WEIGHT, 302, i))
+        g = rmat_csr_n(int(n), int(degree * n), gseed)
+        out.append((g, weights(g.m, wseed)))
+    return out
+
+
 # ---- small hand-built shapes (tests and edge cases) -------------------------------------------
 
 def tree_from_parent(parent) -> Tree:
