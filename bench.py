@@ -45,6 +45,10 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched SSSP section")
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--batch-reps", type=int, default=10)
+    p.add_argument("--no-serve", action="store_true", help="skip the continuous-batching serving section")
+    p.add_argument("--serve-requests", type=int, default=4000, help="requests per arrival rate")
+    p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
+    p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
                    help="first run a plain device-to-device copy of this many MiB three times (a known-size "
                         "kernel for scaling hardware byte counters)")
@@ -209,6 +213,52 @@ def run_batch(args, ctx, torch, synth, wc):
             "tuned_over_heuristic": round(heur["ms_p50"] / tuned["ms_p50"], 3)}
 
 
+def run_serving(args, torch, synth, wc):
+    from paper_1606_08150_amd import serve
+    t0 = time.time()
+    sizes = synth.serving_graph_sizes(64, 14, 20)
+    dev, srcs, degs = [], [], []
+    for k, n in enumerate(sizes):
+        g, w, val, xs = synth.serving_graph(k, n, n_x=4)
+        dev.append(serve.ResidentGraph(wc.DeviceCSR.from_host(g.row_ptr, g.col),
+                                       torch.from_numpy(w.view(np.int32)).cuda(), torch.from_numpy(val).cuda(),
+                                       [torch.from_numpy(x).cuda() for x in xs]))
+        d = np.diff(g.row_ptr)
+        srcs.append(np.flatnonzero(d > 0))
+        degs.append(torch.from_numpy(d.astype(np.int64)).cuda())
+    print(f"[bench] 64 resident graphs ({sum(sizes)} vertices) ready in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    ctx = wc.Context(0)
+    reached_cache = {}
+
+    def reached(gk, src):
+        key = (gk, src)
+        if key not in reached_cache:
+            d = ctx.sssp(dev[gk].csr, dev[gk].w, src, mode="grid")
+            reached_cache[key] = int(degs[gk][d != -1].sum().item())
+        return reached_cache[key]
+
+    rows = []
+    backend = serve.GpuBackend(dev)
+    srv = serve.Server(backend, workers=args.serve_workers, max_slots=512, max_batch=64)
+    try:
+        warm = serve.poisson_requests(200, 5000.0, srcs, n_x=4, seed=1)
+        srv.run(warm)
+        for rate in [float(x) for x in args.serve_rates.split(",")]:
+            reqs = serve.poisson_requests(args.serve_requests, rate, srcs, n_x=4, seed=int(rate))
+            out = srv.run(reqs, time_limit=300)
+            edges = sum(reached(r.graph, r.arg) for r in out if r.kind == serve.SSSP)
+            row = {"rate_rps": rate, **serve.summarize(out, edges)}
+            rows.append(row)
+            print(f"[bench] serving {row}", file=sys.stderr, flush=True)
+    finally:
+        srv.close()
+        ctx.close()
+    return {"workload": "Poisson arrivals, 50% SSSP (random source with out-edges) / 50% SpMV (4 resident x "
+                        "per graph), 64 resident R-MAT graphs of 2^14..2^20 vertices, degree 16",
+            "workers": args.serve_workers, "graphs_vertices": sum(sizes), "rates": rows}
+
+
 def main():
     if "--summarize-profiles" in sys.argv:
         sp = argparse.ArgumentParser()
@@ -370,6 +420,11 @@ def main():
     if not args.no_batch:
         batch = run_batch(args, ctx, torch, synth, wc)
 
+    # ---- serving: Poisson streams of SSSP/SpMV requests over 64 resident graphs
+    serving = None
+    if not args.no_serve:
+        serving = run_serving(args, torch, synth, wc)
+
     # ---- CPU baseline: the oracle's Dijkstra on the same graph, this host
     cpu = None
     if not args.no_cpu_baseline:
@@ -411,6 +466,7 @@ def main():
         "kernels": kernels,
         "modes": modes,
         "batch": batch,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     ctx.close()

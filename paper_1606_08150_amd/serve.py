@@ -1,0 +1,292 @@
+"""Continuous-batching request server over resident graphs.
+
+Requests (SSSP from a source, or SpMV with one of the graph's resident x
+vectors) arrive over time.  The scheduler admits a waiting request as soon as
+the device-memory budget and the slot limit allow it, and hands each batch of
+admitted requests to an idle worker.  Every worker owns a libwc context and its
+own HIP stream, so batches launched while others are still on the device run
+concurrently; SSSP requests of one batch go through one wc_sssp_batch call
+(their work is consolidated across requests), SpMV requests through wc_spmv.
+Each result is the same as the request run alone (bit-identical distances;
+SpMV results bit-identical for a fixed mode and tune).
+
+Only the scheduling lives here; every request's arithmetic runs in libwc.  The
+device side is a backend object, so the scheduling can be exercised on the
+CPU with a stand-in backend.
+"""
+from __future__ import annotations
+
+import collections
+import queue
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SSSP, SPMV = 0, 1
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: int          # SSSP or SPMV
+    graph: int         # index of a resident graph
+    arg: int           # SSSP source vertex, or SpMV x-vector index
+    t_arrive: float    # seconds from the start of the run
+    nbytes: int = 0
+    t_admit: float = -1.0
+    t_start: float = -1.0
+    t_done: float = -1.0
+    out: object = None
+    error: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrive
+
+
+class Admission:
+    """Admits a request while its bytes fit the remaining budget and a slot is
+    free; a request larger than the whole budget is rejected outright."""
+
+    def __init__(self, budget_bytes: int, max_slots: int):
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.used = 0
+        self.slots = 0
+        self.peak_used = 0
+        self.peak_slots = 0
+
+    def fits_ever(self, nbytes: int) -> bool:
+        return nbytes <= self.budget
+
+    def try_admit(self, nbytes: int) -> bool:
+        if self.slots >= self.max_slots or self.used + nbytes > self.budget:
+            return False
+        self.used += nbytes
+        self.slots += 1
+        self.peak_used = max(self.peak_used, self.used)
+        self.peak_slots = max(self.peak_slots, self.slots)
+        return True
+
+    def release(self, nbytes: int):
+        self.used -= nbytes
+        self.slots -= 1
+        assert self.used >= 0 and self.slots >= 0
+
+
+def request_bytes(kind: int, n: int, m: int) -> int:
+    """Device bytes a request holds while admitted: its output plus its share
+    of the consolidation workspace (SSSP: distances, round stamps, grid chunk
+    buffer; SpMV: y plus row bins, chunks, partials and split-row entries)."""
+    if kind == SSSP:
+        return 4 * n + 4 * n + 16 * (n + m // 256 + 1)
+    return 4 * n + 16 * n + 20 * (n + m // 256 + 1) + 16 * n
+
+
+def poisson_requests(count: int, rate: float, sources_per_graph, n_x: int, seed: int, sssp_fraction: float = 0.5):
+    """Seeded request stream: exponential inter-arrival times at `rate` per
+    second, kind SSSP with probability sssp_fraction, graph uniform, SSSP source
+    uniform over the graph's vertices with out-edges, SpMV x uniform over n_x."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    kinds = np.where(rng.random(count) < sssp_fraction, SSSP, SPMV)
+    graphs = rng.integers(0, len(sources_per_graph), size=count)
+    reqs = []
+    for i in range(count):
+        g = int(graphs[i])
+        if kinds[i] == SSSP:
+            cand = sources_per_graph[g]
+            arg = int(cand[rng.integers(0, len(cand))])
+        else:
+            arg = int(rng.integers(0, n_x))
+        reqs.append(Request(i, int(kinds[i]), g, arg, float(t[i])))
+    return reqs
+
+
+@dataclass
+class ResidentGraph:
+    csr: object                # wc.DeviceCSR
+    w: object                  # int32 view of uint32 weights (device)
+    val: object                # fp32 values (device)
+    xs: list = field(default_factory=list)  # fp32 x vectors (device)
+
+    @property
+    def n(self):
+        return self.csr.n
+
+    @property
+    def m(self):
+        return self.csr.m
+
+
+class GpuBackend:
+    """libwc on one device: one context and one stream per worker."""
+
+    def __init__(self, graphs, device: int = 0, sssp_mode="grid", spmv_mode="grid"):
+        self.graphs = graphs
+        self.device = device
+        self.sssp_mode, self.spmv_mode = sssp_mode, spmv_mode
+
+    def free_bytes(self) -> int:
+        import torch
+        return int(torch.cuda.mem_get_info(self.device)[0])
+
+    def worker_state(self):
+        import torch
+        from . import wc
+        return wc.Context(self.device), torch.cuda.Stream(device=self.device)
+
+    def close_state(self, state):
+        state[0].close()
+
+    def allocate(self, r):
+        import torch
+        g = self.graphs[r.graph]
+        dt = torch.int32 if r.kind == SSSP else torch.float32
+        r.out = torch.empty(g.n, dtype=dt, device=f"cuda:{self.device}")
+
+    def execute(self, state, batch):
+        """Runs one batch on the worker's stream and waits for it."""
+        import torch
+        ctx, stream = state
+        with torch.cuda.stream(stream):
+            sssp = [r for r in batch if r.kind == SSSP]
+            if sssp:
+                gs = [self.graphs[r.graph] for r in sssp]
+                ctx.sssp_batch([g.csr for g in gs], [g.w for g in gs], [r.arg for r in sssp],
+                               modes=[self.sssp_mode] * len(sssp), outs=[r.out for r in sssp], stream=stream)
+            for r in batch:
+                if r.kind == SPMV:
+                    g = self.graphs[r.graph]
+                    ctx.spmv(g.csr, g.val, g.xs[r.arg], mode=self.spmv_mode, out=r.out, stream=stream)
+        stream.synchronize()
+
+
+class _Worker(threading.Thread):
+    def __init__(self, server, index):
+        super().__init__(daemon=True)
+        self.server = server
+        self.index = index
+        self.state = server.backend.worker_state()
+        self.inbox: queue.Queue = queue.Queue()
+
+    def run(self):
+        be = self.server.backend
+        while True:
+            batch = self.inbox.get()
+            if batch is None:
+                break
+            now = self.server.clock()
+            for r in batch:
+                r.t_start = now
+            try:
+                be.execute(self.state, batch)
+            except Exception as e:  # a failed batch must not poison the others
+                for r in batch:
+                    r.error = e
+            now = self.server.clock()
+            for r in batch:
+                r.t_done = now
+            self.server._done.put((self.index, batch))
+
+    def close(self):
+        self.inbox.put(None)
+        self.join()
+        self.server.backend.close_state(self.state)
+
+
+class Server:
+    def __init__(self, backend, workers: int = 4, budget_bytes: int | None = None, max_slots: int = 512,
+                 max_batch: int = 64, keep_outputs: bool = False):
+        self.backend = backend
+        self.max_batch = max_batch
+        self.keep_outputs = keep_outputs
+        if budget_bytes is None:
+            budget_bytes = backend.free_bytes() // 2
+        self.admission = Admission(budget_bytes, max_slots)
+        self._done: queue.Queue = queue.Queue()
+        self._t0 = time.perf_counter()
+        self.workers = [_Worker(self, i) for i in range(workers)]
+        for w in self.workers:
+            w.start()
+
+    def clock(self) -> float:
+        return time.perf_counter() - self._t0
+
+    def close(self):
+        for w in self.workers:
+            w.close()
+
+    def _complete(self, wi, batch, idle):
+        idle.add(wi)
+        for r in batch:
+            self.admission.release(r.nbytes)
+            if not self.keep_outputs:
+                r.out = None
+        return len(batch)
+
+    def run(self, requests, time_limit: float = 120.0):
+        """Serves `requests` (sorted by t_arrive) in real time and returns them with
+        admission, start and completion times filled in."""
+        for r in requests:
+            g = self.backend.graphs[r.graph]
+            r.nbytes = request_bytes(r.kind, g.n, g.m)
+            if not self.admission.fits_ever(r.nbytes):
+                raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, more than the whole budget")
+        self._t0 = time.perf_counter()
+        waiting: collections.deque = collections.deque()
+        ready: collections.deque = collections.deque()
+        nxt, done, total = 0, 0, len(requests)
+        idle = set(range(len(self.workers)))
+        while done < total:
+            now = self.clock()
+            if now > time_limit:
+                raise TimeoutError(f"served {done} of {total} requests within {time_limit} s")
+            while nxt < total and requests[nxt].t_arrive <= now:
+                waiting.append(requests[nxt])
+                nxt += 1
+            # admission, in arrival order, while memory and slots allow
+            while waiting and self.admission.try_admit(waiting[0].nbytes):
+                r = waiting.popleft()
+                r.t_admit = now
+                self.backend.allocate(r)
+                ready.append(r)
+            # batched on arrival: every idle worker takes what is ready now
+            while ready and idle:
+                wi = idle.pop()
+                batch = [ready.popleft() for _ in range(min(self.max_batch, len(ready)))]
+                self.workers[wi].inbox.put(batch)
+            # completions free memory and slots for the next admissions
+            progressed = False
+            while True:
+                try:
+                    wi, batch = self._done.get_nowait()
+                except queue.Empty:
+                    break
+                done += self._complete(wi, batch, idle)
+                progressed = True
+            if not progressed and not (ready and idle):
+                wait = 0.0005
+                if nxt < total:
+                    wait = min(wait, max(0.0, requests[nxt].t_arrive - self.clock()))
+                try:
+                    wi, batch = self._done.get(timeout=wait) if wait > 0 else self._done.get_nowait()
+                    done += self._complete(wi, batch, idle)
+                except queue.Empty:
+                    pass
+        return requests
+
+
+def summarize(requests, reached_edges: int | None = None) -> dict:
+    lat = np.array([r.latency for r in requests]) * 1e3
+    span = max(r.t_done for r in requests) - min(r.t_arrive for r in requests)
+    out = {"requests": len(requests), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+           "throughput_rps": round(len(requests) / span, 1), "span_s": round(span, 3),
+           "failed": sum(1 for r in requests if r.error is not None)}
+    if reached_edges is not None:
+        out["sssp_gteps"] = round(reached_edges / span / 1e9, 4)
+    return out

@@ -190,6 +190,25 @@ def batch_instances(count: int, degree: int = 16, lo_log2: float = 10.0, hi_log2
     return out
 
 
+def serving_graph_sizes(count: int = 64, lo_log2: float = 14.0, hi_log2: float = 20.0) -> list:
+    """Vertex counts round(2^(lo + (hi - lo) k / (count - 1))), k = 0..count-1."""
+    if count == 1:
+        return [int(round(2 ** lo_log2))]
+    return [int(round(2 ** (lo_log2 + (hi_log2 - lo_log2) * k / (count - 1)))) for k in range(count)]
+
+
+def serving_graph(k: int, n: int, degree: int = 16, n_x: int = 4):
+    """Resident graph k of the serving workload: R-MAT on n vertices with
+    degree * n edges, weights, matrix values and n_x dense vectors, each from
+    seeds derived from (kind, k)."""
+    gseed = int(_load().syn_rand(SEED_GRAPH, 401, k))
+    g = rmat_csr_n(n, degree * n, gseed)
+    w = weights(g.m, int(_load().syn_rand(SEED_WEIGHT, 402, k)))
+    val = values(g.m, int(_load().syn_rand(SEED_VALUE, 403, k)))
+    xs = [vector_x(n, int(_load().syn_rand(SEED_X, 404, k)), stream=j) for j in range(n_x)]
+    return g, w, val, xs
+
+
 # ---- small hand-built shapes (tests and edge cases) -------------------------------------------
 
 def tree_from_parent(parent) -> Tree:

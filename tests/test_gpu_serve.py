@@ -1,0 +1,60 @@
+"""Continuous batching on the GPU: every request's result is the same alone and
+in the mix (SSSP bit-identical and equal to the oracle; SpMV bit-identical to
+the same call alone and within the 1e-5 bound of the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import say
+from paper_1606_08150_amd import serve, wc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def resident():
+    sizes = synth.serving_graph_sizes(6, 10, 13)
+    host, dev = [], []
+    for k, n in enumerate(sizes):
+        g, w, val, xs = synth.serving_graph(k, n, n_x=2)
+        host.append((g, w, val, xs))
+        dev.append(serve.ResidentGraph(wc.DeviceCSR.from_host(g.row_ptr, g.col),
+                                       torch.from_numpy(w.view(np.int32)).cuda(), torch.from_numpy(val).cuda(),
+                                       [torch.from_numpy(x).cuda() for x in xs]))
+    return host, dev
+
+
+def test_results_same_alone_and_in_the_mix(ctx, resident):
+    host, dev = resident
+    srcs = [np.flatnonzero(np.diff(g.row_ptr) > 0) for g, _, _, _ in host]
+    reqs = serve.poisson_requests(240, 20000.0, srcs, n_x=2, seed=9)
+    say(f"serving {len(reqs)} requests")
+    srv = serve.Server(serve.GpuBackend(dev), workers=3, budget_bytes=64 << 20, max_slots=48, max_batch=16,
+                       keep_outputs=True)
+    try:
+        out = srv.run(reqs, time_limit=60)
+    finally:
+        srv.close()
+    assert all(r.error is None for r in out)
+    assert srv.admission.peak_used <= 64 << 20
+    for r in out:
+        g, w, val, xs = host[r.graph]
+        d = dev[r.graph]
+        if r.kind == serve.SSSP:
+            alone = ctx.sssp(d.csr, d.w, r.arg, mode="grid")
+            torch.cuda.synchronize()
+            mixed = r.out.cpu().numpy().view(np.uint32)
+            assert np.array_equal(mixed, alone.cpu().numpy().view(np.uint32)), r.rid
+            assert np.array_equal(mixed, oracle.sssp_dijkstra(g.row_ptr, g.col, w, r.arg)), r.rid
+        else:
+            alone = ctx.spmv(d.csr, d.val, d.xs[r.arg], mode="grid")
+            torch.cuda.synchronize()
+            mixed = r.out.cpu().numpy()
+            assert np.array_equal(mixed.view(np.uint32), alone.cpu().numpy().view(np.uint32)), r.rid
+            y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, xs[r.arg])
+            assert oracle.spmv_check(y_ref, b, mixed) == (0, -1), r.rid
+    s = serve.summarize(out)
+    say(f"serving summary {s}")
+    assert s["failed"] == 0

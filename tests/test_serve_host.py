@@ -1,0 +1,126 @@
+"""Scheduling logic of the request server on the CPU, with a stand-in backend:
+admission never exceeds the memory budget or the slot limit, every request is
+served, later arrivals are admitted while earlier batches run, and a failing
+batch does not poison the others."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1606_08150_amd import serve
+
+
+class FakeGraph:
+    def __init__(self, n, m):
+        self.n, self.m = n, m
+
+
+class FakeBackend:
+    """Each batch 'runs' for a fixed time; results are the request ids."""
+
+    def __init__(self, graphs, run_s=0.002, fail_graph=None):
+        self.graphs = graphs
+        self.run_s = run_s
+        self.fail_graph = fail_graph
+        self.lock = threading.Lock()
+        self.concurrent = 0
+        self.max_concurrent = 0
+        self.batches = []
+
+    def free_bytes(self):
+        return 1 << 40
+
+    def worker_state(self):
+        return None
+
+    def close_state(self, state):
+        pass
+
+    def allocate(self, r):
+        r.out = None
+
+    def execute(self, state, batch):
+        with self.lock:
+            self.concurrent += 1
+            self.max_concurrent = max(self.max_concurrent, self.concurrent)
+            self.batches.append([r.rid for r in batch])
+        time.sleep(self.run_s)
+        with self.lock:
+            self.concurrent -= 1
+        if self.fail_graph is not None and any(r.graph == self.fail_graph for r in batch):
+            raise RuntimeError("injected failure")
+        for r in batch:
+            r.out = r.rid * 10 + r.kind
+
+
+def make(count=400, rate=20000.0, graphs=8):
+    gs = [FakeGraph(1000 * (i + 1), 16000 * (i + 1)) for i in range(graphs)]
+    srcs = [np.arange(10) for _ in gs]
+    reqs = serve.poisson_requests(count, rate, srcs, n_x=4, seed=3)
+    return gs, reqs
+
+
+def test_poisson_stream_is_seeded_and_has_the_rate():
+    _, a = make(count=20000, rate=5000.0)
+    _, b = make(count=20000, rate=5000.0)
+    assert [(r.kind, r.graph, r.arg, r.t_arrive) for r in a] == [(r.kind, r.graph, r.arg, r.t_arrive) for r in b]
+    span = a[-1].t_arrive - a[0].t_arrive
+    assert abs(len(a) / span - 5000.0) / 5000.0 < 0.05
+    frac = np.mean([r.kind == serve.SSSP for r in a])
+    assert abs(frac - 0.5) < 0.02
+
+
+def test_admission_budget_and_slots():
+    adm = serve.Admission(100, 3)
+    assert adm.try_admit(40) and adm.try_admit(40)
+    assert not adm.try_admit(40)  # bytes
+    assert adm.try_admit(20)
+    assert not adm.try_admit(0)   # slots
+    adm.release(40)
+    assert adm.try_admit(30) and adm.peak_used == 100 and adm.peak_slots == 3
+    assert not adm.fits_ever(101) and adm.fits_ever(100)
+
+
+def test_every_request_served_within_budget_with_overlap():
+    gs, reqs = make()
+    be = FakeBackend(gs)
+    budget = 4 * max(serve.request_bytes(k, g.n, g.m) for g in gs for k in (0, 1))
+    srv = serve.Server(be, workers=4, budget_bytes=budget, max_slots=16, max_batch=8, keep_outputs=True)
+    try:
+        out = srv.run(reqs, time_limit=30)
+    finally:
+        srv.close()
+    assert all(r.out == r.rid * 10 + r.kind for r in out)
+    assert srv.admission.peak_used <= budget and srv.admission.peak_slots <= 16
+    assert srv.admission.used == 0 and srv.admission.slots == 0
+    assert be.max_concurrent >= 2  # batches overlapped
+    assert all(r.t_arrive <= r.t_admit <= r.t_start <= r.t_done for r in out)
+    assert sorted(i for b in be.batches for i in b) == list(range(len(reqs)))
+    s = serve.summarize(out)
+    assert s["requests"] == len(reqs) and s["failed"] == 0 and s["p99_ms"] >= s["p50_ms"]
+
+
+def test_a_failed_batch_does_not_poison_the_others():
+    gs, reqs = make(count=200)
+    be = FakeBackend(gs, fail_graph=3)
+    srv = serve.Server(be, workers=2, budget_bytes=1 << 40, max_slots=64, max_batch=1, keep_outputs=True)
+    try:
+        out = srv.run(reqs, time_limit=30)
+    finally:
+        srv.close()
+    for r in out:
+        if r.graph == 3:
+            assert r.error is not None
+        else:
+            assert r.error is None and r.out == r.rid * 10 + r.kind
+
+
+def test_oversized_request_is_rejected():
+    gs, reqs = make(count=10)
+    srv = serve.Server(FakeBackend(gs), workers=1, budget_bytes=10, max_slots=4)
+    try:
+        with pytest.raises(ValueError):
+            srv.run(reqs)
+    finally:
+        srv.close()
