@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched SSSP section")
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--batch-reps", type=int, default=10)
+    p.add_argument("--no-trees", action="store_true", help="skip the tree descendants / heights section")
     p.add_argument("--no-serve", action="store_true", help="skip the continuous-batching serving section")
     p.add_argument("--serve-requests", type=int, default=4000, help="requests per arrival rate")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
@@ -162,6 +163,33 @@ def summarize_profiles(fetch_dir, write_dir, copy_mb, workload, command):
                 json.dump(rec, f, indent=1)
             out[k] = rec
     print(json.dumps(out, indent=1))
+
+
+def run_trees(ctx, torch, synth, wc, stream, n=1 << 22, reps=5):
+    """Tree descendants and heights, 20 B per node per pass (child_ptr, child,
+    output, buffer entry): two passes (down and up) per call."""
+    t = synth.random_tree(n)
+    dt = wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    res = {}
+    for mode in ("flat", "wave", "block", "grid"):
+        row = {}
+        for what, fn in (("desc", ctx.tree_descendants), ("height", ctx.tree_height)):
+            fn(dt, mode=mode, out=out)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn(dt, mode=mode, out=out)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            row[what + "_ms"] = round(ms, 4)
+            row[what + "_gnodes_s"] = round(n / (ms * 1e-3) / 1e9, 3)
+            row[what + "_alg_gbs"] = round(2 * 20.0 * n / (ms * 1e-3) / 1e9, 1)
+        res[mode] = row
+        print(f"[bench] tree {mode}: {row}", file=sys.stderr, flush=True)
+    return {"workload": f"random tree, {n} nodes, power-law fanout (alpha 2, max 4096), depth cap 24", "modes": res}
 
 
 def run_batch(args, ctx, torch, synth, wc):
@@ -414,6 +442,11 @@ def main():
             modes[mode] = res
             print(f"[bench] mode {mode}: {res}", file=sys.stderr, flush=True)
 
+    # ---- trees: descendants and heights on the 2^22-node random tree, every mode
+    trees = None
+    if not args.no_trees:
+        trees = run_trees(ctx, torch, synth, wc, stream)
+
     # ---- batched SSSP: 512 independent R-MAT instances (2^10..2^18 vertices,
     # degree 16) in one graph-captured launch; heuristic vs autotuned per bucket
     batch = None
@@ -465,6 +498,7 @@ def main():
                       "rounds": sst["rounds"], "items_buffered": sst["items_buffered"]},
         "kernels": kernels,
         "modes": modes,
+        "trees": trees,
         "batch": batch,
         "serving": serving,
         "cpu_baseline": cpu,

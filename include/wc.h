@@ -158,7 +158,7 @@ wc_status wc_tree_height(wc_ctx *ctx, const wc_tree *t, int32_t *height, wc_mode
                          hipStream_t stream, wc_stats *stats);
 
 /* Batched SSSP: `count` independent instances in one launch sequence
- * (spec batching pattern; each instance is the problem of wc_sssp).
+ * (a systems pattern around the method; each instance is the problem of wc_sssp).
  * graphs, w, src, dist are HOST arrays of `count` entries whose pointers are
  * device arrays of each instance (dist[i] has graphs[i].n entries and is written
  * entirely).  modes/tunes (nullable: grid mode, defaults) give each instance

@@ -122,7 +122,7 @@ static int default_threshold(const char *problem, wc_mode mode)
     if (!strcmp(problem, "tree")) return 0;  // every node with children is a recursive call (Fig. 1(c))
     // grid level drains with lane groups sized to each item, so only very short
     // items stay inline; wave and block levels drain with whole groups
-    if (mode == WC_GRID) return !strcmp(problem, "spmv") ? 4 : 8;
+    if (mode == WC_GRID) return 8;
     return 32;
 }
 
@@ -287,12 +287,15 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
         return fail(WC_EINVAL, std::string("unknown problem ") + problem);
     if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "mode must be flat, wave, block or grid");
     out->threshold = default_threshold(problem, mode);
-    out->block_threads = 256;
+    // grid-level SSSP and SpMV: 512-thread workgroups measured fastest on the
+    // scale-22 graph; everything else 256
+    out->block_threads = (mode == WC_GRID && strcmp(problem, "tree")) ? 512 : 256;
     // The drain grid of every mode is the resident maximum (KC_1 of Sec. IV.E):
     // wave- and block-level drains run inside the parent groups, which are
     // already resident, so no downgrade for concurrency is needed.
     out->grid_blocks = resident_blocks > 0 ? resident_blocks : 1;
     out->items_per_lane = 4;  // "const" of Sec. IV.E
+    if (mode == WC_GRID && !strcmp(problem, "spmv")) out->items_per_lane = 8;
     out->driver = 0;
     out->allow_fallback = 0;
     out->buf_capacity = 0;

@@ -336,8 +336,11 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
         Config cfg;
         wc_status st = resolve_tune(ctx, "sssp", mode, tunes ? &tunes[i] : nullptr, 1, &cfg);
         if (st != WC_OK) return st;
+        // one workgroup size for the whole batch: the first instance's; later
+        // instances that leave block_threads unset adopt it
         if (i == 0) block = cfg.block;
-        else if (cfg.block != block) return fail(WC_EINVAL, "wc_sssp_batch: all instances must share block_threads");
+        else if (tunes && tunes[i].block_threads > 0 && tunes[i].block_threads != block)
+            return fail(WC_EINVAL, "wc_sssp_batch: all instances must share block_threads");
         if (cfg.driver != 0) return fail(WC_EINVAL, "wc_sssp_batch: the persistent driver is disabled");
         const int chunk = kWave * cfg.items_per_lane;
         inst[i] = Inst{g.row_ptr, g.col, w[i], dist[i], g.n, (int)mode, mode == WC_FLAT ? 0x7fffffff : cfg.threshold,

@@ -149,7 +149,7 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier *b, int nblocks)
             __hip_atomic_fetch_add(&b->generation, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const unsigned long long deadline = wait_deadline();
-            while (__hip_atomic_load(&b->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&b->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(1);
                 if (past(deadline)) {
                     ok = false;

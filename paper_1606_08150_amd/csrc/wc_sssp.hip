@@ -23,6 +23,7 @@
 #include <cstring>
 #include <algorithm>
 
+
 #include "wc_block.h"
 #include "wc_device.h"
 #include "wc_internal.h"

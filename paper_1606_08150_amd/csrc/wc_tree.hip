@@ -56,6 +56,7 @@ struct TreeArgs {
     int *nl;             // node list the packets point into [n]
     int *nl_tail;
     long long *pq;       // packets: (start << 32) | count; -1 = not yet written
+    long long pq_cap;
     int *pq_head;
     int *pq_tail;
     int *outstanding;
@@ -271,6 +272,18 @@ __device__ void complete_upward(const TreeArgs &a, int v, int val)
     }
 }
 
+// nleaf leaf children of p are done (leaf value 0): fold them in at once; if
+// they were p's last unfinished children, p is done and its post-work climbs on.
+template <int OP>
+__device__ void complete_leaves(const TreeArgs &a, int p, int nleaf)
+{
+    atomic_fold<OP>(&a.out[p], OP == OP_DESC ? nleaf : 1);
+    const int left =
+        __hip_atomic_fetch_add(&a.pending[p], -nleaf, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) - nleaf;
+    if (left != 0) return;
+    complete_upward<OP>(a, p, __hip_atomic_load(&a.out[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 __global__ void tree_init_queue(TreeArgs a, long long pq_cap)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < pq_cap;
@@ -383,47 +396,39 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
     }
     gsync<G>();
     for (;;) {
-        // ---- fetch a packet (group leader), or learn that all work is done
+        // ---- fetch a packet (group leader): take the next ticket of the queue;
+        // its packet is published later or, once no packet is outstanding, never
         if (t == 0) {
-            int got = -2;  // -2: keep waiting, -1: done, >= 0: packet slot
+            const int h = atomic_add_dev(a.pq_head, 1);
             const unsigned long long deadline = wait_deadline();
-            for (;;) {
-                int h = atomic_load_dev(a.pq_head);
-                int tl = atomic_load_dev(a.pq_tail);
-                if (h < tl) {
-                    if (__hip_atomic_compare_exchange_strong(a.pq_head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+            long long pk = -1;
+            int got = -1;
+            // polls are relaxed loads (an acquire load invalidates the L2 each
+            // time); one acquire fence follows the poll that succeeds
+            for (int poll = 0;; ++poll) {
+                if (h < a.pq_cap) {
+                    pk = __hip_atomic_load(&a.pq[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (pk >= 0) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                         got = h;
                         break;
                     }
-                    continue;
                 }
-                if (atomic_load_dev(a.outstanding) == 0) {
-                    got = -1;
+                // the shared counter is read only every 8th poll (thousands of waiting
+                // waves would otherwise contend on its line)
+                if ((poll & 7) == 7 &&
+                    __hip_atomic_load(a.outstanding, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
                     break;
-                }
                 __builtin_amdgcn_s_sleep(2);
                 if (past(deadline)) {
                     a.stats->timed_out = 1;
-                    got = -1;
                     break;
                 }
             }
-            long long pk = -1;
-            if (got >= 0) {
-                while ((pk = __hip_atomic_load(&a.pq[got], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) < 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (past(deadline)) {
-                        a.stats->timed_out = 1;
-                        break;
-                    }
-                }
-            }
             s.flag = got;
-            s.pk_start = pk >= 0 ? (int)(pk >> 32) : 0;
-            s.pk_count = pk >= 0 ? (int)(pk & 0xffffffff) : 0;
-            if (got >= 0 && pk < 0) s.flag = -1;
-            if (a.want_stats && s.flag >= 0) acc.dispatches += 1;
+            s.pk_start = got >= 0 ? (int)(pk >> 32) : 0;
+            s.pk_count = got >= 0 ? (int)(pk & 0xffffffff) : 0;
+            if (a.want_stats && got >= 0) acc.dispatches += 1;
         }
         gsync<G>();
         if (s.flag < 0) break;
@@ -483,10 +488,23 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
                     s.buf_work += work;
                 }
             }
-            // leaves: their post-work right away
-            if (c >= 0 && cf == 0) {
-                (void)p;
-                complete_upward<OP>(a, c, 0);
+            // leaves: their post-work right away, aggregated per parent: the
+            // lanes of a wave that share a parent are consecutive (a segment),
+            // and its first lane folds all of the segment's leaves at once
+            {
+                const int lane = lane_id();
+                const int key = c >= 0 ? k : -1;
+                const int prev = __shfl_up(key, 1, kWave);
+                const bool head = c >= 0 && (lane == 0 || prev != key);
+                const uint64_t heads = __ballot(head);
+                const uint64_t leaves = __ballot(c >= 0 && cf == 0);
+                if (head) {
+                    const uint64_t above = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+                    const int next = above ? __builtin_ctzll(above) : 64;
+                    const uint64_t seg = (next == 64 ? ~0ull : ((1ull << next) - 1)) & (~0ull << lane);
+                    const int nleaf = __builtin_popcountll(leaves & seg);
+                    if (nleaf) complete_leaves<OP>(a, p, nleaf);
+                }
             }
             gsync<G>();
             if (s.buf_cnt >= G || s.buf_work >= a.work_cap) flush_buffer<G>(a, s, acc);
@@ -559,6 +577,7 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
         a.nl = pool_take<int>(ctx, n);
         a.pending = pool_take<int>(ctx, n);
         a.pq = pool_take<long long>(ctx, pq_cap);
+        a.pq_cap = pq_cap;
         a.nl_tail = pool_take<int>(ctx, 1);
         a.pq_head = pool_take<int>(ctx, 1);
         a.pq_tail = pool_take<int>(ctx, 1);
