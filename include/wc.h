@@ -191,6 +191,11 @@ wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable);
 wc_status wc_ctx_kernel_stats(wc_ctx *ctx, int32_t index, const char **name, int64_t *launches, double *total_ms,
                               double *max_ms);
 
+/* The index-th recorded launch in launch order: kernel name (static string) and
+ * its event-measured duration in milliseconds.  Waits for its events.  Returns
+ * WC_EINVAL past the last record. */
+wc_status wc_ctx_kernel_record(wc_ctx *ctx, int32_t index, const char **name, double *ms);
+
 /* Thread-local description of the last non-WC_OK status on this thread. */
 const char *wc_last_error(void);
 

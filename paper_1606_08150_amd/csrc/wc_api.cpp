@@ -385,6 +385,20 @@ wc_status wc_ctx_kernel_stats(wc_ctx *ctx, int32_t index, const char **name, int
     return WC_OK;
 }
 
+wc_status wc_ctx_kernel_record(wc_ctx *ctx, int32_t index, const char **name, double *ms)
+{
+    if (!ctx || !name || !ms) return fail(WC_EINVAL, "NULL argument");
+    if (index < 0 || index >= (int32_t)ctx->records.size()) return fail(WC_EINVAL, "no record with that index");
+    WC_HIP(hipSetDevice(ctx->device));
+    const wc_kernel_record &r = ctx->records[index];
+    WC_HIP(hipEventSynchronize(r.stop));
+    float t = 0.f;
+    WC_HIP(hipEventElapsedTime(&t, r.start, r.stop));
+    *name = r.name;
+    *ms = t;
+    return WC_OK;
+}
+
 wc_status wc_ctx_destroy(wc_ctx *ctx)
 {
     if (!ctx) return WC_OK;

@@ -212,6 +212,11 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
         } else if constexpr (MODE == WC_GRID) {
             __shared__ int s_tmp[2 * (BLOCK / kWave)];
             __shared__ int s_base;
+            // most windows of a small frontier hold no heavy vertex: skip the scan
+            if (!__syncthreads_or(heavy ? 1 : 0)) {
+                mark_active(a, r, any);
+                continue;
+            }
             const int nch = heavy ? (deg + a.chunk - 1) / a.chunk : 0;
             int excl, d0, tot, d1;
             block_scan2<BLOCK>(nch, 0, s_tmp, excl, d0, tot, d1);

@@ -23,7 +23,7 @@ STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: 
 # C-ABI symbols declared in include/wc.h
 EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_spmv", "wc_tree_descendants", "wc_tree_height",
            "wc_sssp_batch",
-           "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_last_error", "wc_version", "wc_per_buffer_size",
+           "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size",
            "wc_kc_config", "wc_default_tune")
 
 
@@ -94,6 +94,8 @@ def load_library():
     lib.wc_ctx_kernel_stats.restype = c.c_int
     lib.wc_ctx_kernel_stats.argtypes = [vp, c.c_int32, c.POINTER(c.c_char_p), c.POINTER(c.c_int64),
                                         c.POINTER(c.c_double), c.POINTER(c.c_double)]
+    lib.wc_ctx_kernel_record.restype = c.c_int
+    lib.wc_ctx_kernel_record.argtypes = [vp, c.c_int32, c.POINTER(c.c_char_p), c.POINTER(c.c_double)]
     lib.wc_last_error.restype = c.c_char_p
     lib.wc_last_error.argtypes = []
     lib.wc_version.restype = c.c_char_p
@@ -231,6 +233,19 @@ class Context:
             if st != 0:
                 break
             out[name.value.decode()] = (n.value, tot.value, mx.value)
+            i += 1
+        return out
+
+    def kernel_records(self) -> list:
+        """[(kernel name, ms)] for every recorded launch, in launch order."""
+        lib = load_library()
+        out = []
+        i = 0
+        while True:
+            name, ms = ctypes.c_char_p(), ctypes.c_double()
+            if lib.wc_ctx_kernel_record(self._ptr, i, ctypes.byref(name), ctypes.byref(ms)) != 0:
+                break
+            out.append((name.value.decode(), ms.value))
             i += 1
         return out
 
