@@ -64,6 +64,10 @@ wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream)
         ctx->graph_exec = nullptr;
         ctx->graph_key = 0;
     }
+    for (auto &tg : ctx->tree_graphs) {
+        if (tg.exec) (void)hipGraphExecDestroy(tg.exec);
+        tg = wc_ctx::TreeGraph{};
+    }
     return pool_alloc(ctx, bytes > grow ? bytes : grow);
 }
 
@@ -229,14 +233,24 @@ wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes,
     return WC_OK;
 }
 
+void clear_host_slot(wc_ctx *ctx, int index)
+{
+    reinterpret_cast<volatile int *>(ctx->host_ring)[index] = -1;
+}
+
 void clear_round_slot(wc_ctx *ctx, int r)
 {
-    reinterpret_cast<volatile int *>(ctx->host_ring)[r % kHostRing] = -1;
+    clear_host_slot(ctx, r % kHostRing);
 }
 
 wc_status wait_round_count(wc_ctx *ctx, int r, int *count)
 {
-    volatile int *slot = reinterpret_cast<volatile int *>(ctx->host_ring) + (r % kHostRing);
+    return wait_host_slot(ctx, r % kHostRing, count);
+}
+
+wc_status wait_host_slot(wc_ctx *ctx, int index, int *count)
+{
+    volatile int *slot = reinterpret_cast<volatile int *>(ctx->host_ring) + index;
     auto t0 = std::chrono::steady_clock::now();
     long spins = 0;
     for (;;) {
@@ -326,7 +340,7 @@ wc_status wc_ctx_create(int device, size_t pool_bytes, wc_ctx **out)
     ctx->lds_per_block = prop.sharedMemPerBlock;
     wc_status st = pool_alloc(ctx, pool_bytes ? pool_bytes : (size_t(512) << 20));
     if (st == WC_OK) {
-        e = hipHostMalloc(&ctx->host_ring, sizeof(int) * kHostRing, hipHostMallocMapped | hipHostMallocCoherent);
+        e = hipHostMalloc(&ctx->host_ring, sizeof(int) * (kHostSlotGraph + 1), hipHostMallocMapped | hipHostMallocCoherent);
         if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&ctx->host_ring_dev, ctx->host_ring, 0);
         if (e == hipSuccess) e = hipMalloc(&ctx->dstats, sizeof(DevStats));
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_start);
@@ -341,7 +355,7 @@ wc_status wc_ctx_create(int device, size_t pool_bytes, wc_ctx **out)
         wc_ctx_destroy(ctx);
         return st;
     }
-    for (int i = 0; i < kHostRing; ++i) ctx->host_ring[i] = -1;
+    for (int i = 0; i <= kHostSlotGraph; ++i) ctx->host_ring[i] = -1;
     *out = ctx;
     return WC_OK;
 }
@@ -413,6 +427,8 @@ wc_status wc_ctx_destroy(wc_ctx *ctx)
     if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
     if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    for (auto &tg : ctx->tree_graphs)
+        if (tg.exec) (void)hipGraphExecDestroy(tg.exec);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);

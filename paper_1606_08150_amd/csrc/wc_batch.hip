@@ -75,9 +75,10 @@ __device__ __forceinline__ uint32_t add_sat(uint32_t du, uint32_t w)
 __device__ __forceinline__ bool relax_loaded(uint32_t *dist, int *stamp_base, int v, uint32_t nd, uint32_t dv,
                                              int next)
 {
+    // as in single-instance SSSP: stamping on nd < dv gives the same frontier
+    // as waiting for the atomic's old value
     if (nd >= dv) return false;
-    uint32_t old = atomic_min_dev(&dist[v], nd);
-    if (nd >= old) return false;
+    atomic_min_dev_noret(&dist[v], nd);
     stamp_base[v] = next;
     return true;
 }
@@ -124,6 +125,8 @@ template <int BLOCK>
 struct BatchLds {
     int inst[BLOCK];
     int beg[BLOCK];
+    int end[BLOCK];
+    int csz[BLOCK];
     uint32_t du[BLOCK];
     int pre[BLOCK + 1];
     int scan_tmp[2 * (BLOCK / kWave)];
@@ -224,18 +227,34 @@ __global__ __launch_bounds__(BLOCK) void batch_round(BatchArgs a, int r)
             }
             int excl, d0, tot, d1;
             block_scan2<BLOCK>(nch, 0, sb.scan_tmp, excl, d0, tot, d1);
+            sb.pre[threadIdx.x] = excl;
+            sb.inst[threadIdx.x] = i;
+            sb.beg[threadIdx.x] = beg;
+            sb.end[threadIdx.x] = end;
+            sb.csz[threadIdx.x] = chunk;
+            sb.du[threadIdx.x] = du;
             if (threadIdx.x == 0) sb.base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
             __syncthreads();
-            const int slot = sb.base + excl;
-            for (int c = 0; c < nch; ++c) {
-                const int cb = beg + c * chunk, ce = min(end, cb + chunk);
-                if ((long long)slot + c < a.chunk_cap) {
-                    a.chunks[slot + c] = make_int4(g, cb, ce, i);
+            // the block writes the window's chunks together: chunk j belongs to
+            // the last thread whose offset is <= j
+            const int slot0 = sb.base;
+            for (int j = threadIdx.x; j < tot; j += BLOCK) {
+                int lo = 0, hi = BLOCK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sb.pre[mid] <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int ck = sb.csz[lo];
+                const int cb = sb.beg[lo] + (j - sb.pre[lo]) * ck, ce = min(sb.end[lo], cb + ck);
+                const int oi = sb.inst[lo];
+                if ((long long)slot0 + j < a.chunk_cap) {
+                    a.chunks[slot0 + j] = make_int4(base + lo, cb, ce, oi);
                 } else {
                     a.stats->overflowed = 1;
-                    const Inst &d = a.inst[i];
-                    int *sbase = a.stamp + a.vbase[i];
-                    for (int e = cb; e < ce; e += kUnroll) any |= relax_batch(d, sbase, e, 1, ce, du, next);
+                    const Inst &d = a.inst[oi];
+                    int *sbase = a.stamp + a.vbase[oi];
+                    for (int e = cb; e < ce; e += kUnroll) any |= relax_batch(d, sbase, e, 1, ce, sb.du[lo], next);
                 }
             }
             __syncthreads();

@@ -43,6 +43,11 @@ __device__ __forceinline__ uint32_t atomic_min_dev(uint32_t *p, uint32_t v)
 {
     return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// result unused: the wave does not wait for the atomic to return
+__device__ __forceinline__ void atomic_min_dev_noret(uint32_t *p, uint32_t v)
+{
+    (void)__hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int atomic_max_dev(int *p, int v)
 {
     return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -36,6 +36,8 @@ struct DevStats {
 // Ring of round counts published by kernels to pinned host memory, so the host
 // can stop relaunching rounds without a blocking copy per round.
 constexpr int kHostRing = 256;
+// host-ring entry after the round slots, written only by a graph's last kernel
+constexpr int kHostSlotGraph = kHostRing;
 
 }  // namespace wc
 
@@ -70,6 +72,13 @@ struct wc_ctx {
     hipEvent_t graph_ready = nullptr, graph_done = nullptr;
     unsigned long long graph_key = 0;
     hipGraphExec_t graph_exec = nullptr;
+    // level-synchronous trees: captured graphs of all levels, keyed by the call
+    struct TreeGraph {
+        unsigned long long key = 0;
+        hipGraphExec_t exec = nullptr;
+        int levels = 0;
+    } tree_graphs[4];
+    int tree_graph_next = 0;
 };
 
 namespace wc {
@@ -130,6 +139,9 @@ wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes,
 // Waits (bounded) until a kernel published the count of round `r` to the host ring.
 wc_status wait_round_count(wc_ctx *ctx, int r, int *count);
 void clear_round_slot(wc_ctx *ctx, int r);
+// the same for one host-ring entry by index (0 <= index <= kHostSlotGraph)
+wc_status wait_host_slot(wc_ctx *ctx, int index, int *value);
+void clear_host_slot(wc_ctx *ctx, int index);
 
 
 }  // namespace wc

@@ -65,26 +65,32 @@ struct SpmvArgs {
 
 // Sum of val[e] * x[col[e]] over e = first + k * stride (k >= 0, e < end), in
 // order of k, kUnroll loads in flight.
-__device__ __forceinline__ float dot_strided(const SpmvArgs &a, int first, int stride, int end)
+template <int U>
+__device__ __forceinline__ float dot_strided_u(const SpmvArgs &a, int first, int stride, int end)
 {
     float s = 0.f;
-    for (int e0 = first; e0 < end; e0 += kUnroll * stride) {
-        int c[kUnroll];
-        float v[kUnroll], xv[kUnroll];
+    for (int e0 = first; e0 < end; e0 += U * stride) {
+        int c[U];
+        float v[U], xv[U];
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
+        for (int k = 0; k < U; ++k) {
             const int e = e0 + k * stride;
             const bool ok = e < end;
             c[k] = ok ? a.col[e] : -1;
             v[k] = ok ? a.val[e] : 0.f;
         }
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) xv[k] = c[k] >= 0 ? a.x[c[k]] : 0.f;
+        for (int k = 0; k < U; ++k) xv[k] = c[k] >= 0 ? a.x[c[k]] : 0.f;
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k)
+        for (int k = 0; k < U; ++k)
             if (c[k] >= 0) s = fmaf(v[k], xv[k], s);
     }
     return s;
+}
+
+__device__ __forceinline__ float dot_strided(const SpmvArgs &a, int first, int stride, int end)
+{
+    return dot_strided_u<kUnroll>(a, first, stride, end);
 }
 
 __device__ __forceinline__ float dot_wave(const SpmvArgs &a, int beg, int end)
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
         const int len = end - beg;
         const bool heavy = len > a.threshold;
         if (a.want_stats) count_stats(acc, len, heavy, false);
-        if (valid && !heavy) a.y[r] = dot_strided(a, beg, 1, end);
+        if (valid && !heavy) a.y[r] = dot_strided_u<2 * kUnroll>(a, beg, 1, end);
         int bin = -1, local = 0, nch = 0, mlocal = 0;
         if (heavy) {
             if (len > a.chunk) {
@@ -288,14 +294,25 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
         if (bin >= 0 && bin < kBins) {
             const long long pos = (long long)binoff[bin] + cur[bin] + local;
             if (pos < a.rows_cap) a.rows_buf[pos] = make_int4(r, beg, end, 0);
-        } else if (bin == kChunkBin) {
-            const int slot = cur[kChunkBin] + local;
+        }
+        // split rows: the wave writes each such row's chunks together (a long
+        // row's chunks are not left to its own lane)
+        const int slot = cur[kChunkBin] + local;
+        const bool split_fits = bin == kChunkBin && (long long)slot + nch <= a.chunk_cap;
+        uint64_t cm = __ballot(split_fits);
+        while (cm) {
+            const int b = __builtin_ctzll(cm);
+            cm &= cm - 1;
+            const int s0 = readlane(slot, b), n0 = readlane(nch, b);
+            const int rb = readlane(beg, b), re = readlane(end, b), rr = readlane(r, b);
+            for (int c = lane_id(); c < n0; c += kWave) {
+                const int cb = rb + c * a.chunk;
+                a.chunks[s0 + c] = make_int4(rr, cb, min(re, cb + a.chunk), 0);
+            }
+        }
+        if (bin == kChunkBin) {
             const long long mpos = (long long)cur[kMultiCol] + mlocal;
-            if ((long long)slot + nch <= a.chunk_cap) {
-                for (int c = 0; c < nch; ++c) {
-                    int cb = beg + c * a.chunk;
-                    a.chunks[slot + c] = make_int4(r, cb, min(end, cb + a.chunk), 0);
-                }
+            if (split_fits) {
                 if (mpos < a.multi_cap) a.multi[mpos] = make_int4(r, slot, nch, 0);
             } else {
                 // buffer full: mark the reserved slots that exist as empty and
@@ -350,7 +367,7 @@ __global__ __launch_bounds__(BLOCK) void spmv_drain(SpmvArgs a)
             if (i < s_cnt[b]) {
                 int4 d = a.rows_buf[s_off[b] + i];
                 row = d.x;
-                s = dot_strided(a, d.y + sub, g, d.z);
+                s = dot_strided_u<2 * kUnroll>(a, d.y + sub, g, d.z);
             }
             s = group_sum(s, g);
             if (row >= 0 && sub == 0) a.y[row] = s;
@@ -359,7 +376,8 @@ __global__ __launch_bounds__(BLOCK) void spmv_drain(SpmvArgs a)
             int4 d = a.chunks[c];
             const int row = __builtin_amdgcn_readfirstlane(d.x);
             if (row < 0) continue;
-            float s = dot_wave(a, __builtin_amdgcn_readfirstlane(d.y), __builtin_amdgcn_readfirstlane(d.z));
+            float s = wave_sum(dot_strided_u<2 * kUnroll>(a, __builtin_amdgcn_readfirstlane(d.y) + lane, kWave,
+                                                          __builtin_amdgcn_readfirstlane(d.z)));
             if (lane == 0) a.partials[c] = s;
         }
     }

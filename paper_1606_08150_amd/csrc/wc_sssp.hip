@@ -59,47 +59,50 @@ __device__ __forceinline__ uint32_t add_sat(uint32_t du, uint32_t w)
     return s < du ? kInf : s;
 }
 
-// Relaxes edge e of a vertex at distance du: atomicMin on dist[v]; a vertex
-// that improved is stamped into the next round's frontier.  The plain read of
-// dist[v] filters most edges; a stale read is only ever too high, so it can
-// cost an extra atomic but never hide an improvement.
+// Relaxes edge e of a vertex at distance du: atomicMin on dist[v], and v is
+// stamped into the next round's frontier.  dv is a plain read of dist[v] taken
+// earlier in the round; a stale read is only ever too high.  The atomic's old
+// value is not waited for: when nd < dv but another relaxation of this round
+// got dist[v] below nd first, that relaxation stamps v too, so stamping on
+// nd < dv gives the same frontier (and a vertex stamped twice is expanded once).
 __device__ __forceinline__ bool relax_loaded(const SsspArgs &a, int v, uint32_t nd, uint32_t dv, int next)
 {
     if (nd >= dv) return false;
-    uint32_t old = atomic_min_dev(&a.dist[v], nd);
-    if (nd >= old) return false;
+    atomic_min_dev_noret(&a.dist[v], nd);
     a.stamp[v] = next;
     return true;
 }
 
-// kUnroll edges per lane at once: e_k = first + k * stride (valid while < end).
+// U edges per lane at once: e_k = first + k * stride (valid while < end).
 // Loads are issued for all k before any relaxation, for memory-level parallelism.
+template <int U = kUnroll>
 __device__ __forceinline__ bool relax_batch(const SsspArgs &a, int first, int stride, int end, uint32_t du,
                                             int next)
 {
-    int v[kUnroll];
-    uint32_t wt[kUnroll], dv[kUnroll];
+    int v[U];
+    uint32_t wt[U], dv[U];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
+    for (int k = 0; k < U; ++k) {
         const int e = first + k * stride;
         const bool ok = e < end;
         v[k] = ok ? a.col[e] : -1;
         wt[k] = ok ? a.w[e] : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
+    for (int k = 0; k < U; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
     bool any = false;
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k)
+    for (int k = 0; k < U; ++k)
         if (v[k] >= 0) any |= relax_loaded(a, v[k], add_sat(du, wt[k]), dv[k], next);
     return any;
 }
 
-// Inline "work" of Fig. 1(b): the lane relaxes edges [beg, end) of its vertex.
+// Inline "work" of Fig. 1(b): the lane relaxes edges [beg, end) of its vertex,
+// 2 * kUnroll at a time (a light vertex of the default threshold in one step).
 __device__ __forceinline__ bool relax_lane(const SsspArgs &a, int beg, int end, uint32_t du, int next)
 {
     bool any = false;
-    for (int e = beg; e < end; e += kUnroll) any |= relax_batch(a, e, 1, end, du, next);
+    for (int e = beg; e < end; e += 2 * kUnroll) any |= relax_batch<2 * kUnroll>(a, e, 1, end, du, next);
     return any;
 }
 
@@ -108,6 +111,36 @@ __device__ __forceinline__ bool relax_wave(const SsspArgs &a, int beg, int end, 
 {
     bool any = false;
     for (int b = beg; b < end; b += kWave * kUnroll) any |= relax_batch(a, b + lane_id(), kWave, end, du, next);
+    return any;
+}
+
+// Two chunks of the grid buffer at once (uniform arguments): each lane keeps
+// 2 * kUnroll edges in flight.  The chunks' source distances are read after
+// their edges are requested (they may have improved since the vertex was
+// buffered).  Chunk 1 may be empty (cb1 == ce1, u1 unused).
+__device__ __forceinline__ bool relax_wave2(const SsspArgs &a, int u0, int cb0, int ce0, int u1, int cb1, int ce1,
+                                            int next)
+{
+    bool any = false;
+    const int len = max(ce0 - cb0, ce1 - cb1);
+    for (int o = lane_id(); o - lane_id() < len; o += kWave * kUnroll) {
+        int v[2 * kUnroll];
+        uint32_t wt[2 * kUnroll], dv[2 * kUnroll];
+#pragma unroll
+        for (int k = 0; k < 2 * kUnroll; ++k) {
+            const int e = (k < kUnroll ? cb0 : cb1) + o + (k % kUnroll) * kWave;
+            const bool ok = e < (k < kUnroll ? ce0 : ce1);
+            v[k] = ok ? a.col[e] : -1;
+            wt[k] = ok ? a.w[e] : 0u;
+        }
+        const uint32_t du0 = a.dist[u0];
+        const uint32_t du1 = cb1 < ce1 ? a.dist[u1] : 0u;
+#pragma unroll
+        for (int k = 0; k < 2 * kUnroll; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < 2 * kUnroll; ++k)
+            if (v[k] >= 0) any |= relax_loaded(a, v[k], add_sat(k < kUnroll ? du0 : du1, wt[k]), dv[k], next);
+    }
     return any;
 }
 
@@ -212,6 +245,8 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
         } else if constexpr (MODE == WC_GRID) {
             __shared__ int s_tmp[2 * (BLOCK / kWave)];
             __shared__ int s_base;
+            __shared__ int s_excl[BLOCK], s_beg[BLOCK], s_end[BLOCK];
+            __shared__ uint32_t s_du[BLOCK];
             // most windows of a small frontier hold no heavy vertex: skip the scan
             if (!__syncthreads_or(heavy ? 1 : 0)) {
                 mark_active(a, r, any);
@@ -220,23 +255,34 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
             const int nch = heavy ? (deg + a.chunk - 1) / a.chunk : 0;
             int excl, d0, tot, d1;
             block_scan2<BLOCK>(nch, 0, s_tmp, excl, d0, tot, d1);
+            s_excl[threadIdx.x] = excl;
+            s_beg[threadIdx.x] = beg;
+            s_end[threadIdx.x] = end;
+            s_du[threadIdx.x] = du;
             if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
             __syncthreads();
-            const int slot = s_base + excl;
-            if (heavy) {
-                for (int c = 0; c < nch; ++c) {
-                    int cb = beg + c * a.chunk;
-                    int ce = min(end, cb + a.chunk);
-                    if ((long long)slot + c < a.chunk_cap) {
-                        a.chunks[slot + c] = make_int4(u, cb, ce, 0);
-                    } else {
-                        // buffer full: this chunk is processed inline (fallback)
-                        a.stats->overflowed = 1;
-                        any |= relax_lane(a, cb, ce, du, next);
-                    }
+            // the block writes the window's chunks together (a hub's chunks are
+            // not left to its own lane): chunk j belongs to the last thread whose
+            // offset is <= j
+            const int slot0 = s_base;
+            for (int j = threadIdx.x; j < tot; j += BLOCK) {
+                int lo = 0, hi = BLOCK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_excl[mid] <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int cb = s_beg[lo] + (j - s_excl[lo]) * a.chunk;
+                const int ce = min(s_end[lo], cb + a.chunk);
+                if ((long long)slot0 + j < a.chunk_cap) {
+                    a.chunks[slot0 + j] = make_int4(base + lo, cb, ce, 0);
+                } else {
+                    // buffer full: this chunk is processed inline (fallback)
+                    a.stats->overflowed = 1;
+                    any |= relax_lane(a, cb, ce, s_du[lo], next);
                 }
             }
-            __syncthreads();  // s_base is rewritten by the next window
+            __syncthreads();  // the LDS arrays are rewritten by the next window
         }
         mark_active(a, r, any);
     }
@@ -257,13 +303,18 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
     if (a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0)
         atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
     bool any = false;
-    for (int c = gw; c < total; c += nw) {
-        int4 d = a.chunks[c];
-        int u = __builtin_amdgcn_readfirstlane(d.x);
-        int cb = __builtin_amdgcn_readfirstlane(d.y);
-        int ce = __builtin_amdgcn_readfirstlane(d.z);
-        uint32_t du = a.dist[u];
-        any |= relax_wave(a, cb, ce, du, next);
+    // two chunks per wave and step; the next pair's entries are fetched before
+    // the current pair's edges
+    int4 d0 = gw < total ? a.chunks[gw] : make_int4(0, 0, 0, 0);
+    int4 d1 = gw + nw < total ? a.chunks[gw + nw] : make_int4(0, 0, 0, 0);
+    for (int c = gw; c < total; c += 2 * nw) {
+        const int u0 = __builtin_amdgcn_readfirstlane(d0.x), u1 = __builtin_amdgcn_readfirstlane(d1.x);
+        const int cb0 = __builtin_amdgcn_readfirstlane(d0.y), ce0 = __builtin_amdgcn_readfirstlane(d0.z);
+        const int cb1 = __builtin_amdgcn_readfirstlane(d1.y), ce1 = __builtin_amdgcn_readfirstlane(d1.z);
+        const int cn = c + 2 * nw;
+        d0 = cn < total ? a.chunks[cn] : make_int4(0, 0, 0, 0);
+        d1 = cn + nw < total ? a.chunks[cn + nw] : make_int4(0, 0, 0, 0);
+        any |= relax_wave2(a, u0, cb0, ce0, u1, cb1, ce1, next);
     }
     mark_active(a, r, any);
 }

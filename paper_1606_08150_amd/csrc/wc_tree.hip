@@ -220,6 +220,22 @@ __global__ __launch_bounds__(BLOCK) void tree_up(TreeArgs a, int l)
     level_up<MODE, OP, BLOCK>(a, a.lvl_start[l], a.lvl_count[l]);
 }
 
+// Last kernel of a captured graph of levels 0..L: publishes the tree's depth
+// (its first empty level), or -2 when level L is not empty (the tree is deeper
+// than the recorded one and the levels have to be driven from the host).
+__global__ void tree_publish_depth(TreeArgs a, int L)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int d = -2;
+        for (int l = 0; l <= L; ++l)
+            if (a.lvl_count[l] == 0) {
+                d = l;
+                break;
+            }
+        store_system(&a.host_ring[kHostSlotGraph], d);
+    }
+}
+
 // Persistent driver of the level-synchronous modes: all levels, both
 // directions, one co-resident launch, grid barrier between levels.
 template <int MODE, int OP, int BLOCK>
@@ -635,14 +651,54 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
         }
         return st;
     }
+    // A call repeated on the same tree replays a captured graph of all levels
+    // (down to the recorded depth plus one empty level, then up); the empty
+    // level publishes its count, and a non-zero count (a deeper tree at the same
+    // addresses) sends the call down the ordinary path.
+    const char *down_name = mode == WC_GRID ? "tree_down_grid" : "tree_down_flat";
+    const char *up_name = mode == WC_GRID ? "tree_up_grid" : "tree_up_flat";
+    unsigned long long key = 1469598103934665603ull;
+    {
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(&a);
+        for (size_t k = 0; k < sizeof(a); ++k) key = (key ^ b[k]) * 1099511628211ull;
+        const long long extra[4] = {(long long)mode, (long long)OP, (long long)grid, (long long)BLOCK};
+        b = reinterpret_cast<const unsigned char *>(extra);
+        for (size_t k = 0; k < sizeof(extra); ++k) key = (key ^ b[k]) * 1099511628211ull;
+    }
+    wc_ctx::TreeGraph *tg = nullptr;
+    if (!ctx->timing)
+        for (auto &e : ctx->tree_graphs)
+            if (e.exec && e.key == key) tg = &e;
+    if (tg) {
+        clear_host_slot(ctx, kHostSlotGraph);
+        WC_HIP(hipEventRecord(ctx->graph_ready, stream));
+        WC_HIP(hipStreamWaitEvent(ctx->capture_stream, ctx->graph_ready, 0));
+        WC_HIP(hipGraphLaunch(tg->exec, ctx->capture_stream));
+        WC_HIP(hipEventRecord(ctx->graph_done, ctx->capture_stream));
+        WC_HIP(hipStreamWaitEvent(stream, ctx->graph_done, 0));
+        int depth = 0;
+        st = wait_host_slot(ctx, kHostSlotGraph, &depth);
+        if (st != WC_OK) return st;
+        if (depth >= 0) return end_call(ctx, stream, stats, depth, cfg.fail_on_overflow);
+        WC_HIP(hipStreamSynchronize(stream));
+        (void)hipGraphExecDestroy(tg->exec);
+        *tg = wc_ctx::TreeGraph{};
+        st = begin_call(ctx, stream, stats);
+        if (st != WC_OK) return st;
+        void *args[] = {&a};
+        st = launch(ctx, "tree_init_levels",
+                    mode == WC_GRID ? reinterpret_cast<const void *>(&tree_init_levels)
+                                    : reinterpret_cast<const void *>(&tree_init_levels_flat),
+                    dim3(1), dim3(64), args, stream);
+        if (st != WC_OK) return st;
+    }
     const int window = 4;
     int launched = 0, levels = 0;
     for (;;) {
         while (launched < levels + window) {
             clear_round_slot(ctx, launched);
             void *args[] = {&a, &launched};
-            st = launch(ctx, mode == WC_GRID ? "tree_down_grid" : "tree_down_flat", ks.down, dim3(grid), dim3(BLOCK),
-                        args, stream);
+            st = launch(ctx, down_name, ks.down, dim3(grid), dim3(BLOCK), args, stream);
             if (st != WC_OK) return st;
             ++launched;
         }
@@ -655,9 +711,48 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
     }
     for (int l = levels - 1; l >= 0; --l) {
         void *args[] = {&a, &l};
-        st = launch(ctx, mode == WC_GRID ? "tree_up_grid" : "tree_up_flat", ks.up, dim3(grid), dim3(BLOCK), args,
-                    stream);
+        st = launch(ctx, up_name, ks.up, dim3(grid), dim3(BLOCK), args, stream);
         if (st != WC_OK) return st;
+    }
+    if (levels <= 1024 && !ctx->timing) {
+        // record the levels of this tree as a graph for the next call
+        hipGraph_t graph = nullptr;
+        WC_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        const int saved_timing = ctx->timing;
+        ctx->timing = 0;
+        for (int l = 0; l <= levels && st == WC_OK; ++l) {
+            void *args[] = {&a, &l};
+            st = launch(ctx, down_name, ks.down, dim3(grid), dim3(BLOCK), args, ctx->capture_stream);
+        }
+        for (int l = levels - 1; l >= 0 && st == WC_OK; --l) {
+            void *args[] = {&a, &l};
+            st = launch(ctx, up_name, ks.up, dim3(grid), dim3(BLOCK), args, ctx->capture_stream);
+        }
+        if (st == WC_OK) {
+            int L = levels;
+            void *args[] = {&a, &L};
+            st = launch(ctx, "tree_publish_depth", reinterpret_cast<const void *>(&tree_publish_depth), dim3(1),
+                        dim3(64), args, ctx->capture_stream);
+        }
+        ctx->timing = saved_timing;
+        hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
+        if (st != WC_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        wc_ctx::TreeGraph &slot = ctx->tree_graphs[ctx->tree_graph_next];
+        ctx->tree_graph_next = (ctx->tree_graph_next + 1) % 4;
+        if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+        slot = wc_ctx::TreeGraph{};
+        e = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            slot.exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        slot.key = key;
+        slot.levels = levels;
     }
     return end_call(ctx, stream, stats, levels, cfg.fail_on_overflow);
 }

@@ -112,3 +112,44 @@ def test_2p22_tree_bit_exact(ctx, c3_tree, mode):
     t, d, h = c3_tree
     assert np.array_equal(run(ctx, t, "desc", mode), d)
     assert np.array_equal(run(ctx, t, "height", mode), h)
+
+
+def deep_tree(n, depth):
+    """A chain of `depth` edges from the root, every other node a child of the root."""
+    parent = [-1] + list(range(depth)) + [0] * (n - depth - 1)
+    return synth.tree_from_parent(parent)
+
+
+@pytest.mark.parametrize("mode", ["flat", "grid"])
+def test_level_graph_replays(ctx, mode):
+    """Repeated calls replay a captured graph of the levels.  Different trees
+    are copied into the same device buffers, so the graph recorded for one tree
+    meets a deeper one (the call falls back to host-driven levels) and a
+    shallower one (the extra levels are empty); eager work runs between calls."""
+    n = 5000
+    trees = [("random", synth.random_tree(n, seed=11)), ("deep", deep_tree(n, 700)),
+             ("star", synth.star_tree(n)), ("deeper", deep_tree(n, 1500)), ("random", synth.random_tree(n, seed=11))]
+    first = trees[0][1]
+    dt = wc.DeviceTree.from_host(first.parent, first.child_ptr, first.child)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    other = synth.random_tree(3000, seed=12)
+    other_dt = wc.DeviceTree.from_host(other.parent, other.child_ptr, other.child)
+    other_ref = oracle.tree_height(other.child_ptr, other.child)
+    for name, t in trees:
+        dt.parent.copy_(torch.as_tensor(t.parent, dtype=torch.int32))
+        dt.child_ptr.copy_(torch.as_tensor(t.child_ptr, dtype=torch.int32))
+        dt.child.copy_(torch.as_tensor(t.child, dtype=torch.int32))
+        d = oracle.tree_descendants(t.child_ptr, t.child)
+        h = oracle.tree_height(t.child_ptr, t.child)
+        for rep in range(4):
+            say(f"tree graph replay mode={mode} tree={name} rep={rep}")
+            res, st = ctx.tree_descendants(dt, mode=mode, out=out, stats=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(res.cpu().numpy(), d), (name, rep)
+            assert st["rounds"] == h[0], (name, rep)
+            res = ctx.tree_height(dt, mode=mode, out=out)
+            torch.cuda.synchronize()
+            assert np.array_equal(res.cpu().numpy(), h), (name, rep)
+            e = ctx.tree_height(other_dt, mode="grid")
+            torch.cuda.synchronize()
+            assert np.array_equal(e.cpu().numpy(), other_ref)
