@@ -289,6 +289,131 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
     if (a.want_stats) stat_flush(a.stats, acc);
 }
 
+// Two light vertices' inline work at once: each lane keeps kUnroll edges of
+// each vertex in flight.
+__device__ __forceinline__ bool relax_lane2(const SsspArgs &a, int b0, int e0, uint32_t du0, int b1, int e1,
+                                            uint32_t du1, int next)
+{
+    constexpr int U = kUnroll;
+    bool any = false;
+    const int len = max(e0 - b0, e1 - b1);
+    for (int o = 0; o < len; o += U) {
+        int v[2 * U];
+        uint32_t nd[2 * U], dv[2 * U];
+#pragma unroll
+        for (int k = 0; k < 2 * U; ++k) {
+            const int e = (k < U ? b0 : b1) + o + (k % U);
+            const bool ok = e < (k < U ? e0 : e1);
+            v[k] = ok ? a.col[e] : -1;
+            nd[k] = ok ? add_sat(k < U ? du0 : du1, a.w[e]) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * U; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < 2 * U; ++k)
+            if (v[k] >= 0) any |= relax_loaded(a, v[k], nd[k], dv[k], next);
+    }
+    return any;
+}
+
+// Parent kernel of grid mode.  As sssp_round, but every thread takes two
+// vertices of a window of 2 * BLOCK (u and u + BLOCK), with the loads of both
+// issued together: the parent is bound by the latency of its dependent loads
+// (stamp, then CSR range and distance, then edges, then targets).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void sssp_round_grid2(SsspArgs a,
+                                                                                         int r)
+{
+    constexpr int V = 2;
+    __shared__ int s_tmp[2 * (BLOCK / kWave)];
+    __shared__ int s_base;
+    __shared__ int s_excl[V * BLOCK], s_beg[V * BLOCK], s_end[V * BLOCK];
+    __shared__ uint32_t s_du[V * BLOCK];
+    const int act = a.active[(r % 3) * kPad];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.active[((r + 2) % 3) * kPad] = 0;
+        a.chunk_tail[((r + 1) % 3) * kPad] = 0;
+        store_system(&a.host_ring[r % kHostRing], act);
+    }
+    if (!act) return;
+    const int next = r + 1;
+    StatAcc acc;
+    for (int base = blockIdx.x * V * BLOCK; base < a.n; base += gridDim.x * V * BLOCK) {
+        int u[V], beg[V], end[V], nch[V];
+        uint32_t du[V];
+        bool member[V], heavy[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            u[k] = base + k * BLOCK + threadIdx.x;
+            member[k] = u[k] < a.n && a.stamp[u[k]] == r;
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            beg[k] = end[k] = 0;
+            du[k] = 0;
+            if (member[k]) {
+                beg[k] = a.row_ptr[u[k]];
+                end[k] = a.row_ptr[u[k] + 1];
+                du[k] = a.dist[u[k]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const int deg = end[k] - beg[k];
+            heavy[k] = deg > a.threshold;
+            nch[k] = heavy[k] ? (deg + a.chunk - 1) / a.chunk : 0;
+            if (a.want_stats) {
+                acc.edges += deg;
+                acc.buffered += heavy[k] ? deg : 0;
+                acc.items += heavy[k] ? 1 : 0;
+            }
+        }
+        // work: light items relax inline
+        bool any = relax_lane2(a, beg[0], heavy[0] ? beg[0] : end[0], du[0], beg[1], heavy[1] ? beg[1] : end[1], du[1],
+                               next);
+        // most windows of a small frontier hold no heavy vertex: skip the scan
+        if (!__syncthreads_or((heavy[0] || heavy[1]) ? 1 : 0)) {
+            mark_active(a, r, any);
+            continue;
+        }
+        int excl, d0, tot, d1;
+        block_scan2<BLOCK>(nch[0] + nch[1], 0, s_tmp, excl, d0, tot, d1);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const int q = threadIdx.x * V + k;  // entries in (thread, vertex) order
+            s_excl[q] = excl + (k == 0 ? 0 : nch[0]);
+            s_beg[q] = beg[k];
+            s_end[q] = end[k];
+            s_du[q] = du[k];
+        }
+        if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
+        __syncthreads();
+        // the block writes the window's chunks together: chunk j belongs to the
+        // last entry whose offset is <= j
+        const int slot0 = s_base;
+        for (int j = threadIdx.x; j < tot; j += BLOCK) {
+            int lo = 0, hi = V * BLOCK - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_excl[mid] <= j) lo = mid;
+                else hi = mid - 1;
+            }
+            const int cb = s_beg[lo] + (j - s_excl[lo]) * a.chunk;
+            const int ce = min(s_end[lo], cb + a.chunk);
+            if ((long long)slot0 + j < a.chunk_cap) {
+                a.chunks[slot0 + j] = make_int4(base + (lo % V) * BLOCK + lo / V, cb, ce, 0);
+            } else {
+                // buffer full: this chunk is processed inline (fallback)
+                a.stats->overflowed = 1;
+                any |= relax_lane(a, cb, ce, s_du[lo], next);
+            }
+        }
+        __syncthreads();  // the LDS arrays are rewritten by the next window
+        mark_active(a, r, any);
+    }
+    if (a.want_stats) stat_flush(a.stats, acc);
+}
+
 // Consolidated child of grid-level consolidation: one wave per chunk, chunks
 // fetched grid-stride until the buffer is exhausted (moldable).
 template <int BLOCK>
@@ -346,7 +471,7 @@ KernelSet pick_block(wc_mode mode)
     case WC_FLAT: return {reinterpret_cast<const void *>(&sssp_round<WC_FLAT, BLOCK>), nullptr};
     case WC_WAVE: return {reinterpret_cast<const void *>(&sssp_round<WC_WAVE, BLOCK>), nullptr};
     case WC_BLOCK: return {reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK>), nullptr};
-    default: return {reinterpret_cast<const void *>(&sssp_round<WC_GRID, BLOCK>), drain};
+    default: return {reinterpret_cast<const void *>(&sssp_round_grid2<BLOCK>), drain};
     }
 }
 
@@ -424,7 +549,8 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     a.stats = ctx->dstats;
     a.want_stats = stats != nullptr;
 
-    const int windows = (int)((n + cfg.block - 1) / cfg.block);
+    const long long per_window = mode == WC_GRID ? 2LL * cfg.block : cfg.block;
+    const int windows = (int)((n + per_window - 1) / per_window);
     const int grid = std::max(1, std::min(std::min(cfg.grid, resident), windows));
     const int dgrid = std::max(1, std::min(cfg.grid, resident));
     st = begin_call(ctx, stream, stats);
