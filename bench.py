@@ -82,7 +82,7 @@ def counter_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     profiles/<kernel>_<workload>_pmc.json (FETCH_SIZE and WRITE_SIZE scaled by the
     copy calibration), or None when absent or taken on different kernel sources."""
-    symbol = {"sssp_round_grid": "sssp_round"}.get(kernel, kernel)  # counter files use the kernel symbol
+    symbol = {"sssp_round_grid": "sssp_round_grid2"}.get(kernel, kernel)  # counter files use the kernel symbol
     path = os.path.join(ROOT, "profiles", f"{symbol}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -262,7 +262,9 @@ def run_serving(args, torch, synth, wc):
     def reached(gk, src):
         key = (gk, src)
         if key not in reached_cache:
-            d = ctx.sssp(dev[gk].csr, dev[gk].w, src, mode="grid")
+            # through the batch entry point, so that the single-instance grid kernels'
+            # per-launch profile stays that of the headline workload
+            d = ctx.sssp_batch([dev[gk].csr], [dev[gk].w], [src], modes=["grid"])[0]
             reached_cache[key] = int(degs[gk][d != -1].sum().item())
         return reached_cache[key]
 

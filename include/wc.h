@@ -178,10 +178,12 @@ wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *graphs, const 
                         const int32_t *src, uint32_t *const *dist, const wc_mode *modes, const wc_tune *tunes,
                         int32_t graph_rounds, hipStream_t stream, wc_stats *stats);
 
-/* Per-kernel timing.  When enabled, every kernel the library launches on a
- * context is bracketed by two HIP events recorded on the launch stream, so its
- * device execution time can be read back afterwards.  Enabling or disabling
- * waits for the device and discards earlier records. */
+/* Per-kernel timing.  When enabled, a HIP event is recorded on the launch
+ * stream after every kernel the library launches on a context, and before the
+ * first kernel of a call (and after any other stream work of the library), so
+ * each kernel's device time, dispatch gap included, can be read back
+ * afterwards.  Enabling or disabling waits for the device and discards earlier
+ * records. */
 wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable);
 
 /* Aggregate of the recorded launches of the index-th distinct kernel name (in

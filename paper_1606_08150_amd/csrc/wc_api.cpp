@@ -98,10 +98,11 @@ static hipEvent_t take_event(wc_ctx *ctx)
 static void recycle_records(wc_ctx *ctx)
 {
     for (auto &r : ctx->records) {
-        ctx->spare_events.push_back(r.start);
+        if (r.own_start) ctx->spare_events.push_back(r.start);
         ctx->spare_events.push_back(r.stop);
     }
     ctx->records.clear();
+    chain_break(ctx);
 }
 
 wc_status launch(wc_ctx *ctx, const char *name, const void *kernel, dim3 grid, dim3 block, void **args,
@@ -111,12 +112,18 @@ wc_status launch(wc_ctx *ctx, const char *name, const void *kernel, dim3 grid, d
         WC_HIP(hipLaunchKernel(kernel, grid, block, args, 0, stream));
         return WC_OK;
     }
-    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    // one event per launch: a launch that directly follows a timed launch on
+    // the same stream starts at that launch's stop event
+    const bool chained = ctx->chain_event && ctx->chain_stream == stream;
+    hipEvent_t a = chained ? ctx->chain_event : take_event(ctx);
+    hipEvent_t b = take_event(ctx);
     if (!a || !b) return fail(WC_EHIP, "hipEventCreate failed");
-    WC_HIP(hipEventRecord(a, stream));
+    if (!chained) WC_HIP(hipEventRecord(a, stream));
     WC_HIP(hipLaunchKernel(kernel, grid, block, args, 0, stream));
     WC_HIP(hipEventRecord(b, stream));
-    ctx->records.push_back({name, a, b});
+    ctx->records.push_back({name, a, b, !chained});
+    ctx->chain_event = b;
+    ctx->chain_stream = stream;
     return WC_OK;
 }
 
@@ -172,17 +179,22 @@ __global__ void zero_stats(DevStats *s)
 wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats)
 {
     if (stats) memset(stats, 0, sizeof(*stats));
+    chain_break(ctx);  // other work may have been queued since the last call
     void *args[] = {&ctx->dstats};
     wc_status st = launch(ctx, "zero_stats", reinterpret_cast<const void *>(&zero_stats), dim3(1), dim3(64), args,
                           stream);
     if (st != WC_OK) return st;
-    if (stats) WC_HIP(hipEventRecord(ctx->ev_start, stream));
+    if (stats) {
+        WC_HIP(hipEventRecord(ctx->ev_start, stream));
+        chain_break(ctx);
+    }
     return WC_OK;
 }
 
 wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow)
 {
     DevStats ds;
+    chain_break(ctx);
     if (stats) {
         WC_HIP(hipEventRecord(ctx->ev_stop, stream));
         WC_HIP(hipMemcpyAsync(&ds, ctx->dstats, sizeof(ds), hipMemcpyDeviceToHost, stream));
@@ -227,6 +239,7 @@ wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes,
         ctx->staging_bytes = sz;
     }
     std::memcpy(ctx->staging, src, bytes);
+    chain_break(ctx);
     WC_HIP(hipMemcpyAsync(dst, ctx->staging, bytes, hipMemcpyHostToDevice, stream));
     WC_HIP(hipEventRecord(ctx->staging_done, stream));
     ctx->staging_pending = true;

@@ -461,6 +461,7 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
             ctx->graph_key = key;
         }
         for (int r = 0; r <= graph_rounds; ++r) clear_round_slot(ctx, r);
+        chain_break(ctx);
         WC_HIP(hipEventRecord(ctx->graph_ready, stream));
         WC_HIP(hipStreamWaitEvent(ctx->capture_stream, ctx->graph_ready, 0));
         WC_HIP(hipGraphLaunch(ctx->graph_exec, ctx->capture_stream));

@@ -44,6 +44,7 @@ constexpr int kHostSlotGraph = kHostRing;
 struct wc_kernel_record {
     const char *name;
     hipEvent_t start, stop;
+    bool own_start;  // false: start is the previous record's stop
 };
 
 struct wc_ctx {
@@ -62,6 +63,10 @@ struct wc_ctx {
     int timing = 0;
     std::vector<wc_kernel_record> records;
     std::vector<hipEvent_t> spare_events;
+    // consecutive timed launches on one stream share an event (the stop of one
+    // is the start of the next); any other stream work breaks the chain
+    hipEvent_t chain_event = nullptr;
+    hipStream_t chain_stream = nullptr;
     // pinned staging buffer for small host-to-device descriptor uploads
     void *staging = nullptr;
     size_t staging_bytes = 0;
@@ -137,6 +142,7 @@ wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds,
 wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t stream);
 
 // Waits (bounded) until a kernel published the count of round `r` to the host ring.
+inline void chain_break(wc_ctx *ctx) { ctx->chain_event = nullptr; }
 wc_status wait_round_count(wc_ctx *ctx, int r, int *count);
 void clear_round_slot(wc_ctx *ctx, int r);
 // the same for one host-ring entry by index (0 <= index <= kHostSlotGraph)

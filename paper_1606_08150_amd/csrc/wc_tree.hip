@@ -671,6 +671,7 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
             if (e.exec && e.key == key) tg = &e;
     if (tg) {
         clear_host_slot(ctx, kHostSlotGraph);
+        chain_break(ctx);
         WC_HIP(hipEventRecord(ctx->graph_ready, stream));
         WC_HIP(hipStreamWaitEvent(ctx->capture_stream, ctx->graph_ready, 0));
         WC_HIP(hipGraphLaunch(tg->exec, ctx->capture_stream));

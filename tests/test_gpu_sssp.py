@@ -139,6 +139,39 @@ def test_stats_and_repeat_runs(ctx, c1):
                 assert st["items_buffered"] >= 1 and st["dispatches"] >= 1
 
 
+def test_kernel_timing_records(ctx, c1):
+    """Per-kernel timing: one record per launch, in launch order, with positive
+    durations that tile the call (their sum stays within the call's own elapsed
+    time), aggregates that match the records, and unchanged results."""
+    g, w, ref = c1
+    dg, dw = upload(g, w)
+    d = ctx.sssp(dg, dw, 0, mode="grid")
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    try:
+        for rep in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            d = ctx.sssp(dg, dw, 0, mode="grid", out=d)
+            b.record()
+            torch.cuda.synchronize()
+            assert np.array_equal(dev_to_u32(d), ref)
+            recs = ctx.kernel_records()
+            names = [n for n, _ in recs]
+            assert names[:2] == ["zero_stats", "sssp_init"]
+            body = names[2:]
+            assert len(body) % 2 == 0 and body[0::2] == ["sssp_round_grid"] * (len(body) // 2)
+            assert body[1::2] == ["sssp_drain"] * (len(body) // 2)
+            assert all(ms > 0 for _, ms in recs)
+            assert sum(ms for _, ms in recs) <= a.elapsed_time(b) * 1.02 + 0.01
+            kt = ctx.kernel_times()
+            assert kt["sssp_drain"][0] == len(body) // 2
+            assert abs(kt["sssp_drain"][1] - sum(ms for n, ms in recs if n == "sssp_drain")) < 1e-6
+            ctx.set_timing(True)  # discards the records
+    finally:
+        ctx.set_timing(False)
+
+
 @pytest.fixture(scope="module")
 def c2_sssp():
     say("generating scale-22 graph")
