@@ -48,6 +48,10 @@ __device__ __forceinline__ void atomic_min_dev_noret(uint32_t *p, uint32_t v)
 {
     (void)__hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void atomic_max_dev_noret(uint32_t *p, uint32_t v)
+{
+    (void)__hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int atomic_max_dev(int *p, int v)
 {
     return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -41,6 +41,7 @@ struct SsspArgs {
     const uint32_t *w;
     uint32_t *dist;
     int *stamp;       // stamp[v] == r: v is a frontier vertex of round r
+    uint32_t *relaxed_at;  // grid mode: the largest distance v's edges were last relaxed with
     int *active;      // ring of 3 flags (stride kPad): round r has a frontier
     int *chunk_tail;  // ring of 3 grid-buffer tails (stride kPad)
     int4 *chunks;     // grid consolidation buffer: (u, begin, end, 0)
@@ -117,12 +118,15 @@ __device__ __forceinline__ bool relax_wave(const SsspArgs &a, int beg, int end, 
 // Two chunks of the grid buffer at once (uniform arguments): each lane keeps
 // 2 * kUnroll edges in flight.  The chunks' source distances are read after
 // their edges are requested (they may have improved since the vertex was
-// buffered).  Chunk 1 may be empty (cb1 == ce1, u1 unused).
+// buffered); the largest distance used per chunk is returned.  Chunk 1 may be
+// empty (cb1 == ce1, u1 unused).
 __device__ __forceinline__ bool relax_wave2(const SsspArgs &a, int u0, int cb0, int ce0, int u1, int cb1, int ce1,
-                                            int next)
+                                            int next, uint32_t &du0_used, uint32_t &du1_used)
 {
     bool any = false;
     const int len = max(ce0 - cb0, ce1 - cb1);
+    du0_used = 0u;
+    du1_used = 0u;
     for (int o = lane_id(); o - lane_id() < len; o += kWave * kUnroll) {
         int v[2 * kUnroll];
         uint32_t wt[2 * kUnroll], dv[2 * kUnroll];
@@ -135,6 +139,8 @@ __device__ __forceinline__ bool relax_wave2(const SsspArgs &a, int u0, int cb0, 
         }
         const uint32_t du0 = a.dist[u0];
         const uint32_t du1 = cb1 < ce1 ? a.dist[u1] : 0u;
+        du0_used = max(du0_used, du0);
+        du1_used = max(du1_used, du1);
 #pragma unroll
         for (int k = 0; k < 2 * kUnroll; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
 #pragma unroll
@@ -158,16 +164,15 @@ struct BlockBuf {
     int base;
 };
 
-// Parent kernel of round r: thread i takes vertex i (Fig. 1(b)); the vertices
-// stamped r form the frontier.  Grid-stride windows of BLOCK vertices; every
-// thread of a block runs the same number of windows.
+// Parent kernel of round r in flat, wave and block modes: thread i takes vertex
+// i (Fig. 1(b)); the vertices stamped r form the frontier.  Grid-stride windows
+// of BLOCK vertices; every thread of a block runs the same number of windows.
 template <int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
 {
     const int act = a.active[(r % 3) * kPad];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.active[((r + 2) % 3) * kPad] = 0;
-        if (MODE == WC_GRID) a.chunk_tail[((r + 1) % 3) * kPad] = 0;
         store_system(&a.host_ring[r % kHostRing], act);
     }
     if (!act) return;
@@ -242,47 +247,6 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
                     if (v[q] >= 0) any |= relax_loaded(a, v[q], nd[q], dv[q], next);
             }
             __syncthreads();  // LDS buffer is reused by the next window
-        } else if constexpr (MODE == WC_GRID) {
-            __shared__ int s_tmp[2 * (BLOCK / kWave)];
-            __shared__ int s_base;
-            __shared__ int s_excl[BLOCK], s_beg[BLOCK], s_end[BLOCK];
-            __shared__ uint32_t s_du[BLOCK];
-            // most windows of a small frontier hold no heavy vertex: skip the scan
-            if (!__syncthreads_or(heavy ? 1 : 0)) {
-                mark_active(a, r, any);
-                continue;
-            }
-            const int nch = heavy ? (deg + a.chunk - 1) / a.chunk : 0;
-            int excl, d0, tot, d1;
-            block_scan2<BLOCK>(nch, 0, s_tmp, excl, d0, tot, d1);
-            s_excl[threadIdx.x] = excl;
-            s_beg[threadIdx.x] = beg;
-            s_end[threadIdx.x] = end;
-            s_du[threadIdx.x] = du;
-            if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
-            __syncthreads();
-            // the block writes the window's chunks together (a hub's chunks are
-            // not left to its own lane): chunk j belongs to the last thread whose
-            // offset is <= j
-            const int slot0 = s_base;
-            for (int j = threadIdx.x; j < tot; j += BLOCK) {
-                int lo = 0, hi = BLOCK - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_excl[mid] <= j) lo = mid;
-                    else hi = mid - 1;
-                }
-                const int cb = s_beg[lo] + (j - s_excl[lo]) * a.chunk;
-                const int ce = min(s_end[lo], cb + a.chunk);
-                if ((long long)slot0 + j < a.chunk_cap) {
-                    a.chunks[slot0 + j] = make_int4(base + lo, cb, ce, 0);
-                } else {
-                    // buffer full: this chunk is processed inline (fallback)
-                    a.stats->overflowed = 1;
-                    any |= relax_lane(a, cb, ce, s_du[lo], next);
-                }
-            }
-            __syncthreads();  // the LDS arrays are rewritten by the next window
         }
         mark_active(a, r, any);
     }
@@ -351,11 +315,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
         for (int k = 0; k < V; ++k) {
             beg[k] = end[k] = 0;
             du[k] = 0;
+            uint32_t ra = 0;
             if (member[k]) {
                 beg[k] = a.row_ptr[u[k]];
                 end[k] = a.row_ptr[u[k] + 1];
                 du[k] = a.dist[u[k]];
+                ra = a.relaxed_at[u[k]];
             }
+            // every edge of u was already relaxed with its present distance
+            // (it improved in the last round, but before its own relaxations
+            // read it): nothing to do
+            if (member[k] && ra == du[k]) end[k] = beg[k];
         }
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -371,6 +341,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
         // work: light items relax inline
         bool any = relax_lane2(a, beg[0], heavy[0] ? beg[0] : end[0], du[0], beg[1], heavy[1] ? beg[1] : end[1], du[1],
                                next);
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (end[k] > beg[k] && !heavy[k]) a.relaxed_at[u[k]] = du[k];
         // most windows of a small frontier hold no heavy vertex: skip the scan
         if (!__syncthreads_or((heavy[0] || heavy[1]) ? 1 : 0)) {
             mark_active(a, r, any);
@@ -388,9 +361,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
         }
         if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
         __syncthreads();
+        const int slot0 = s_base;
+        // a heavy vertex's chunks raise relaxed_at to the distances they use
+        // (drain atomics, next kernel); a chunk that overflows is relaxed here
+        // with the parent's reading
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (heavy[k]) {
+                const long long last = (long long)slot0 + s_excl[threadIdx.x * V + k] + nch[k];
+                a.relaxed_at[u[k]] = last > a.chunk_cap ? du[k] : 0u;
+            }
         // the block writes the window's chunks together: chunk j belongs to the
         // last entry whose offset is <= j
-        const int slot0 = s_base;
         for (int j = threadIdx.x; j < tot; j += BLOCK) {
             int lo = 0, hi = V * BLOCK - 1;
             while (lo < hi) {
@@ -439,7 +421,12 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
         const int cn = c + 2 * nw;
         d0 = cn < total ? a.chunks[cn] : make_int4(0, 0, 0, 0);
         d1 = cn + nw < total ? a.chunks[cn + nw] : make_int4(0, 0, 0, 0);
-        any |= relax_wave2(a, u0, cb0, ce0, u1, cb1, ce1, next);
+        uint32_t du0, du1;
+        any |= relax_wave2(a, u0, cb0, ce0, u1, cb1, ce1, next, du0, du1);
+        if (lane_id() == 0) {
+            atomic_max_dev_noret(&a.relaxed_at[u0], du0);
+            if (cb1 < ce1) atomic_max_dev_noret(&a.relaxed_at[u1], du1);
+        }
     }
     mark_active(a, r, any);
 }
@@ -450,6 +437,7 @@ __global__ void sssp_init(SsspArgs a, int src)
     for (; i < a.n; i += gridDim.x * blockDim.x) {
         a.dist[i] = i == src ? 0u : kInf;
         a.stamp[i] = i == src ? 0 : -1;
+        if (a.relaxed_at) a.relaxed_at[i] = kInf;
     }
     if (blockIdx.x == 0 && threadIdx.x < 3) {
         a.active[threadIdx.x * kPad] = threadIdx.x == 0 ? 1 : 0;
@@ -529,7 +517,7 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     // ceil(deg / chunk) chunks, so n + m / chunk + 1 entries never overflow.
     long long cap_full = n + m / chunk + 1;
     long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    size_t need = padded(n * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
+    size_t need = padded(n * 4) * (mode == WC_GRID ? 2 : 1) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     SsspArgs a;
@@ -538,6 +526,7 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     a.w = w;
     a.dist = dist;
     a.stamp = pool_take<int>(ctx, n);
+    a.relaxed_at = mode == WC_GRID ? pool_take<uint32_t>(ctx, n) : nullptr;
     a.active = pool_take<int>(ctx, 3 * kPad);
     a.chunk_tail = pool_take<int>(ctx, 3 * kPad);
     a.chunks = pool_take<int4>(ctx, cap);
