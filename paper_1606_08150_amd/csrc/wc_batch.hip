@@ -45,6 +45,7 @@ struct BatchArgs {
     int count;
     int total;         // vbase[count]
     int *stamp;        // [total]
+    uint32_t *relaxed_at;  // [total]: the largest distance the vertex's edges were last relaxed with
     int *active;       // ring of 3 (stride kPad)
     int *chunk_tail;   // ring of 3 (stride kPad)
     int4 *chunks;      // (global u, begin, end, instance)
@@ -114,6 +115,7 @@ __global__ void batch_init(BatchArgs a)
         const bool s = v == d.src;
         d.dist[v] = s ? 0u : kInf;
         a.stamp[g] = s ? 0 : -1;
+        a.relaxed_at[g] = kInf;
     }
     if (blockIdx.x == 0 && threadIdx.x < 3) {
         a.active[threadIdx.x * kPad] = threadIdx.x == 0 ? 1 : 0;
@@ -159,7 +161,13 @@ __global__ __launch_bounds__(BLOCK) void batch_round(BatchArgs a, int r)
             beg = d.row_ptr[v];
             end = d.row_ptr[v + 1];
             du = d.dist[v];
+            // already relaxed with its present distance (it improved before its
+            // own relaxations read it): nothing to do
+            if (a.relaxed_at[g] == du) end = beg;
             mode = end - beg > d.threshold ? d.mode : WC_FLAT;
+            // wave, block and inline work use this reading; grid chunks raise
+            // the value from 0 in the drain (or it stays du on overflow)
+            if (end > beg && mode != WC_GRID) a.relaxed_at[g] = du;
         }
         const int deg = end - beg;
         const bool heavy = mode != WC_FLAT;
@@ -235,9 +243,10 @@ __global__ __launch_bounds__(BLOCK) void batch_round(BatchArgs a, int r)
             sb.du[threadIdx.x] = du;
             if (threadIdx.x == 0) sb.base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
             __syncthreads();
+            const int slot0 = sb.base;
+            if (nch > 0) a.relaxed_at[g] = (long long)slot0 + excl + nch > a.chunk_cap ? du : 0u;
             // the block writes the window's chunks together: chunk j belongs to
             // the last thread whose offset is <= j
-            const int slot0 = sb.base;
             for (int j = threadIdx.x; j < tot; j += BLOCK) {
                 int lo = 0, hi = BLOCK - 1;
                 while (lo < hi) {
@@ -286,6 +295,7 @@ __global__ __launch_bounds__(BLOCK) void batch_drain(BatchArgs a, int r)
         int *sbase = a.stamp + a.vbase[i];
         for (int e0 = cb; e0 < ce; e0 += kWave * kUnroll)
             any |= relax_batch(d, sbase, e0 + lane_id(), kWave, ce, du, next);
+        if (lane_id() == 0) atomic_max_dev_noret(&a.relaxed_at[__builtin_amdgcn_readfirstlane(q.x)], du);
     }
     if (__ballot(any) && lane_id() == 0) a.active[((r + 1) % 3) * kPad] = 1;
 }
@@ -377,7 +387,7 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
     const int grid = std::max(1, std::min(resident, windows));
     const int dgrid = std::max(1, resident);
     const size_t blob = padded(sizeof(Inst) * count) + padded(4 * (count + 1));
-    size_t need = blob + padded(total * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
+    size_t need = blob + 2 * padded(total * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
     wc_status st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     BatchArgs a;
@@ -388,6 +398,7 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
     a.count = count;
     a.total = (int)total;
     a.stamp = pool_take<int>(ctx, total);
+    a.relaxed_at = pool_take<uint32_t>(ctx, total);
     a.active = pool_take<int>(ctx, 3 * kPad);
     a.chunk_tail = pool_take<int>(ctx, 3 * kPad);
     a.chunks = pool_take<int4>(ctx, cap);
