@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kPad = 32;
 constexpr int kUnroll = 4;
+constexpr int kWinInst = 256;  // vertices per entry of the instance lookup table
 
 struct Inst {
     const int *row_ptr;
@@ -42,6 +43,7 @@ struct Inst {
 struct BatchArgs {
     const Inst *inst;
     const int *vbase;  // [count + 1]
+    const int *win_inst;  // [total / kWinInst + 1]: instance owning vertex k * kWinInst
     int count;
     int total;         // vbase[count]
     int *stamp;        // [total]
@@ -56,15 +58,13 @@ struct BatchArgs {
     int has_wave, has_block, has_grid;  // which consolidation levels occur in this batch
 };
 
+// Instance owning global vertex gid: the instance owning vertex
+// (gid / kWinInst) * kWinInst, from the window table, then forward.
 __device__ __forceinline__ int find_inst(const BatchArgs &a, int gid)
 {
-    int lo = 0, hi = a.count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.vbase[mid] <= gid) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    int i = a.win_inst[gid / kWinInst];
+    while (gid >= a.vbase[i + 1]) ++i;
+    return i;
 }
 
 __device__ __forceinline__ uint32_t add_sat(uint32_t du, uint32_t w)
@@ -273,6 +273,49 @@ __global__ __launch_bounds__(BLOCK) void batch_round(BatchArgs a, int r)
     if (a.want_stats) stat_flush(a.stats, acc);
 }
 
+// Two chunks at once (uniform arguments; the chunks may belong to different
+// instances): each lane keeps 2 * kUnroll edges in flight.  The source
+// distances are read after the edges are requested; the distances used are
+// returned.  Chunk 1 may be empty (cb1 == ce1).
+__device__ __forceinline__ bool relax_pair(const BatchArgs &a, int g0, int i0, int cb0, int ce0, int g1, int i1,
+                                           int cb1, int ce1, int next, uint32_t &du0_used, uint32_t &du1_used)
+{
+    const Inst &d0 = a.inst[i0];
+    const Inst &d1 = a.inst[i1];
+    const int vb0 = a.vbase[i0], vb1 = a.vbase[i1];
+    int *sb0 = a.stamp + vb0;
+    int *sb1 = a.stamp + vb1;
+    bool any = false;
+    du0_used = du1_used = 0u;
+    const int len = max(ce0 - cb0, ce1 - cb1);
+    for (int o = lane_id(); o - lane_id() < len; o += kWave * kUnroll) {
+        int v[2 * kUnroll];
+        uint32_t wt[2 * kUnroll], dv[2 * kUnroll];
+#pragma unroll
+        for (int k = 0; k < 2 * kUnroll; ++k) {
+            const bool first = k < kUnroll;
+            const int e = (first ? cb0 : cb1) + o + (k % kUnroll) * kWave;
+            const bool ok = e < (first ? ce0 : ce1);
+            v[k] = ok ? (first ? d0.col[e] : d1.col[e]) : -1;
+            wt[k] = ok ? (first ? d0.w[e] : d1.w[e]) : 0u;
+        }
+        const uint32_t du0 = d0.dist[g0 - vb0];
+        const uint32_t du1 = cb1 < ce1 ? d1.dist[g1 - vb1] : 0u;
+        du0_used = max(du0_used, du0);
+        du1_used = max(du1_used, du1);
+#pragma unroll
+        for (int k = 0; k < 2 * kUnroll; ++k) dv[k] = v[k] >= 0 ? (k < kUnroll ? d0.dist[v[k]] : d1.dist[v[k]]) : 0u;
+#pragma unroll
+        for (int k = 0; k < 2 * kUnroll; ++k)
+            if (v[k] >= 0) {
+                const bool first = k < kUnroll;
+                any |= relax_loaded(first ? d0.dist : d1.dist, first ? sb0 : sb1, v[k],
+                                    add_sat(first ? du0 : du1, wt[k]), dv[k], next);
+            }
+    }
+    return any;
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void batch_drain(BatchArgs a, int r)
 {
@@ -285,17 +328,25 @@ __global__ __launch_bounds__(BLOCK) void batch_drain(BatchArgs a, int r)
     if (a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0)
         atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
     bool any = false;
-    for (int c = gw; c < total; c += nw) {
-        const int4 q = a.chunks[c];
-        const int i = __builtin_amdgcn_readfirstlane(q.w);
-        const int cb = __builtin_amdgcn_readfirstlane(q.y), ce = __builtin_amdgcn_readfirstlane(q.z);
-        const Inst &d = a.inst[i];
-        const int u = __builtin_amdgcn_readfirstlane(q.x) - a.vbase[i];
-        const uint32_t du = d.dist[u];
-        int *sbase = a.stamp + a.vbase[i];
-        for (int e0 = cb; e0 < ce; e0 += kWave * kUnroll)
-            any |= relax_batch(d, sbase, e0 + lane_id(), kWave, ce, du, next);
-        if (lane_id() == 0) atomic_max_dev_noret(&a.relaxed_at[__builtin_amdgcn_readfirstlane(q.x)], du);
+    // two chunks per wave and step; the next pair's entries are fetched before
+    // the current pair's edges
+    const int4 zero = make_int4(0, 0, 0, 0);
+    int4 q0 = gw < total ? a.chunks[gw] : zero;
+    int4 q1 = gw + nw < total ? a.chunks[gw + nw] : zero;
+    for (int c = gw; c < total; c += 2 * nw) {
+        const int g0 = __builtin_amdgcn_readfirstlane(q0.x), i0 = __builtin_amdgcn_readfirstlane(q0.w);
+        const int cb0 = __builtin_amdgcn_readfirstlane(q0.y), ce0 = __builtin_amdgcn_readfirstlane(q0.z);
+        const int g1 = __builtin_amdgcn_readfirstlane(q1.x), i1 = __builtin_amdgcn_readfirstlane(q1.w);
+        const int cb1 = __builtin_amdgcn_readfirstlane(q1.y), ce1 = __builtin_amdgcn_readfirstlane(q1.z);
+        const int cn = c + 2 * nw;
+        q0 = cn < total ? a.chunks[cn] : zero;
+        q1 = cn + nw < total ? a.chunks[cn + nw] : zero;
+        uint32_t du0, du1;
+        any |= relax_pair(a, g0, i0, cb0, ce0, g1, i1, cb1, ce1, next, du0, du1);
+        if (lane_id() == 0) {
+            atomic_max_dev_noret(&a.relaxed_at[g0], du0);
+            if (cb1 < ce1) atomic_max_dev_noret(&a.relaxed_at[g1], du1);
+        }
     }
     if (__ballot(any) && lane_id() == 0) a.active[((r + 1) % 3) * kPad] = 1;
 }
@@ -386,7 +437,8 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
     const int windows = (int)((total + block - 1) / block);
     const int grid = std::max(1, std::min(resident, windows));
     const int dgrid = std::max(1, resident);
-    const size_t blob = padded(sizeof(Inst) * count) + padded(4 * (count + 1));
+    const long long nwin = total / kWinInst + 1;
+    const size_t blob = padded(sizeof(Inst) * count) + padded(4 * (count + 1)) + padded(4 * nwin);
     size_t need = blob + 2 * padded(total * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
     wc_status st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
@@ -395,6 +447,7 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
     char *d_blob = pool_take<char>(ctx, blob);
     a.inst = reinterpret_cast<const Inst *>(d_blob);
     a.vbase = reinterpret_cast<const int *>(d_blob + padded(sizeof(Inst) * count));
+    a.win_inst = reinterpret_cast<const int *>(d_blob + padded(sizeof(Inst) * count) + padded(4 * (count + 1)));
     a.count = count;
     a.total = (int)total;
     a.stamp = pool_take<int>(ctx, total);
@@ -413,6 +466,15 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
     std::vector<char> host_blob(blob, 0);
     std::memcpy(host_blob.data(), inst.data(), sizeof(Inst) * count);
     std::memcpy(host_blob.data() + padded(sizeof(Inst) * count), vbase.data(), 4 * (count + 1));
+    {
+        int *win = reinterpret_cast<int *>(host_blob.data() + padded(sizeof(Inst) * count) + padded(4 * (count + 1)));
+        int i = 0;
+        for (long long k = 0; k < nwin; ++k) {
+            const long long v = k * kWinInst;
+            while (i + 1 < count && v >= vbase[i + 1]) ++i;
+            win[k] = i;
+        }
+    }
     st = stage_to_device(ctx, d_blob, host_blob.data(), blob, stream);
     if (st != WC_OK) return st;
     st = begin_call(ctx, stream, stats);
