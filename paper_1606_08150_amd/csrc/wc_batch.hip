@@ -149,126 +149,142 @@ __global__ __launch_bounds__(BLOCK) void batch_round(BatchArgs a, int r)
     const int next = r + 1;
     const int lane = lane_id();
     StatAcc acc;
-    for (int base = blockIdx.x * BLOCK; base < a.total; base += gridDim.x * BLOCK) {
-        const int g = base + threadIdx.x;
-        const bool member = g < a.total && a.stamp[g] == r;
-        int i = 0, beg = 0, end = 0, mode = WC_FLAT;
-        uint32_t du = 0;
-        if (member) {
-            i = find_inst(a, g);
-            const Inst &d = a.inst[i];
-            const int v = g - a.vbase[i];
-            beg = d.row_ptr[v];
-            end = d.row_ptr[v + 1];
-            du = d.dist[v];
-            // already relaxed with its present distance (it improved before its
-            // own relaxations read it): nothing to do
-            if (a.relaxed_at[g] == du) end = beg;
-            mode = end - beg > d.threshold ? d.mode : WC_FLAT;
-            // wave, block and inline work use this reading; grid chunks raise
-            // the value from 0 in the drain (or it stays du on overflow)
-            if (end > beg && mode != WC_GRID) a.relaxed_at[g] = du;
+    // the stamps of S windows are read together and a block skips all S at
+    // once when none of them holds a frontier vertex
+    constexpr int S = 8;
+    const int stride = gridDim.x * BLOCK;
+    for (long long wbase = (long long)blockIdx.x * BLOCK; wbase < a.total; wbase += (long long)S * stride) {
+        int bits = 0;
+#pragma unroll
+        for (int w = 0; w < S; ++w) {
+            const long long gg = wbase + (long long)w * stride + threadIdx.x;
+            if (gg < a.total && a.stamp[gg] == r) bits |= 1 << w;
         }
-        const int deg = end - beg;
-        const bool heavy = mode != WC_FLAT;
-        if (a.want_stats) {
-            acc.edges += deg;
-            acc.buffered += heavy ? deg : 0;
-            acc.items += heavy ? 1 : 0;
-        }
-        bool any = false;
-        if (member && !heavy) any = [&] {
-            const Inst &d = a.inst[i];
-            int *sbase = a.stamp + a.vbase[i];
-            bool f = false;
-            for (int e = beg; e < end; e += kUnroll) f |= relax_batch(d, sbase, e, 1, end, du, next);
-            return f;
-        }();
-        // wave-level items: the ballot mask is the buffer, the wave drains it
-        uint64_t wmask = a.has_wave ? __ballot(mode == WC_WAVE) : 0ull;
-        if (a.want_stats && wmask && lane == 0) acc.dispatches += 1;
-        while (wmask) {
-            const int b = __builtin_ctzll(wmask);
-            wmask &= wmask - 1;
-            const int ii = readlane(i, b);
-            const Inst &d = a.inst[ii];
-            int *sbase = a.stamp + a.vbase[ii];
-            const int ub = readlane(beg, b), ue = readlane(end, b);
-            const uint32_t ud = readlane_u(du, b);
-            for (int e0 = ub; e0 < ue; e0 += kWave * kUnroll)
-                any |= relax_batch(d, sbase, e0 + lane, kWave, ue, ud, next);
-        }
-        // block-level items: LDS buffer, barrier, flattened drain by the block
-        if (a.has_block) {
-            const bool bl = mode == WC_BLOCK;
-            int k, off, nb, total;
-            block_scan2<BLOCK>(bl ? 1 : 0, bl ? deg : 0, sb.scan_tmp, k, off, nb, total);
-            if (bl) {
-                sb.inst[k] = i;
-                sb.beg[k] = beg;
-                sb.du[k] = du;
-                sb.pre[k] = off;
+        if (!__syncthreads_or(bits)) continue;
+        for (int w = 0; w < S; ++w) {
+            const long long base_l = wbase + (long long)w * stride;
+            if (base_l >= a.total) break;  // uniform in the block
+            const int base = (int)base_l;
+            const int g = base + threadIdx.x;
+            const bool member = (bits >> w) & 1;
+            int i = 0, beg = 0, end = 0, mode = WC_FLAT;
+            uint32_t du = 0;
+            if (member) {
+                i = find_inst(a, g);
+                const Inst &d = a.inst[i];
+                const int v = g - a.vbase[i];
+                beg = d.row_ptr[v];
+                end = d.row_ptr[v + 1];
+                du = d.dist[v];
+                // already relaxed with its present distance (it improved before its
+                // own relaxations read it): nothing to do
+                if (a.relaxed_at[g] == du) end = beg;
+                mode = end - beg > d.threshold ? d.mode : WC_FLAT;
+                // wave, block and inline work use this reading; grid chunks raise
+                // the value from 0 in the drain (or it stays du on overflow)
+                if (end > beg && mode != WC_GRID) a.relaxed_at[g] = du;
             }
-            if (threadIdx.x == 0) {
-                sb.pre[nb] = total;
-                if (a.want_stats && nb) acc.dispatches += 1;
+            const int deg = end - beg;
+            const bool heavy = mode != WC_FLAT;
+            if (a.want_stats) {
+                acc.edges += deg;
+                acc.buffered += heavy ? deg : 0;
+                acc.items += heavy ? 1 : 0;
             }
-            __syncthreads();
-            int it = 0;
-            for (int j = threadIdx.x; j < total; j += BLOCK) {
-                while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
-                const Inst &d = a.inst[sb.inst[it]];
-                const int e = sb.beg[it] + (j - sb.pre[it]);
-                const int v = d.col[e];
-                const uint32_t nd = add_sat(sb.du[it], d.w[e]);
-                any |= relax_loaded(d.dist, a.stamp + a.vbase[sb.inst[it]], v, nd, d.dist[v], next);
+            bool any = false;
+            if (member && !heavy) any = [&] {
+                const Inst &d = a.inst[i];
+                int *sbase = a.stamp + a.vbase[i];
+                bool f = false;
+                for (int e = beg; e < end; e += kUnroll) f |= relax_batch(d, sbase, e, 1, end, du, next);
+                return f;
+            }();
+            // wave-level items: the ballot mask is the buffer, the wave drains it
+            uint64_t wmask = a.has_wave ? __ballot(mode == WC_WAVE) : 0ull;
+            if (a.want_stats && wmask && lane == 0) acc.dispatches += 1;
+            while (wmask) {
+                const int b = __builtin_ctzll(wmask);
+                wmask &= wmask - 1;
+                const int ii = readlane(i, b);
+                const Inst &d = a.inst[ii];
+                int *sbase = a.stamp + a.vbase[ii];
+                const int ub = readlane(beg, b), ue = readlane(end, b);
+                const uint32_t ud = readlane_u(du, b);
+                for (int e0 = ub; e0 < ue; e0 += kWave * kUnroll)
+                    any |= relax_batch(d, sbase, e0 + lane, kWave, ue, ud, next);
             }
-            __syncthreads();
-        }
-        // grid-level items: chunks into the global buffer (block-aggregated reservation)
-        if (a.has_grid) {
-            const bool gr = mode == WC_GRID;
-            int chunk = 1, nch = 0;
-            if (gr) {
-                chunk = a.inst[i].chunk;
-                nch = (deg + chunk - 1) / chunk;
-            }
-            int excl, d0, tot, d1;
-            block_scan2<BLOCK>(nch, 0, sb.scan_tmp, excl, d0, tot, d1);
-            sb.pre[threadIdx.x] = excl;
-            sb.inst[threadIdx.x] = i;
-            sb.beg[threadIdx.x] = beg;
-            sb.end[threadIdx.x] = end;
-            sb.csz[threadIdx.x] = chunk;
-            sb.du[threadIdx.x] = du;
-            if (threadIdx.x == 0) sb.base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
-            __syncthreads();
-            const int slot0 = sb.base;
-            if (nch > 0) a.relaxed_at[g] = (long long)slot0 + excl + nch > a.chunk_cap ? du : 0u;
-            // the block writes the window's chunks together: chunk j belongs to
-            // the last thread whose offset is <= j
-            for (int j = threadIdx.x; j < tot; j += BLOCK) {
-                int lo = 0, hi = BLOCK - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (sb.pre[mid] <= j) lo = mid;
-                    else hi = mid - 1;
+            // block-level items: LDS buffer, barrier, flattened drain by the block
+            if (a.has_block) {
+                const bool bl = mode == WC_BLOCK;
+                int k, off, nb, total;
+                block_scan2<BLOCK>(bl ? 1 : 0, bl ? deg : 0, sb.scan_tmp, k, off, nb, total);
+                if (bl) {
+                    sb.inst[k] = i;
+                    sb.beg[k] = beg;
+                    sb.du[k] = du;
+                    sb.pre[k] = off;
                 }
-                const int ck = sb.csz[lo];
-                const int cb = sb.beg[lo] + (j - sb.pre[lo]) * ck, ce = min(sb.end[lo], cb + ck);
-                const int oi = sb.inst[lo];
-                if ((long long)slot0 + j < a.chunk_cap) {
-                    a.chunks[slot0 + j] = make_int4(base + lo, cb, ce, oi);
-                } else {
-                    a.stats->overflowed = 1;
-                    const Inst &d = a.inst[oi];
-                    int *sbase = a.stamp + a.vbase[oi];
-                    for (int e = cb; e < ce; e += kUnroll) any |= relax_batch(d, sbase, e, 1, ce, sb.du[lo], next);
+                if (threadIdx.x == 0) {
+                    sb.pre[nb] = total;
+                    if (a.want_stats && nb) acc.dispatches += 1;
                 }
+                __syncthreads();
+                int it = 0;
+                for (int j = threadIdx.x; j < total; j += BLOCK) {
+                    while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
+                    const Inst &d = a.inst[sb.inst[it]];
+                    const int e = sb.beg[it] + (j - sb.pre[it]);
+                    const int v = d.col[e];
+                    const uint32_t nd = add_sat(sb.du[it], d.w[e]);
+                    any |= relax_loaded(d.dist, a.stamp + a.vbase[sb.inst[it]], v, nd, d.dist[v], next);
+                }
+                __syncthreads();
             }
-            __syncthreads();
+            // grid-level items: chunks into the global buffer (block-aggregated reservation)
+            if (a.has_grid) {
+                const bool gr = mode == WC_GRID;
+                int chunk = 1, nch = 0;
+                if (gr) {
+                    chunk = a.inst[i].chunk;
+                    nch = (deg + chunk - 1) / chunk;
+                }
+                int excl, d0, tot, d1;
+                block_scan2<BLOCK>(nch, 0, sb.scan_tmp, excl, d0, tot, d1);
+                sb.pre[threadIdx.x] = excl;
+                sb.inst[threadIdx.x] = i;
+                sb.beg[threadIdx.x] = beg;
+                sb.end[threadIdx.x] = end;
+                sb.csz[threadIdx.x] = chunk;
+                sb.du[threadIdx.x] = du;
+                if (threadIdx.x == 0) sb.base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
+                __syncthreads();
+                const int slot0 = sb.base;
+                if (nch > 0) a.relaxed_at[g] = (long long)slot0 + excl + nch > a.chunk_cap ? du : 0u;
+                // the block writes the window's chunks together: chunk j belongs to
+                // the last thread whose offset is <= j
+                for (int j = threadIdx.x; j < tot; j += BLOCK) {
+                    int lo = 0, hi = BLOCK - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sb.pre[mid] <= j) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const int ck = sb.csz[lo];
+                    const int cb = sb.beg[lo] + (j - sb.pre[lo]) * ck, ce = min(sb.end[lo], cb + ck);
+                    const int oi = sb.inst[lo];
+                    if ((long long)slot0 + j < a.chunk_cap) {
+                        a.chunks[slot0 + j] = make_int4(base + lo, cb, ce, oi);
+                    } else {
+                        a.stats->overflowed = 1;
+                        const Inst &d = a.inst[oi];
+                        int *sbase = a.stamp + a.vbase[oi];
+                        for (int e = cb; e < ce; e += kUnroll) any |= relax_batch(d, sbase, e, 1, ce, sb.du[lo], next);
+                    }
+                }
+                __syncthreads();
+            }
+            if (__ballot(any) && lane == 0) a.active[((r + 1) % 3) * kPad] = 1;
         }
-        if (__ballot(any) && lane == 0) a.active[((r + 1) % 3) * kPad] = 1;
     }
     if (a.want_stats) stat_flush(a.stats, acc);
 }

@@ -302,96 +302,115 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     if (!act) return;
     const int next = r + 1;
     StatAcc acc;
-    for (int base = blockIdx.x * V * BLOCK; base < a.n; base += gridDim.x * V * BLOCK) {
-        int u[V], beg[V], end[V], nch[V];
-        uint32_t du[V];
-        bool member[V], heavy[V];
+    // the stamps of S windows are read together and a block skips all S at
+    // once when none of them holds a frontier vertex (late rounds scan an
+    // almost empty frontier)
+    constexpr int S = 4;
+    const int stride = gridDim.x * V * BLOCK;
+    for (long long wbase = (long long)blockIdx.x * V * BLOCK; wbase < a.n; wbase += (long long)S * stride) {
+        int bits = 0;
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            u[k] = base + k * BLOCK + threadIdx.x;
-            member[k] = u[k] < a.n && a.stamp[u[k]] == r;
-        }
+        for (int w = 0; w < S; ++w)
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            beg[k] = end[k] = 0;
-            du[k] = 0;
-            uint32_t ra = 0;
-            if (member[k]) {
-                beg[k] = a.row_ptr[u[k]];
-                end[k] = a.row_ptr[u[k] + 1];
-                du[k] = a.dist[u[k]];
-                ra = a.relaxed_at[u[k]];
+            for (int k = 0; k < V; ++k) {
+                const long long uu = wbase + (long long)w * stride + k * BLOCK + threadIdx.x;
+                if (uu < a.n && a.stamp[uu] == r) bits |= 1 << (w * V + k);
             }
-            // every edge of u was already relaxed with its present distance
-            // (it improved in the last round, but before its own relaxations
-            // read it): nothing to do
-            if (member[k] && ra == du[k]) end[k] = beg[k];
-        }
+        if (!__syncthreads_or(bits)) continue;
+        for (int w = 0; w < S; ++w) {
+            const long long base_l = wbase + (long long)w * stride;
+            if (base_l >= a.n) break;  // uniform in the block
+            const int base = (int)base_l;
+            int u[V], beg[V], end[V], nch[V];
+            uint32_t du[V];
+            bool member[V], heavy[V];
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const int deg = end[k] - beg[k];
-            heavy[k] = deg > a.threshold;
-            nch[k] = heavy[k] ? (deg + a.chunk - 1) / a.chunk : 0;
-            if (a.want_stats) {
-                acc.edges += deg;
-                acc.buffered += heavy[k] ? deg : 0;
-                acc.items += heavy[k] ? 1 : 0;
+            for (int k = 0; k < V; ++k) {
+                u[k] = base + k * BLOCK + threadIdx.x;
+                member[k] = (bits >> (w * V + k)) & 1;
             }
-        }
-        // work: light items relax inline
-        bool any = relax_lane2(a, beg[0], heavy[0] ? beg[0] : end[0], du[0], beg[1], heavy[1] ? beg[1] : end[1], du[1],
-                               next);
 #pragma unroll
-        for (int k = 0; k < V; ++k)
-            if (end[k] > beg[k] && !heavy[k]) a.relaxed_at[u[k]] = du[k];
-        // most windows of a small frontier hold no heavy vertex: skip the scan
-        if (!__syncthreads_or((heavy[0] || heavy[1]) ? 1 : 0)) {
+            for (int k = 0; k < V; ++k) {
+                beg[k] = end[k] = 0;
+                du[k] = 0;
+                uint32_t ra = 0;
+                if (member[k]) {
+                    beg[k] = a.row_ptr[u[k]];
+                    end[k] = a.row_ptr[u[k] + 1];
+                    du[k] = a.dist[u[k]];
+                    ra = a.relaxed_at[u[k]];
+                }
+                // every edge of u was already relaxed with its present distance
+                // (it improved in the last round, but before its own relaxations
+                // read it): nothing to do
+                if (member[k] && ra == du[k]) end[k] = beg[k];
+            }
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const int deg = end[k] - beg[k];
+                heavy[k] = deg > a.threshold;
+                nch[k] = heavy[k] ? (deg + a.chunk - 1) / a.chunk : 0;
+                if (a.want_stats) {
+                    acc.edges += deg;
+                    acc.buffered += heavy[k] ? deg : 0;
+                    acc.items += heavy[k] ? 1 : 0;
+                }
+            }
+            // work: light items relax inline
+            bool any = relax_lane2(a, beg[0], heavy[0] ? beg[0] : end[0], du[0], beg[1], heavy[1] ? beg[1] : end[1], du[1],
+                                   next);
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (end[k] > beg[k] && !heavy[k]) a.relaxed_at[u[k]] = du[k];
+            // most windows of a small frontier hold no heavy vertex: skip the scan
+            if (!__syncthreads_or((heavy[0] || heavy[1]) ? 1 : 0)) {
+                mark_active(a, r, any);
+                continue;
+            }
+            int excl, d0, tot, d1;
+            block_scan2<BLOCK>(nch[0] + nch[1], 0, s_tmp, excl, d0, tot, d1);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                const int q = threadIdx.x * V + k;  // entries in (thread, vertex) order
+                s_excl[q] = excl + (k == 0 ? 0 : nch[0]);
+                s_beg[q] = beg[k];
+                s_end[q] = end[k];
+                s_du[q] = du[k];
+            }
+            if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
+            __syncthreads();
+            const int slot0 = s_base;
+            // a heavy vertex's chunks raise relaxed_at to the distances they use
+            // (drain atomics, next kernel); a chunk that overflows is relaxed here
+            // with the parent's reading
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (heavy[k]) {
+                    const long long last = (long long)slot0 + s_excl[threadIdx.x * V + k] + nch[k];
+                    a.relaxed_at[u[k]] = last > a.chunk_cap ? du[k] : 0u;
+                }
+            // the block writes the window's chunks together: chunk j belongs to the
+            // last entry whose offset is <= j
+            for (int j = threadIdx.x; j < tot; j += BLOCK) {
+                int lo = 0, hi = V * BLOCK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_excl[mid] <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int cb = s_beg[lo] + (j - s_excl[lo]) * a.chunk;
+                const int ce = min(s_end[lo], cb + a.chunk);
+                if ((long long)slot0 + j < a.chunk_cap) {
+                    a.chunks[slot0 + j] = make_int4(base + (lo % V) * BLOCK + lo / V, cb, ce, 0);
+                } else {
+                    // buffer full: this chunk is processed inline (fallback)
+                    a.stats->overflowed = 1;
+                    any |= relax_lane(a, cb, ce, s_du[lo], next);
+                }
+            }
+            __syncthreads();  // the LDS arrays are rewritten by the next window
             mark_active(a, r, any);
-            continue;
         }
-        int excl, d0, tot, d1;
-        block_scan2<BLOCK>(nch[0] + nch[1], 0, s_tmp, excl, d0, tot, d1);
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const int q = threadIdx.x * V + k;  // entries in (thread, vertex) order
-            s_excl[q] = excl + (k == 0 ? 0 : nch[0]);
-            s_beg[q] = beg[k];
-            s_end[q] = end[k];
-            s_du[q] = du[k];
-        }
-        if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
-        __syncthreads();
-        const int slot0 = s_base;
-        // a heavy vertex's chunks raise relaxed_at to the distances they use
-        // (drain atomics, next kernel); a chunk that overflows is relaxed here
-        // with the parent's reading
-#pragma unroll
-        for (int k = 0; k < V; ++k)
-            if (heavy[k]) {
-                const long long last = (long long)slot0 + s_excl[threadIdx.x * V + k] + nch[k];
-                a.relaxed_at[u[k]] = last > a.chunk_cap ? du[k] : 0u;
-            }
-        // the block writes the window's chunks together: chunk j belongs to the
-        // last entry whose offset is <= j
-        for (int j = threadIdx.x; j < tot; j += BLOCK) {
-            int lo = 0, hi = V * BLOCK - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_excl[mid] <= j) lo = mid;
-                else hi = mid - 1;
-            }
-            const int cb = s_beg[lo] + (j - s_excl[lo]) * a.chunk;
-            const int ce = min(s_end[lo], cb + a.chunk);
-            if ((long long)slot0 + j < a.chunk_cap) {
-                a.chunks[slot0 + j] = make_int4(base + (lo % V) * BLOCK + lo / V, cb, ce, 0);
-            } else {
-                // buffer full: this chunk is processed inline (fallback)
-                a.stats->overflowed = 1;
-                any |= relax_lane(a, cb, ce, s_du[lo], next);
-            }
-        }
-        __syncthreads();  // the LDS arrays are rewritten by the next window
-        mark_active(a, r, any);
     }
     if (a.want_stats) stat_flush(a.stats, acc);
 }
