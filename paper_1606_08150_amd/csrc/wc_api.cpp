@@ -314,15 +314,18 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
         return fail(WC_EINVAL, std::string("unknown problem ") + problem);
     if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "mode must be flat, wave, block or grid");
     out->threshold = default_threshold(problem, mode);
-    // grid-level SSSP and SpMV: 512-thread workgroups measured fastest on the
-    // scale-22 graph; everything else 256
-    out->block_threads = (mode == WC_GRID && strcmp(problem, "tree")) ? 512 : 256;
+    // grid level: 512-thread workgroups measured fastest (scale-22 graph,
+    // 2^22-node tree); everything else 256
+    out->block_threads = mode == WC_GRID ? 512 : 256;
     // The drain grid of every mode is the resident maximum (KC_1 of Sec. IV.E):
     // wave- and block-level drains run inside the parent groups, which are
     // already resident, so no downgrade for concurrency is needed.
     out->grid_blocks = resident_blocks > 0 ? resident_blocks : 1;
     out->items_per_lane = 4;  // "const" of Sec. IV.E
     if (mode == WC_GRID && !strcmp(problem, "spmv")) out->items_per_lane = 8;
+    // tree items are child ranges: most nodes have a few children, and shorter
+    // chunks split the few wide nodes over more waves (measured on 2^22 nodes)
+    if (mode == WC_GRID && !strcmp(problem, "tree")) out->items_per_lane = 2;
     out->driver = 0;
     out->allow_fallback = 0;
     out->buf_capacity = 0;

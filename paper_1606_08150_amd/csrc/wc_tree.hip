@@ -100,7 +100,7 @@ __global__ void tree_init_levels(TreeArgs a)
             int nch = (f + a.chunk - 1) / a.chunk;
             for (int c = 0; c < nch; ++c) {
                 int cb = a.child_ptr[0] + c * a.chunk;
-                a.items[c] = make_int4(0, cb, min(cb + a.chunk, a.child_ptr[1]), 0);
+                a.items[c] = make_int4(0, cb, min(cb + a.chunk, a.child_ptr[1]), nch == 1);
             }
             a.lvl_count[0] = nch;
         }
@@ -122,6 +122,15 @@ __global__ void tree_init_levels_flat(TreeArgs a)
     }
 }
 
+// Items per block tile in the grid-mode level passes: up to BLOCK, fewer when
+// the level is small, so that every block of the grid gets work.
+template <int BLOCK>
+__device__ __forceinline__ int tile_items(int count)
+{
+    const int per_block = (count + (int)gridDim.x - 1) / (int)gridDim.x;
+    return max(1, min(BLOCK, per_block));
+}
+
 // Top-down step of level l: children of the level's buffered nodes.  Internal
 // children are inserted into level l+1's buffer, leaves get the leaf work.
 template <int MODE, int BLOCK>
@@ -130,30 +139,57 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count, StatA
     const int out_base = start + count;
     int *cnt_next = &a.lvl_count[l + 1];
     if constexpr (MODE == WC_GRID) {
-        const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
-        const int nw = gridDim.x * (BLOCK / kWave);
-        for (int it = gw; it < count; it += nw) {
-            int4 d = a.items[start + it];
-            const int cb = __builtin_amdgcn_readfirstlane(d.y), ce = __builtin_amdgcn_readfirstlane(d.z);
-            if (a.want_stats && lane_id() == 0) acc.edges += ce - cb;
-            for (int b = cb; b < ce; b += kWave) {
-                const int e = b + lane_id();
+        // The block takes a tile of buffered items at a time and walks their
+        // children as one flattened range (most items have a few children), so
+        // the next level's buffer is reserved with one atomic per BLOCK
+        // children instead of one per item.
+        __shared__ int s_pre[BLOCK], s_cb[BLOCK], s_tmp[2 * (BLOCK / kWave)];
+        __shared__ int s_base;
+        const int T = tile_items<BLOCK>(count);
+        for (int tile = blockIdx.x * T; tile < count; tile += gridDim.x * T) {
+            const int it = tile + threadIdx.x;
+            int cb = 0, len = 0;
+            if ((int)threadIdx.x < T && it < count) {
+                const int4 d = a.items[start + it];
+                cb = d.y;
+                len = d.z - d.y;
+            }
+            if (a.want_stats) acc.edges += len;
+            int excl, e0, total, e1;
+            block_scan2<BLOCK>(len, 0, s_tmp, excl, e0, total, e1);
+            s_pre[threadIdx.x] = excl;
+            s_cb[threadIdx.x] = cb;
+            __syncthreads();
+            for (int j0 = 0; j0 < total; j0 += BLOCK) {
+                const int j = j0 + threadIdx.x;
                 int c = -1, f = 0;
-                if (e < ce) {
-                    c = a.child[e];
+                if (j < total) {
+                    // owner: the last item whose offset is <= j
+                    int lo = 0, hi = BLOCK - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= j) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    c = a.child[s_cb[lo] + (j - s_pre[lo])];
                     f = fanout(a, c);
                     a.out[c] = 0;  // leaf work, or the identity the folds start from
                 }
                 const int nch = f > 0 ? (f + a.chunk - 1) / a.chunk : 0;
-                const int slot = wave_reserve_n(nch, cnt_next);
                 if (a.want_stats) acc.items += f > 0 ? 1 : 0;
+                int x0, x1, tot, x2;
+                block_scan2<BLOCK>(nch, 0, s_tmp, x0, x1, tot, x2);
+                if (threadIdx.x == 0) s_base = tot ? atomic_add_dev(cnt_next, tot) : 0;
+                __syncthreads();
+                const int slot = s_base + x0;
                 if (nch > 0) {
                     const int c0 = a.child_ptr[c];
                     for (int k = 0; k < nch; ++k) {
-                        int kb = c0 + k * a.chunk;
-                        a.items[out_base + slot + k] = make_int4(c, kb, min(kb + a.chunk, c0 + f), 0);
+                        const int kb = c0 + k * a.chunk;
+                        a.items[out_base + slot + k] = make_int4(c, kb, min(kb + a.chunk, c0 + f), nch == 1);
                     }
                 }
+                __syncthreads();  // s_base is rewritten by the next step
             }
         }
     } else {
@@ -177,16 +213,45 @@ template <int MODE, int OP, int BLOCK>
 __device__ void level_up(const TreeArgs &a, int start, int count)
 {
     if constexpr (MODE == WC_GRID) {
-        const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
-        const int nw = gridDim.x * (BLOCK / kWave);
-        for (int it = gw; it < count; it += nw) {
-            int4 d = a.items[start + it];
-            const int p = __builtin_amdgcn_readfirstlane(d.x);
-            const int cb = __builtin_amdgcn_readfirstlane(d.y), ce = __builtin_amdgcn_readfirstlane(d.z);
-            int acc = 0;
-            for (int e = cb + lane_id(); e < ce; e += kWave) acc = fold<OP>(acc, a.out[a.child[e]]);
-            acc = OP == OP_DESC ? wave_sum_i(acc) : wave_max_i(acc);
-            if (lane_id() == 0) atomic_fold<OP>(&a.out[p], acc);
+        // tiles of items as in the top-down pass: the children's values are
+        // folded per item in LDS, then one atomic per item folds into its node
+        __shared__ int s_pre[BLOCK], s_cb[BLOCK], s_acc[BLOCK], s_tmp[2 * (BLOCK / kWave)];
+        const int T = tile_items<BLOCK>(count);
+        for (int tile = blockIdx.x * T; tile < count; tile += gridDim.x * T) {
+            const int it = tile + threadIdx.x;
+            int p = -1, cb = 0, len = 0, whole = 0;
+            if ((int)threadIdx.x < T && it < count) {
+                const int4 d = a.items[start + it];
+                p = d.x;
+                cb = d.y;
+                len = d.z - d.y;
+                whole = d.w;
+            }
+            int excl, e0, total, e1;
+            block_scan2<BLOCK>(len, 0, s_tmp, excl, e0, total, e1);
+            s_pre[threadIdx.x] = excl;
+            s_cb[threadIdx.x] = cb;
+            s_acc[threadIdx.x] = 0;
+            __syncthreads();
+            for (int j = threadIdx.x; j < total; j += BLOCK) {
+                int lo = 0, hi = BLOCK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int v = 1 + a.out[a.child[s_cb[lo] + (j - s_pre[lo])]];
+                if (OP == OP_DESC) atomicAdd(&s_acc[lo], v);
+                else atomicMax(&s_acc[lo], v);
+            }
+            __syncthreads();
+            // an item holding all of its node's children is the node's only
+            // contribution: a plain store; split nodes fold atomically
+            if (p >= 0) {
+                if (whole) a.out[p] = s_acc[threadIdx.x];
+                else atomic_fold<OP>(&a.out[p], s_acc[threadIdx.x]);
+            }
+            __syncthreads();  // the LDS arrays are rewritten by the next tile
         }
     } else {
         for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
@@ -565,7 +630,8 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
                    wc_stats *stats)
 {
     TreeKernels<OP, BLOCK> ks = kernels_for<OP, BLOCK>(mode);
-    const void *main_kernel = ks.queue ? ks.queue : ks.persistent;
+    // the grid is sized to the residency of the kernel that runs: the queue kernel, or the level kernels
+    const void *main_kernel = ks.queue ? ks.queue : (cfg.driver == 1 ? ks.persistent : ks.down);
     const int resident = resident_blocks(ctx, main_kernel, BLOCK);
     const int grid = std::max(1, std::min(cfg.grid, resident));
     const long long n = t->n;
