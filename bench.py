@@ -59,22 +59,25 @@ def parse():
 def algorithmic_bytes(kernel: str, info: dict, launches: int) -> tuple[float, str] | None:
     """Algorithmic bytes per launch of `kernel` (each datum read or written once),
     from the per-unit figures: SpMV 12 B per nonzero (col, val, x gather) + 8 B
-    per row (row_ptr, y); SSSP 16 B per edge relaxation (col, w, dist read and
-    write).  For kernels launched once per round the units are the per-call
-    totals spread over that call's launches (empty trailing rounds included)."""
+    per row (row_ptr, y); SSSP 12 B per edge relaxation (col, w, dist read) + 8 B
+    per update (dist write, frontier stamp).  For kernels launched once per round
+    the units are the per-call totals spread over that call's launches (empty
+    trailing rounds included)."""
     if kernel == "spmv_drain":
         return 12.0 * info["nnz_heavy"] + 4.0 * info["rows_heavy"], "12 B x nonzeros of buffered rows + 4 B x rows"
     if kernel == "spmv_parent_grid":
         return (12.0 * info["nnz_light"] + 8.0 * info["n"],
                 "12 B x nonzeros of inline rows + 8 B x rows (row_ptr, y)")
     if kernel == "sssp_drain":
-        per_call = info["sssp_edges_buffered"] * 16.0
-        return per_call * info["sssp_calls"] / launches, "16 B x edges relaxed by the drain (col, w, dist r+w)"
+        per_call = 12.0 * info["sssp_edges_buffered"] + 8.0 * info["sssp_updates_buffered"]
+        return (per_call * info["sssp_calls"] / launches,
+                "12 B x edges relaxed by the drain (col, w, dist read) + 8 B x its updates (dist, stamp)")
     if kernel.startswith("sssp_round"):
         inline = info["sssp_edges"] - info["sssp_edges_buffered"]
-        per_call = 16.0 * inline + 4.0 * info["n"] * info["sssp_rounds"]
+        upd_inline = info["sssp_updates"] - info["sssp_updates_buffered"]
+        per_call = 12.0 * inline + 8.0 * upd_inline + 4.0 * info["n"] * info["sssp_rounds"]
         return (per_call * info["sssp_calls"] / launches,
-                "16 B x inline edges + 4 B x vertices scanned per round")
+                "12 B x inline edges + 8 B x inline updates + 4 B x vertices scanned per round")
     return None
 
 
@@ -399,7 +402,8 @@ def main():
     heavy = lens > thr
     info = dict(n=g.n, nnz_heavy=int(lens[heavy].sum()), rows_heavy=int(heavy.sum()),
                 nnz_light=int(lens[~heavy].sum()), sssp_edges=sst["edges_processed"],
-                sssp_edges_buffered=sst["edges_buffered"], sssp_rounds=sst["rounds"], sssp_calls=args.steps)
+                sssp_edges_buffered=sst["edges_buffered"], sssp_updates=sst["updates"],
+                sssp_updates_buffered=sst["updates_buffered"], sssp_rounds=sst["rounds"], sssp_calls=args.steps)
     workload_tag = f"rmat{scale}"
     dominant = max(ktimes.items(), key=lambda kv: kv[1][1])
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
@@ -497,6 +501,7 @@ def main():
         "roofline": roofline,
         "spmv_roofline": spmv_roofline,
         "sssp_work": {"edges_relaxed": sst["edges_processed"], "edges_by_consolidated_child": sst["edges_buffered"],
+                      "updates": sst["updates"], "updates_by_consolidated_child": sst["updates_buffered"],
                       "rounds": sst["rounds"], "items_buffered": sst["items_buffered"]},
         "kernels": kernels,
         "modes": modes,

@@ -117,6 +117,10 @@ typedef struct {
     int64_t edges_processed; /* edges relaxed / nonzeros multiplied / children visited */
     int64_t edges_buffered;  /* the part of edges_processed handled by consolidated children */
     float ms;                /* wall time of the call on its stream, from HIP events */
+    int32_t reserved;        /* 0 */
+    int64_t updates;         /* SSSP: relaxations that lowered a distance (one atomic min and one
+                                frontier stamp each); 0 for the other problems */
+    int64_t updates_buffered; /* the part of updates made by consolidated children */
 } wc_stats;
 
 typedef struct wc_ctx wc_ctx;

@@ -208,6 +208,8 @@ wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds,
             stats->dispatches += (int64_t)ds.rep[r].dispatches;
             stats->edges_processed += (int64_t)ds.rep[r].edges_processed;
             stats->edges_buffered += (int64_t)ds.rep[r].edges_buffered;
+            stats->updates += (int64_t)ds.rep[r].updates;
+            stats->updates_buffered += (int64_t)ds.rep[r].updates_buffered;
         }
         stats->ms = ms;
     } else if (fail_on_overflow) {

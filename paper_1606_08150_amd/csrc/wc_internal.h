@@ -23,7 +23,9 @@ struct StatRep {
     unsigned long long dispatches;
     unsigned long long edges_processed;
     unsigned long long edges_buffered;
-    unsigned long long pad[12];
+    unsigned long long updates;
+    unsigned long long updates_buffered;
+    unsigned long long pad[10];
 };
 struct DevStats {
     StatRep rep[kStatReps];

@@ -77,7 +77,7 @@ __device__ __forceinline__ bool relax_loaded(const SsspArgs &a, int v, uint32_t 
 // U edges per lane at once: e_k = first + k * stride (valid while < end).
 // Loads are issued for all k before any relaxation, for memory-level parallelism.
 template <int U = kUnroll>
-__device__ __forceinline__ bool relax_batch(const SsspArgs &a, int first, int stride, int end, uint32_t du,
+__device__ __forceinline__ int relax_batch(const SsspArgs &a, int first, int stride, int end, uint32_t du,
                                             int next)
 {
     int v[U];
@@ -91,28 +91,28 @@ __device__ __forceinline__ bool relax_batch(const SsspArgs &a, int first, int st
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
-    bool any = false;
+    int upd = 0;
 #pragma unroll
     for (int k = 0; k < U; ++k)
-        if (v[k] >= 0) any |= relax_loaded(a, v[k], add_sat(du, wt[k]), dv[k], next);
-    return any;
+        if (v[k] >= 0) upd += relax_loaded(a, v[k], add_sat(du, wt[k]), dv[k], next);
+    return upd;
 }
 
 // Inline "work" of Fig. 1(b): the lane relaxes edges [beg, end) of its vertex,
 // 2 * kUnroll at a time (a light vertex of the default threshold in one step).
-__device__ __forceinline__ bool relax_lane(const SsspArgs &a, int beg, int end, uint32_t du, int next)
+__device__ __forceinline__ int relax_lane(const SsspArgs &a, int beg, int end, uint32_t du, int next)
 {
-    bool any = false;
-    for (int e = beg; e < end; e += 2 * kUnroll) any |= relax_batch<2 * kUnroll>(a, e, 1, end, du, next);
-    return any;
+    int upd = 0;
+    for (int e = beg; e < end; e += 2 * kUnroll) upd += relax_batch<2 * kUnroll>(a, e, 1, end, du, next);
+    return upd;
 }
 
 // The wave cooperatively relaxes edges [beg, end) of one vertex (uniform arguments).
-__device__ __forceinline__ bool relax_wave(const SsspArgs &a, int beg, int end, uint32_t du, int next)
+__device__ __forceinline__ int relax_wave(const SsspArgs &a, int beg, int end, uint32_t du, int next)
 {
-    bool any = false;
-    for (int b = beg; b < end; b += kWave * kUnroll) any |= relax_batch(a, b + lane_id(), kWave, end, du, next);
-    return any;
+    int upd = 0;
+    for (int b = beg; b < end; b += kWave * kUnroll) upd += relax_batch(a, b + lane_id(), kWave, end, du, next);
+    return upd;
 }
 
 // Two chunks of the grid buffer at once (uniform arguments): each lane keeps
@@ -120,10 +120,10 @@ __device__ __forceinline__ bool relax_wave(const SsspArgs &a, int beg, int end, 
 // their edges are requested (they may have improved since the vertex was
 // buffered); the largest distance used per chunk is returned.  Chunk 1 may be
 // empty (cb1 == ce1, u1 unused).
-__device__ __forceinline__ bool relax_wave2(const SsspArgs &a, int u0, int cb0, int ce0, int u1, int cb1, int ce1,
+__device__ __forceinline__ int relax_wave2(const SsspArgs &a, int u0, int cb0, int ce0, int u1, int cb1, int ce1,
                                             int next, uint32_t &du0_used, uint32_t &du1_used)
 {
-    bool any = false;
+    int upd = 0;
     const int len = max(ce0 - cb0, ce1 - cb1);
     du0_used = 0u;
     du1_used = 0u;
@@ -145,9 +145,9 @@ __device__ __forceinline__ bool relax_wave2(const SsspArgs &a, int u0, int cb0, 
         for (int k = 0; k < 2 * kUnroll; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
 #pragma unroll
         for (int k = 0; k < 2 * kUnroll; ++k)
-            if (v[k] >= 0) any |= relax_loaded(a, v[k], add_sat(k < kUnroll ? du0 : du1, wt[k]), dv[k], next);
+            if (v[k] >= 0) upd += relax_loaded(a, v[k], add_sat(k < kUnroll ? du0 : du1, wt[k]), dv[k], next);
     }
-    return any;
+    return upd;
 }
 
 __device__ __forceinline__ void mark_active(const SsspArgs &a, int r, bool any)
@@ -198,7 +198,8 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
             if (MODE == WC_WAVE && __ballot(heavy) && lane == 0) acc.dispatches += 1;
         }
         // work: light items relax inline
-        bool any = relax_lane(a, beg, heavy ? beg : end, du, next);
+        const int upd_inline = relax_lane(a, beg, heavy ? beg : end, du, next);
+        int upd = 0;  // by the consolidated child
 
         if constexpr (MODE == WC_WAVE) {
             // insert_buffer = ballot; the mask is the wave's buffer; no barrier needed
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
             while (mask) {
                 int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                any |= relax_wave(a, readlane(beg, b), readlane(end, b), readlane_u(du, b), next);
+                upd += relax_wave(a, readlane(beg, b), readlane(end, b), readlane_u(du, b), next);
             }
         } else if constexpr (MODE == WC_BLOCK) {
             __shared__ BlockBuf<BLOCK> sb;
@@ -244,22 +245,26 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
                 for (int q = 0; q < kUnroll; ++q) dv[q] = v[q] >= 0 ? a.dist[v[q]] : 0u;
 #pragma unroll
                 for (int q = 0; q < kUnroll; ++q)
-                    if (v[q] >= 0) any |= relax_loaded(a, v[q], nd[q], dv[q], next);
+                    if (v[q] >= 0) upd += relax_loaded(a, v[q], nd[q], dv[q], next);
             }
             __syncthreads();  // LDS buffer is reused by the next window
         }
-        mark_active(a, r, any);
+        if (a.want_stats) {
+            acc.updates += upd_inline + upd;
+            acc.updates_buffered += upd;
+        }
+        mark_active(a, r, upd_inline + upd > 0);
     }
     if (a.want_stats) stat_flush(a.stats, acc);
 }
 
 // Two light vertices' inline work at once: each lane keeps kUnroll edges of
 // each vertex in flight.
-__device__ __forceinline__ bool relax_lane2(const SsspArgs &a, int b0, int e0, uint32_t du0, int b1, int e1,
+__device__ __forceinline__ int relax_lane2(const SsspArgs &a, int b0, int e0, uint32_t du0, int b1, int e1,
                                             uint32_t du1, int next)
 {
     constexpr int U = kUnroll;
-    bool any = false;
+    int upd = 0;
     const int len = max(e0 - b0, e1 - b1);
     for (int o = 0; o < len; o += U) {
         int v[2 * U];
@@ -275,9 +280,9 @@ __device__ __forceinline__ bool relax_lane2(const SsspArgs &a, int b0, int e0, u
         for (int k = 0; k < 2 * U; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
 #pragma unroll
         for (int k = 0; k < 2 * U; ++k)
-            if (v[k] >= 0) any |= relax_loaded(a, v[k], nd[k], dv[k], next);
+            if (v[k] >= 0) upd += relax_loaded(a, v[k], nd[k], dv[k], next);
     }
-    return any;
+    return upd;
 }
 
 // Parent kernel of grid mode.  As sssp_round, but every thread takes two
@@ -357,16 +362,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
                 }
             }
             // work: light items relax inline
-            bool any = relax_lane2(a, beg[0], heavy[0] ? beg[0] : end[0], du[0], beg[1], heavy[1] ? beg[1] : end[1], du[1],
-                                   next);
+            const int upd_inline = relax_lane2(a, beg[0], heavy[0] ? beg[0] : end[0], du[0], beg[1],
+                                               heavy[1] ? beg[1] : end[1], du[1], next);
+            if (a.want_stats) acc.updates += upd_inline;
 #pragma unroll
             for (int k = 0; k < V; ++k)
                 if (end[k] > beg[k] && !heavy[k]) a.relaxed_at[u[k]] = du[k];
             // most windows of a small frontier hold no heavy vertex: skip the scan
             if (!__syncthreads_or((heavy[0] || heavy[1]) ? 1 : 0)) {
-                mark_active(a, r, any);
+                mark_active(a, r, upd_inline > 0);
                 continue;
             }
+            int upd_over = 0;  // chunks that did not fit, relaxed here
             int excl, d0, tot, d1;
             block_scan2<BLOCK>(nch[0] + nch[1], 0, s_tmp, excl, d0, tot, d1);
 #pragma unroll
@@ -405,11 +412,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
                 } else {
                     // buffer full: this chunk is processed inline (fallback)
                     a.stats->overflowed = 1;
-                    any |= relax_lane(a, cb, ce, s_du[lo], next);
+                    upd_over += relax_lane(a, cb, ce, s_du[lo], next);
                 }
             }
             __syncthreads();  // the LDS arrays are rewritten by the next window
-            mark_active(a, r, any);
+            if (a.want_stats) {
+                acc.updates += upd_over;
+                acc.updates_buffered += upd_over;
+            }
+            mark_active(a, r, upd_inline + upd_over > 0);
         }
     }
     if (a.want_stats) stat_flush(a.stats, acc);
@@ -428,7 +439,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
     const int nw = gridDim.x * (BLOCK / kWave);
     if (a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0)
         atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
-    bool any = false;
+    int upd = 0;
     // two chunks per wave and step; the next pair's entries are fetched before
     // the current pair's edges
     int4 d0 = gw < total ? a.chunks[gw] : make_int4(0, 0, 0, 0);
@@ -441,13 +452,18 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
         d0 = cn < total ? a.chunks[cn] : make_int4(0, 0, 0, 0);
         d1 = cn + nw < total ? a.chunks[cn + nw] : make_int4(0, 0, 0, 0);
         uint32_t du0, du1;
-        any |= relax_wave2(a, u0, cb0, ce0, u1, cb1, ce1, next, du0, du1);
+        upd += relax_wave2(a, u0, cb0, ce0, u1, cb1, ce1, next, du0, du1);
         if (lane_id() == 0) {
             atomic_max_dev_noret(&a.relaxed_at[u0], du0);
             if (cb1 < ce1) atomic_max_dev_noret(&a.relaxed_at[u1], du1);
         }
     }
-    mark_active(a, r, any);
+    mark_active(a, r, upd > 0);
+    if (a.want_stats) {
+        StatAcc acc;
+        acc.updates = acc.updates_buffered = (unsigned long long)upd;
+        stat_flush(a.stats, acc);
+    }
 }
 
 __global__ void sssp_init(SsspArgs a, int src)

@@ -9,7 +9,7 @@
 namespace wc {
 
 struct StatAcc {
-    unsigned long long items = 0, dispatches = 0, edges = 0, buffered = 0;
+    unsigned long long items = 0, dispatches = 0, edges = 0, buffered = 0, updates = 0, updates_buffered = 0;
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -22,25 +22,24 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // All threads of the block must call this (it contains barriers).
 __device__ __forceinline__ void stat_flush(DevStats *s, const StatAcc &acc)
 {
-    __shared__ unsigned long long sh[4];
-    if (threadIdx.x < 4) sh[threadIdx.x] = 0;
+    constexpr int K = 6;
+    __shared__ unsigned long long sh[K];
+    if (threadIdx.x < K) sh[threadIdx.x] = 0;
     __syncthreads();
-    unsigned long long v[4] = {acc.items, acc.dispatches, acc.edges, acc.buffered};
+    unsigned long long v[K] = {acc.items, acc.dispatches, acc.edges, acc.buffered, acc.updates, acc.updates_buffered};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = wave_sum_u64(v[k]);
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_u64(v[k]);
     if (lane_id() == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < K; ++k)
             if (v[k]) atomicAdd(&sh[k], v[k]);
     }
     __syncthreads();
-    if (threadIdx.x < 4 && sh[threadIdx.x]) {
+    if (threadIdx.x < K && sh[threadIdx.x]) {
         StatRep &r = s->rep[blockIdx.x % kStatReps];
-        unsigned long long *dst = threadIdx.x == 0   ? &r.items_buffered
-                                  : threadIdx.x == 1 ? &r.dispatches
-                                  : threadIdx.x == 2 ? &r.edges_processed
-                                                     : &r.edges_buffered;
-        atomic_add_dev(dst, sh[threadIdx.x]);
+        unsigned long long *dst[K] = {&r.items_buffered,  &r.dispatches, &r.edges_processed,
+                                      &r.edges_buffered,  &r.updates,    &r.updates_buffered};
+        atomic_add_dev(dst[threadIdx.x], sh[threadIdx.x]);
     }
 }
 

@@ -55,7 +55,8 @@ class Tune(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("overflowed", ctypes.c_int32), ("items_buffered", ctypes.c_int64),
                 ("dispatches", ctypes.c_int64), ("edges_processed", ctypes.c_int64),
-                ("edges_buffered", ctypes.c_int64), ("ms", ctypes.c_float)]
+                ("edges_buffered", ctypes.c_int64), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("updates", ctypes.c_int64), ("updates_buffered", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -128,11 +128,16 @@ def test_stats_and_repeat_runs(ctx, c1):
     g, w, ref = c1
     dg, dw = upload(g, w)
     reached = oracle.sssp_reached_edges(g.row_ptr, ref)
+    n_reached = int((ref != np.uint32(0xFFFFFFFF)).sum())
     for mode in MODES:
         for _ in range(10):
             d, st = ctx.sssp(dg, dw, 0, mode=mode, stats=True)
             assert np.array_equal(dev_to_u32(d), ref)
             assert st["rounds"] >= 1 and st["edges_processed"] >= reached
+            # every reached vertex but the source was lowered from infinity at least once
+            assert n_reached - 1 <= st["updates"] <= st["edges_processed"]
+            assert 0 <= st["updates_buffered"] <= st["updates"]
+            assert (st["updates_buffered"] == 0) == (mode == "flat")
             if mode == "flat":
                 assert st["items_buffered"] == 0 and st["dispatches"] == 0
             else:
