@@ -206,10 +206,19 @@ __global__ __launch_bounds__(BLOCK) void spmv_classify(SpmvArgs a)
     int mine[kCols];
 #pragma unroll
     for (int c = 0; c < kCols; ++c) mine[c] = 0;
-    for (int base = blockIdx.x * BLOCK; base < a.n; base += gridDim.x * BLOCK) {
-        const int r = base + threadIdx.x;
-        if (r < a.n) {
-            const int len = a.row_ptr[r + 1] - a.row_ptr[r];
+    // four windows' row lengths are requested together
+    constexpr int W = 4;
+    const int stride = gridDim.x * BLOCK;
+    for (long long base0 = (long long)blockIdx.x * BLOCK; base0 < a.n; base0 += (long long)W * stride) {
+        int lens[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const long long r = base0 + (long long)w * stride + threadIdx.x;
+            lens[w] = r < a.n ? a.row_ptr[r + 1] - a.row_ptr[r] : 0;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int len = lens[w];
             if (len > a.threshold) {
                 if (len > a.chunk) {
                     mine[kChunkBin] += (len + a.chunk - 1) / a.chunk;
@@ -231,22 +240,30 @@ __global__ __launch_bounds__(BLOCK) void spmv_classify(SpmvArgs a)
     if (threadIdx.x < kCols) a.blk_count[blockIdx.x * kCols + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of the per-block counts down each column (one workgroup).
-__global__ __launch_bounds__(1024) void spmv_scan(SpmvArgs a, int nblocks)
+// Exclusive scan of the per-block counts down each column: one workgroup, one
+// wave per column; a wave requests 16 x 64 counts at once, then scans them
+// with wave scans and a running carry (no barriers).
+__global__ __launch_bounds__(kCols * kWave) void spmv_scan(SpmvArgs a, int nblocks)
 {
-    __shared__ int tmp[2 * (1024 / kWave)];
-    for (int c = 0; c < kCols; ++c) {
-        int carry = 0;
-        for (int b0 = 0; b0 < nblocks; b0 += 1024) {
-            const int b = b0 + threadIdx.x;
-            const int v = b < nblocks ? a.blk_count[b * kCols + c] : 0;
-            int excl, d0, tot, d1;
-            block_scan2<1024>(v, 0, tmp, excl, d0, tot, d1);
-            if (b < nblocks) a.blk_off[b * kCols + c] = carry + excl;
-            carry += tot;
+    constexpr int K = 16;
+    const int c = threadIdx.x / kWave, lane = lane_id();
+    int carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += K * kWave) {
+        int v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int b = b0 + k * kWave + lane;
+            v[k] = b < nblocks ? a.blk_count[b * kCols + c] : 0;
         }
-        if (threadIdx.x == 0) a.bin_total[c] = carry;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int b = b0 + k * kWave + lane;
+            const int incl = wave_incl_scan(v[k]);
+            if (b < nblocks) a.blk_off[b * kCols + c] = carry + incl - v[k];
+            carry += __shfl(incl, kWave - 1, kWave);
+        }
     }
+    if (lane == 0) a.bin_total[c] = carry;
 }
 
 // Parent pass of grid mode: light rows inline, heavy rows written into their
@@ -510,7 +527,8 @@ extern "C" wc_status wc_spmv(wc_ctx *ctx, const wc_csr *g, const float *val, con
     void *sargs[] = {&a, &nblocks};
     st = launch(ctx, "spmv_classify", ks.classify, dim3(grid), dim3(cfg.block), args, stream);
     if (st == WC_OK)
-        st = launch(ctx, "spmv_scan", reinterpret_cast<const void *>(&spmv_scan), dim3(1), dim3(1024), sargs, stream);
+        st = launch(ctx, "spmv_scan", reinterpret_cast<const void *>(&spmv_scan), dim3(1), dim3(kCols * kWave), sargs,
+                    stream);
     if (st == WC_OK) st = launch(ctx, "spmv_parent_grid", ks.parent_grid, dim3(grid), dim3(cfg.block), args, stream);
     if (st == WC_OK) st = launch(ctx, "spmv_drain", ks.drain, dim3(dgrid), dim3(cfg.block), args, stream);
     if (st == WC_OK) st = launch(ctx, "spmv_combine", ks.combine, dim3(dgrid), dim3(cfg.block), args, stream);
