@@ -94,3 +94,35 @@ def test_autotuner_table_gives_exact_results(ctx, small_batch):
     outs = ctx.sssp_batch(graphs, weights, srcs, modes=modes, tunes=tunes, graph_rounds=16)
     torch.cuda.synchronize()
     check(outs, refs)
+
+
+@pytest.fixture(scope="module")
+def full_batch():
+    """The 512-instance batch at its full size (25.2M vertices, 403M edges)."""
+    say("generating the 512-instance batch")
+    inst = synth.batch_instances(512)
+    graphs = [wc.DeviceCSR.from_host(g.row_ptr, g.col) for g, _ in inst]
+    weights = [u32_to_dev(np.asarray(w, np.uint32)) for _, w in inst]
+    yield inst, graphs, weights
+    del graphs, weights
+    torch.cuda.empty_cache()
+
+
+def test_full_batch_certified_and_sampled_exact(ctx, full_batch):
+    """Every instance passes the shortest-path certificate; a seeded sample
+    (with the smallest and the largest instance) equals the oracle's Dijkstra."""
+    inst, graphs, weights = full_batch
+    srcs = [0] * len(inst)
+    for rounds in (0, 16):
+        say(f"full batch graph_rounds={rounds}")
+        outs = ctx.sssp_batch(graphs, weights, srcs, modes=["grid"] * len(inst), graph_rounds=rounds)
+        torch.cuda.synchronize()
+        got = [dev_to_u32(o) for o in outs]
+        for i, ((g, w), d) in enumerate(zip(inst, got)):
+            assert oracle.sssp_certify(g.row_ptr, g.col, np.asarray(w, np.uint32), 0, d) == (0, -1), i
+    sizes = np.array([g.n for g, _ in inst])
+    rng = np.random.default_rng(12)
+    sample = {int(sizes.argmin()), int(sizes.argmax())} | set(rng.choice(len(inst), 14, replace=False).tolist())
+    for i in sorted(sample):
+        g, w = inst[i]
+        assert np.array_equal(got[i], oracle.sssp_dijkstra(g.row_ptr, g.col, np.asarray(w, np.uint32), 0)), i

@@ -58,3 +58,37 @@ def test_results_same_alone_and_in_the_mix(ctx, resident):
     s = serve.summarize(out)
     say(f"serving summary {s}")
     assert s["failed"] == 0
+
+
+def test_full_resident_set_under_load(ctx):
+    """The full serving configuration (64 resident graphs of 2^14..2^20 vertices,
+    4 x vectors each) at a rate above saturation: every SSSP result passes the
+    shortest-path certificate and every SpMV result the 1e-5 bound."""
+    sizes = synth.serving_graph_sizes(64, 14, 20)
+    say(f"generating 64 resident graphs ({sum(sizes)} vertices)")
+    host, dev = [], []
+    for k, n in enumerate(sizes):
+        g, w, val, xs = synth.serving_graph(k, n, n_x=4)
+        host.append((g, w, val, xs))
+        dev.append(serve.ResidentGraph(wc.DeviceCSR.from_host(g.row_ptr, g.col),
+                                       torch.from_numpy(w.view(np.int32)).cuda(), torch.from_numpy(val).cuda(),
+                                       [torch.from_numpy(x).cuda() for x in xs]))
+    srcs = [np.flatnonzero(np.diff(g.row_ptr) > 0) for g, _, _, _ in host]
+    reqs = serve.poisson_requests(300, 20000.0, srcs, n_x=4, seed=21)
+    say(f"serving {len(reqs)} requests on the full resident set")
+    srv = serve.Server(serve.GpuBackend(dev), workers=4, max_slots=512, max_batch=64, keep_outputs=True)
+    try:
+        out = srv.run(reqs, time_limit=120)
+    finally:
+        srv.close()
+    assert all(r.error is None for r in out)
+    for r in out:
+        g, w, val, xs = host[r.graph]
+        if r.kind == serve.SSSP:
+            d = r.out.cpu().numpy().view(np.uint32)
+            assert oracle.sssp_certify(g.row_ptr, g.col, w, r.arg, d) == (0, -1), r.rid
+        else:
+            y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, xs[r.arg])
+            assert oracle.spmv_check(y_ref, b, r.out.cpu().numpy()) == (0, -1), r.rid
+    del dev
+    torch.cuda.empty_cache()
