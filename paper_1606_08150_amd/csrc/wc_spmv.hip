@@ -350,7 +350,7 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
 // Consolidated child of grid mode.  Wave tasks: for bin b (g = 2^b lanes per
 // row) a task is 64 / g consecutive rows of the bin; then one task per chunk.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void spmv_drain(SpmvArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void spmv_drain(SpmvArgs a)
 {
     __shared__ int s_cnt[8], s_off[8], s_task[9];
     if (threadIdx.x == 0) {
@@ -375,27 +375,34 @@ __global__ __launch_bounds__(BLOCK) void spmv_drain(SpmvArgs a)
     for (int t = gw; t < total; t += nw) {
         int b = 0;
         while (b < 7 && s_task[b + 1] <= t) ++b;
-        if (b < kBins) {
-            const int g = 1 << b;
-            const int i = (t - s_task[b]) * (kWave >> b) + (lane >> b);
-            const int sub = lane & (g - 1);
-            float s = 0.f;
-            int row = -1;
-            if (i < s_cnt[b]) {
-                int4 d = a.rows_buf[s_off[b] + i];
-                row = d.x;
-                s = dot_strided_u<2 * kUnroll>(a, d.y + sub, g, d.z);
-            }
-            s = group_sum(s, g);
-            if (row >= 0 && sub == 0) a.y[row] = s;
-        } else {
+        // bin task: groups of g lanes per row; chunk task: the whole wave on
+        // one chunk (g = 64).  One code path, so one copy of the dot product.
+        const bool chunk = b >= kBins;
+        const int g = chunk ? kWave : 1 << b;
+        const int sub = lane & (g - 1);
+        int first = 0, end = 0, dst = -1;
+        if (chunk) {
             const int c = t - s_task[kChunkBin];
-            int4 d = a.chunks[c];
-            const int row = __builtin_amdgcn_readfirstlane(d.x);
-            if (row < 0) continue;
-            float s = wave_sum(dot_strided_u<2 * kUnroll>(a, __builtin_amdgcn_readfirstlane(d.y) + lane, kWave,
-                                                          __builtin_amdgcn_readfirstlane(d.z)));
-            if (lane == 0) a.partials[c] = s;
+            const int4 d = a.chunks[c];
+            if (__builtin_amdgcn_readfirstlane(d.x) >= 0) {
+                first = __builtin_amdgcn_readfirstlane(d.y) + lane;
+                end = __builtin_amdgcn_readfirstlane(d.z);
+                dst = c;
+            }
+        } else {
+            const int i = (t - s_task[b]) * (kWave >> b) + (lane >> b);
+            if (i < s_cnt[b]) {
+                const int4 d = a.rows_buf[s_off[b] + i];
+                first = d.y + sub;
+                end = d.z;
+                dst = d.x;
+            }
+        }
+        float s = dot_strided_u<2 * kUnroll>(a, first, g, end);
+        s = group_sum(s, g);
+        if (dst >= 0 && sub == 0) {
+            if (chunk) a.partials[dst] = s;
+            else a.y[dst] = s;
         }
     }
 }
