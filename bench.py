@@ -48,6 +48,7 @@ def parse():
     p.add_argument("--no-trees", action="store_true", help="skip the tree descendants / heights section")
     p.add_argument("--no-serve", action="store_true", help="skip the continuous-batching serving section")
     p.add_argument("--serve-requests", type=int, default=4000, help="requests per arrival rate")
+    p.add_argument("--no-gather-ceiling", action="store_true", help="skip the bare-gather reference timing")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -426,6 +427,32 @@ def main():
     roofline = roof(dominant[0])
     spmv_roofline = roof("spmv_drain") if "spmv_drain" in ktimes else None
 
+    # ---- context for the drains: a bare gather of x over the same CSR columns
+    # (torch.index_select, int64 indices), and over the columns sorted (the same
+    # bytes with perfect locality); untimed for `value`
+    gather_ceiling = None
+    if not args.no_gather_ceiling:
+        col64 = torch.from_numpy(g.col.astype(np.int64)).cuda()
+        gout = torch.empty(g.m, dtype=torch.float32, device="cuda")
+
+        def timed_gather(idx, reps=10):
+            torch.index_select(dx, 0, idx, out=gout)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                torch.index_select(dx, 0, idx, out=gout)
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+
+        gather_ceiling = {"what": f"torch.index_select of x over the {g.m} CSR columns",
+                          "csr_order_ms": round(timed_gather(col64), 4)}
+        col64 = torch.sort(col64).values
+        gather_ceiling["sorted_ms"] = round(timed_gather(col64), 4)
+        del col64, gout
+        print(f"[bench] gather ceiling: {gather_ceiling}", file=sys.stderr, flush=True)
+
     # ---- flat / wave / block / grid side by side (1 timed run each after 1 warm-up)
     modes = {}
     if not args.no_modes:
@@ -500,6 +527,7 @@ def main():
         "spmv_frac_hbm": round(spmv_gbs / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "spmv_roofline": spmv_roofline,
+        "gather_ceiling": gather_ceiling,
         "sssp_work": {"edges_relaxed": sst["edges_processed"], "edges_by_consolidated_child": sst["edges_buffered"],
                       "updates": sst["updates"], "updates_by_consolidated_child": sst["updates_buffered"],
                       "rounds": sst["rounds"], "items_buffered": sst["items_buffered"]},
