@@ -13,11 +13,14 @@
 //           thread taking every BLOCK-th edge (a multi-thread child wrapped in a
 //           loop over the buffer, Sec. IV.C, load-balanced over items).
 //   grid  - global buffer of (vertex, edge range) chunks of 64 * items_per_lane
-//           edges, appended with one atomic per wave; after the grid-wide
-//           barrier a moldable grid drains all chunks, one wave per chunk.
+//           edges, reserved with one atomic per workgroup window; after the
+//           grid-wide barrier (the kernel boundary) a moldable grid drains all
+//           chunks, two per wave at a time.
 //   flat  - every vertex relaxes all of its edges itself.
-// Relaxation: nd = dist[u] + w; atomicMin on dist[v]; an improved vertex is
-// appended once per round to the next frontier (per-vertex round stamp).
+// Relaxation: nd = dist[u] + w; atomicMin on dist[v].  Flat, wave and block
+// modes put an improved vertex into the next frontier with a per-vertex round
+// stamp; grid mode keeps relaxed_at[v], the distance v's edges were last
+// relaxed with, and its frontier is every vertex whose distance is below it.
 // The distances reached are the unique shortest-path distances, so every mode
 // and schedule yields identical results.
 #include <cstring>
@@ -41,7 +44,8 @@ struct SsspArgs {
     const uint32_t *w;
     uint32_t *dist;
     int *stamp;       // stamp[v] == r: v is a frontier vertex of round r
-    uint32_t *relaxed_at;  // grid mode: the largest distance v's edges were last relaxed with
+    uint32_t *relaxed_at;  // grid mode: the largest distance v's edges were last relaxed with;
+                           // v is in the frontier while dist[v] is below it
     int *active;      // ring of 3 flags (stride kPad): round r has a frontier
     int *chunk_tail;  // ring of 3 grid-buffer tails (stride kPad)
     int4 *chunks;     // grid consolidation buffer: (u, begin, end, 0)
@@ -60,25 +64,28 @@ __device__ __forceinline__ uint32_t add_sat(uint32_t du, uint32_t w)
     return s < du ? kInf : s;
 }
 
-// Relaxes edge e of a vertex at distance du: atomicMin on dist[v], and v is
-// stamped into the next round's frontier.  dv is a plain read of dist[v] taken
-// earlier in the round; a stale read is only ever too high.  The atomic's old
-// value is not waited for: when nd < dv but another relaxation of this round
-// got dist[v] below nd first, that relaxation stamps v too, so stamping on
-// nd < dv gives the same frontier (and a vertex stamped twice is expanded once).
+// Relaxes edge e of a vertex at distance du: atomicMin on dist[v]; with STAMP
+// (flat, wave and block modes), v is stamped into the next round's frontier.
+// dv is a plain read of dist[v] taken earlier in the round; a stale read is
+// only ever too high.  The atomic's old value is not waited for: when nd < dv
+// but another relaxation of this round got dist[v] below nd first, that
+// relaxation stamps v too, so stamping on nd < dv gives the same frontier (and
+// a vertex stamped twice is expanded once).  Grid mode keeps no stamps: its
+// frontier is the set of vertices whose distance is below relaxed_at.
+template <bool STAMP>
 __device__ __forceinline__ bool relax_loaded(const SsspArgs &a, int v, uint32_t nd, uint32_t dv, int next)
 {
     if (nd >= dv) return false;
     atomic_min_dev_noret(&a.dist[v], nd);
-    a.stamp[v] = next;
+    if (STAMP) a.stamp[v] = next;
     return true;
 }
 
 // U edges per lane at once: e_k = first + k * stride (valid while < end).
 // Loads are issued for all k before any relaxation, for memory-level parallelism.
-template <int U = kUnroll>
+template <bool STAMP, int U = kUnroll>
 __device__ __forceinline__ int relax_batch(const SsspArgs &a, int first, int stride, int end, uint32_t du,
-                                            int next)
+                                           int next)
 {
     int v[U];
     uint32_t wt[U], dv[U];
@@ -94,16 +101,17 @@ __device__ __forceinline__ int relax_batch(const SsspArgs &a, int first, int str
     int upd = 0;
 #pragma unroll
     for (int k = 0; k < U; ++k)
-        if (v[k] >= 0) upd += relax_loaded(a, v[k], add_sat(du, wt[k]), dv[k], next);
+        if (v[k] >= 0) upd += relax_loaded<STAMP>(a, v[k], add_sat(du, wt[k]), dv[k], next);
     return upd;
 }
 
 // Inline "work" of Fig. 1(b): the lane relaxes edges [beg, end) of its vertex,
 // 2 * kUnroll at a time (a light vertex of the default threshold in one step).
+template <bool STAMP>
 __device__ __forceinline__ int relax_lane(const SsspArgs &a, int beg, int end, uint32_t du, int next)
 {
     int upd = 0;
-    for (int e = beg; e < end; e += 2 * kUnroll) upd += relax_batch<2 * kUnroll>(a, e, 1, end, du, next);
+    for (int e = beg; e < end; e += 2 * kUnroll) upd += relax_batch<STAMP, 2 * kUnroll>(a, e, 1, end, du, next);
     return upd;
 }
 
@@ -111,7 +119,7 @@ __device__ __forceinline__ int relax_lane(const SsspArgs &a, int beg, int end, u
 __device__ __forceinline__ int relax_wave(const SsspArgs &a, int beg, int end, uint32_t du, int next)
 {
     int upd = 0;
-    for (int b = beg; b < end; b += kWave * kUnroll) upd += relax_batch(a, b + lane_id(), kWave, end, du, next);
+    for (int b = beg; b < end; b += kWave * kUnroll) upd += relax_batch<true>(a, b + lane_id(), kWave, end, du, next);
     return upd;
 }
 
@@ -145,7 +153,7 @@ __device__ __forceinline__ int relax_wave2(const SsspArgs &a, int u0, int cb0, i
         for (int k = 0; k < 2 * kUnroll; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
 #pragma unroll
         for (int k = 0; k < 2 * kUnroll; ++k)
-            if (v[k] >= 0) upd += relax_loaded(a, v[k], add_sat(k < kUnroll ? du0 : du1, wt[k]), dv[k], next);
+            if (v[k] >= 0) upd += relax_loaded<false>(a, v[k], add_sat(k < kUnroll ? du0 : du1, wt[k]), dv[k], next);
     }
     return upd;
 }
@@ -198,7 +206,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
             if (MODE == WC_WAVE && __ballot(heavy) && lane == 0) acc.dispatches += 1;
         }
         // work: light items relax inline
-        const int upd_inline = relax_lane(a, beg, heavy ? beg : end, du, next);
+        const int upd_inline = relax_lane<true>(a, beg, heavy ? beg : end, du, next);
         int upd = 0;  // by the consolidated child
 
         if constexpr (MODE == WC_WAVE) {
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
                 for (int q = 0; q < kUnroll; ++q) dv[q] = v[q] >= 0 ? a.dist[v[q]] : 0u;
 #pragma unroll
                 for (int q = 0; q < kUnroll; ++q)
-                    if (v[q] >= 0) upd += relax_loaded(a, v[q], nd[q], dv[q], next);
+                    if (v[q] >= 0) upd += relax_loaded<true>(a, v[q], nd[q], dv[q], next);
             }
             __syncthreads();  // LDS buffer is reused by the next window
         }
@@ -280,7 +288,7 @@ __device__ __forceinline__ int relax_lane2(const SsspArgs &a, int b0, int e0, ui
         for (int k = 0; k < 2 * U; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
 #pragma unroll
         for (int k = 0; k < 2 * U; ++k)
-            if (v[k] >= 0) upd += relax_loaded(a, v[k], nd[k], dv[k], next);
+            if (v[k] >= 0) upd += relax_loaded<false>(a, v[k], nd[k], dv[k], next);
     }
     return upd;
 }
@@ -288,7 +296,7 @@ __device__ __forceinline__ int relax_lane2(const SsspArgs &a, int b0, int e0, ui
 // Parent kernel of grid mode.  As sssp_round, but every thread takes two
 // vertices of a window of 2 * BLOCK (u and u + BLOCK), with the loads of both
 // issued together: the parent is bound by the latency of its dependent loads
-// (stamp, then CSR range and distance, then edges, then targets).
+// (frontier test, then CSR range and distance, then edges, then targets).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void sssp_round_grid2(SsspArgs a,
                                                                                          int r)
@@ -307,9 +315,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     if (!act) return;
     const int next = r + 1;
     StatAcc acc;
-    // the stamps of S windows are read together and a block skips all S at
-    // once when none of them holds a frontier vertex (late rounds scan an
-    // almost empty frontier)
+    // Frontier of grid mode: the vertices whose distance is below relaxed_at
+    // (improved since their edges were last relaxed); no stamps are kept.  The
+    // test for S windows is read together, and a block skips all S at once
+    // when none of them holds a frontier vertex (late rounds scan an almost
+    // empty frontier).
     constexpr int S = 4;
     const int stride = gridDim.x * V * BLOCK;
     for (long long wbase = (long long)blockIdx.x * V * BLOCK; wbase < a.n; wbase += (long long)S * stride) {
@@ -319,7 +329,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
 #pragma unroll
             for (int k = 0; k < V; ++k) {
                 const long long uu = wbase + (long long)w * stride + k * BLOCK + threadIdx.x;
-                if (uu < a.n && a.stamp[uu] == r) bits |= 1 << (w * V + k);
+                if (uu < a.n && a.dist[uu] < a.relaxed_at[uu]) bits |= 1 << (w * V + k);
             }
         if (!__syncthreads_or(bits)) continue;
         for (int w = 0; w < S; ++w) {
@@ -338,17 +348,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
             for (int k = 0; k < V; ++k) {
                 beg[k] = end[k] = 0;
                 du[k] = 0;
-                uint32_t ra = 0;
                 if (member[k]) {
                     beg[k] = a.row_ptr[u[k]];
                     end[k] = a.row_ptr[u[k] + 1];
-                    du[k] = a.dist[u[k]];
-                    ra = a.relaxed_at[u[k]];
+                    du[k] = a.dist[u[k]];  // read again: it may have improved since the test
                 }
-                // every edge of u was already relaxed with its present distance
-                // (it improved in the last round, but before its own relaxations
-                // read it): nothing to do
-                if (member[k] && ra == du[k]) end[k] = beg[k];
             }
 #pragma unroll
             for (int k = 0; k < V; ++k) {
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
                 } else {
                     // buffer full: this chunk is processed inline (fallback)
                     a.stats->overflowed = 1;
-                    upd_over += relax_lane(a, cb, ce, s_du[lo], next);
+                    upd_over += relax_lane<false>(a, cb, ce, s_du[lo], next);
                 }
             }
             __syncthreads();  // the LDS arrays are rewritten by the next window
@@ -471,7 +475,7 @@ __global__ void sssp_init(SsspArgs a, int src)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < a.n; i += gridDim.x * blockDim.x) {
         a.dist[i] = i == src ? 0u : kInf;
-        a.stamp[i] = i == src ? 0 : -1;
+        if (a.stamp) a.stamp[i] = i == src ? 0 : -1;
         if (a.relaxed_at) a.relaxed_at[i] = kInf;
     }
     if (blockIdx.x == 0 && threadIdx.x < 3) {
@@ -552,7 +556,7 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     // ceil(deg / chunk) chunks, so n + m / chunk + 1 entries never overflow.
     long long cap_full = n + m / chunk + 1;
     long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    size_t need = padded(n * 4) * (mode == WC_GRID ? 2 : 1) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
+    size_t need = padded(n * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     SsspArgs a;
@@ -560,7 +564,8 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
     a.col = g->col;
     a.w = w;
     a.dist = dist;
-    a.stamp = pool_take<int>(ctx, n);
+    // the frontier: round stamps (flat, wave, block) or relaxed_at (grid)
+    a.stamp = mode == WC_GRID ? nullptr : pool_take<int>(ctx, n);
     a.relaxed_at = mode == WC_GRID ? pool_take<uint32_t>(ctx, n) : nullptr;
     a.active = pool_take<int>(ctx, 3 * kPad);
     a.chunk_tail = pool_take<int>(ctx, 3 * kPad);
