@@ -72,7 +72,7 @@ def algorithmic_bytes(kernel: str, info: dict, launches: int) -> tuple[float, st
     if kernel == "sssp_drain":
         per_call = 12.0 * info["sssp_edges_buffered"] + 8.0 * info["sssp_updates_buffered"]
         return (per_call * info["sssp_calls"] / launches,
-                "12 B x edges relaxed by the drain (col, w, dist read) + 8 B x its updates (dist, stamp)")
+                "12 B x edges relaxed by the drain (col, w, dist read) + 8 B x its updates (dist write, frontier mark)")
     if kernel.startswith("sssp_round"):
         inline = info["sssp_edges"] - info["sssp_edges_buffered"]
         upd_inline = info["sssp_updates"] - info["sssp_updates_buffered"]
