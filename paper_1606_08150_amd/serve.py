@@ -1,12 +1,13 @@
-"""Continuous-batching request server over resident graphs.
+"""Continuous-batching request server over resident graphs and trees.
 
-Requests (SSSP from a source, or SpMV with one of the graph's resident x
-vectors) arrive over time.  The scheduler admits a waiting request as soon as
+Requests (SSSP from a source, SpMV with one of the graph's resident x vectors,
+or tree descendants / heights of a resident tree) arrive over time.  The scheduler admits a waiting request as soon as
 the device-memory budget and the slot limit allow it, and hands each batch of
 admitted requests to an idle worker.  Every worker owns a libwc context and its
 own HIP stream, so batches launched while others are still on the device run
 concurrently; SSSP requests of one batch go through one wc_sssp_batch call
-(their work is consolidated across requests), SpMV requests through wc_spmv.
+(their work is consolidated across requests), SpMV requests through wc_spmv,
+tree requests through wc_tree_descendants / wc_tree_height.
 Each result is the same as the request run alone (bit-identical distances;
 SpMV results bit-identical for a fixed mode and tune).
 
@@ -24,15 +25,16 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SSSP, SPMV = 0, 1
+SSSP, SPMV, TREE_DESC, TREE_HEIGHT = 0, 1, 2, 3
+TREE_KINDS = (TREE_DESC, TREE_HEIGHT)
 
 
 @dataclass
 class Request:
     rid: int
-    kind: int          # SSSP or SPMV
-    graph: int         # index of a resident graph
-    arg: int           # SSSP source vertex, or SpMV x-vector index
+    kind: int          # SSSP, SPMV, TREE_DESC or TREE_HEIGHT
+    graph: int         # index of a resident graph (SSSP, SpMV) or tree (tree kinds)
+    arg: int           # SSSP source vertex, SpMV x-vector index; unused for trees
     t_arrive: float    # seconds from the start of the run
     nbytes: int = 0
     t_admit: float = -1.0
@@ -78,17 +80,24 @@ class Admission:
 
 def request_bytes(kind: int, n: int, m: int) -> int:
     """Device bytes a request holds while admitted: its output plus its share
-    of the consolidation workspace (SSSP: distances, round stamps, grid chunk
-    buffer; SpMV: y plus row bins, chunks, partials and split-row entries)."""
+    of the consolidation workspace (SSSP: distances, frontier array, grid chunk
+    buffer; SpMV: y plus row bins, chunks, partials and split-row entries;
+    trees (m unused): the output plus the level buffers)."""
     if kind == SSSP:
         return 4 * n + 4 * n + 16 * (n + m // 256 + 1)
+    if kind in TREE_KINDS:
+        return 4 * n + 8 * (n + 17) + 16 * (n + n // 128 + 2)
     return 4 * n + 16 * n + 20 * (n + m // 256 + 1) + 16 * n
 
 
-def poisson_requests(count: int, rate: float, sources_per_graph, n_x: int, seed: int, sssp_fraction: float = 0.5):
+def poisson_requests(count: int, rate: float, sources_per_graph, n_x: int, seed: int, sssp_fraction: float = 0.5,
+                     tree_fraction: float = 0.0, n_trees: int = 0):
     """Seeded request stream: exponential inter-arrival times at `rate` per
-    second, kind SSSP with probability sssp_fraction, graph uniform, SSSP source
-    uniform over the graph's vertices with out-edges, SpMV x uniform over n_x."""
+    second, kind SSSP with probability sssp_fraction (else SpMV), graph uniform,
+    SSSP source uniform over the graph's vertices with out-edges, SpMV x uniform
+    over n_x.  With tree_fraction > 0, that share of the requests (drawn after
+    the others, so the rest of the stream is unchanged) become tree descendants
+    or heights (even odds) of a uniform one of n_trees resident trees."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=count)
     t = np.cumsum(gaps) - gaps[0]
@@ -103,6 +112,15 @@ def poisson_requests(count: int, rate: float, sources_per_graph, n_x: int, seed:
         else:
             arg = int(rng.integers(0, n_x))
         reqs.append(Request(i, int(kinds[i]), g, arg, float(t[i])))
+    if tree_fraction > 0:
+        if n_trees < 1:
+            raise ValueError("tree requests need at least one resident tree")
+        tree_rng = np.random.default_rng([seed, 7])
+        is_tree = tree_rng.random(count) < tree_fraction
+        tree_kind = np.where(tree_rng.random(count) < 0.5, TREE_DESC, TREE_HEIGHT)
+        tree_idx = tree_rng.integers(0, n_trees, size=count)
+        for i in np.flatnonzero(is_tree).tolist():
+            reqs[i].kind, reqs[i].graph, reqs[i].arg = int(tree_kind[i]), int(tree_idx[i]), 0
     return reqs
 
 
@@ -125,10 +143,11 @@ class ResidentGraph:
 class GpuBackend:
     """libwc on one device: one context and one stream per worker."""
 
-    def __init__(self, graphs, device: int = 0, sssp_mode="grid", spmv_mode="grid"):
+    def __init__(self, graphs, device: int = 0, sssp_mode="grid", spmv_mode="grid", trees=(), tree_mode="grid"):
         self.graphs = graphs
+        self.trees = list(trees)  # wc.DeviceTree
         self.device = device
-        self.sssp_mode, self.spmv_mode = sssp_mode, spmv_mode
+        self.sssp_mode, self.spmv_mode, self.tree_mode = sssp_mode, spmv_mode, tree_mode
 
     def free_bytes(self) -> int:
         import torch
@@ -144,6 +163,9 @@ class GpuBackend:
 
     def allocate(self, r):
         import torch
+        if r.kind in TREE_KINDS:
+            r.out = torch.empty(self.trees[r.graph].n, dtype=torch.int32, device=f"cuda:{self.device}")
+            return
         g = self.graphs[r.graph]
         dt = torch.int32 if r.kind == SSSP else torch.float32
         r.out = torch.empty(g.n, dtype=dt, device=f"cuda:{self.device}")
@@ -162,6 +184,9 @@ class GpuBackend:
                 if r.kind == SPMV:
                     g = self.graphs[r.graph]
                     ctx.spmv(g.csr, g.val, g.xs[r.arg], mode=self.spmv_mode, out=r.out, stream=stream)
+                elif r.kind in TREE_KINDS:
+                    fn = ctx.tree_descendants if r.kind == TREE_DESC else ctx.tree_height
+                    fn(self.trees[r.graph], mode=self.tree_mode, out=r.out, stream=stream)
         stream.synchronize()
 
 
@@ -232,8 +257,11 @@ class Server:
         """Serves `requests` (sorted by t_arrive) in real time and returns them with
         admission, start and completion times filled in."""
         for r in requests:
-            g = self.backend.graphs[r.graph]
-            r.nbytes = request_bytes(r.kind, g.n, g.m)
+            if r.kind in TREE_KINDS:
+                r.nbytes = request_bytes(r.kind, self.backend.trees[r.graph].n, 0)
+            else:
+                g = self.backend.graphs[r.graph]
+                r.nbytes = request_bytes(r.kind, g.n, g.m)
             if not self.admission.fits_ever(r.nbytes):
                 raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, more than the whole budget")
         self._t0 = time.perf_counter()

@@ -1,6 +1,7 @@
 """Continuous batching on the GPU: every request's result is the same alone and
-in the mix (SSSP bit-identical and equal to the oracle; SpMV bit-identical to
-the same call alone and within the 1e-5 bound of the oracle)."""
+in the mix (SSSP and tree results bit-identical and equal to the oracle; SpMV
+bit-identical to the same call alone and within the 1e-5 bound of the
+oracle)."""
 import numpy as np
 import pytest
 import torch
@@ -23,16 +24,19 @@ def resident():
         dev.append(serve.ResidentGraph(wc.DeviceCSR.from_host(g.row_ptr, g.col),
                                        torch.from_numpy(w.view(np.int32)).cuda(), torch.from_numpy(val).cuda(),
                                        [torch.from_numpy(x).cuda() for x in xs]))
-    return host, dev
+    trees = [synth.random_tree(3000, seed=31), synth.random_tree(20000, seed=32)]
+    dtrees = [wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child) for t in trees]
+    return host, dev, trees, dtrees
 
 
 def test_results_same_alone_and_in_the_mix(ctx, resident):
-    host, dev = resident
+    host, dev, trees, dtrees = resident
     srcs = [np.flatnonzero(np.diff(g.row_ptr) > 0) for g, _, _, _ in host]
-    reqs = serve.poisson_requests(240, 20000.0, srcs, n_x=2, seed=9)
+    reqs = serve.poisson_requests(240, 20000.0, srcs, n_x=2, seed=9, tree_fraction=0.25, n_trees=len(trees))
+    assert any(r.kind in serve.TREE_KINDS for r in reqs)
     say(f"serving {len(reqs)} requests")
-    srv = serve.Server(serve.GpuBackend(dev), workers=3, budget_bytes=64 << 20, max_slots=48, max_batch=16,
-                       keep_outputs=True)
+    srv = serve.Server(serve.GpuBackend(dev, trees=dtrees), workers=3, budget_bytes=64 << 20, max_slots=48,
+                       max_batch=16, keep_outputs=True)
     try:
         out = srv.run(reqs, time_limit=60)
     finally:
@@ -40,6 +44,16 @@ def test_results_same_alone_and_in_the_mix(ctx, resident):
     assert all(r.error is None for r in out)
     assert srv.admission.peak_used <= 64 << 20
     for r in out:
+        if r.kind in serve.TREE_KINDS:
+            t = trees[r.graph]
+            fn = ctx.tree_descendants if r.kind == serve.TREE_DESC else ctx.tree_height
+            alone = fn(dtrees[r.graph], mode="grid")
+            torch.cuda.synchronize()
+            mixed = r.out.cpu().numpy()
+            assert np.array_equal(mixed, alone.cpu().numpy()), r.rid
+            ref = (oracle.tree_descendants if r.kind == serve.TREE_DESC else oracle.tree_height)(t.child_ptr, t.child)
+            assert np.array_equal(mixed, ref), r.rid
+            continue
         g, w, val, xs = host[r.graph]
         d = dev[r.graph]
         if r.kind == serve.SSSP:

@@ -124,3 +124,42 @@ def test_oversized_request_is_rejected():
             srv.run(reqs)
     finally:
         srv.close()
+
+
+class FakeTree:
+    def __init__(self, n):
+        self.n = n
+
+
+def test_tree_requests_join_the_stream_without_changing_the_rest():
+    gs = [FakeGraph(1000, 16000) for _ in range(4)]
+    srcs = [np.arange(10) for _ in gs]
+    base = serve.poisson_requests(5000, 5000.0, srcs, n_x=4, seed=5)
+    mixed = serve.poisson_requests(5000, 5000.0, srcs, n_x=4, seed=5, tree_fraction=0.3, n_trees=3)
+    assert [r.t_arrive for r in base] == [r.t_arrive for r in mixed]
+    trees = [r for r in mixed if r.kind in serve.TREE_KINDS]
+    assert abs(len(trees) / len(mixed) - 0.3) < 0.03
+    assert {r.kind for r in trees} == set(serve.TREE_KINDS) and {r.graph for r in trees} == {0, 1, 2}
+    for a, b in zip(base, mixed):
+        if b.kind not in serve.TREE_KINDS:
+            assert (a.kind, a.graph, a.arg) == (b.kind, b.graph, b.arg)
+    with pytest.raises(ValueError):
+        serve.poisson_requests(10, 100.0, srcs, n_x=4, seed=5, tree_fraction=0.5)
+
+
+def test_tree_requests_are_admitted_by_their_own_size():
+    gs, _ = make(count=1)
+    be = FakeBackend(gs)
+    be.trees = [FakeTree(5000), FakeTree(200000)]
+    srcs = [np.arange(10) for _ in gs]
+    reqs = serve.poisson_requests(300, 20000.0, srcs, n_x=4, seed=8, tree_fraction=0.5, n_trees=2)
+    srv = serve.Server(be, workers=3, budget_bytes=1 << 40, max_slots=32, max_batch=8, keep_outputs=True)
+    try:
+        out = srv.run(reqs, time_limit=30)
+    finally:
+        srv.close()
+    assert all(r.out == r.rid * 10 + r.kind for r in out)
+    for r in out:
+        if r.kind in serve.TREE_KINDS:
+            assert r.nbytes == serve.request_bytes(r.kind, be.trees[r.graph].n, 0)
+    assert srv.admission.used == 0 and srv.admission.slots == 0
