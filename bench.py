@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="skip the continuous-batching serving section")
     p.add_argument("--serve-requests", type=int, default=4000, help="requests per arrival rate")
     p.add_argument("--no-gather-ceiling", action="store_true", help="skip the bare-gather reference timing")
+    p.add_argument("--no-cold", action="store_true", help="skip the cold-cache (L2 and MALL flushed) timings")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -80,6 +81,17 @@ def algorithmic_bytes(kernel: str, info: dict, launches: int) -> tuple[float, st
         return (per_call * info["sssp_calls"] / launches,
                 "12 B x inline edges + 8 B x inline updates + 4 B x vertices scanned per round")
     return None
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def counter_traffic(kernel: str, workload: str):
@@ -427,6 +439,26 @@ def main():
     roofline = roof(dominant[0])
     spmv_roofline = roof("spmv_drain") if "spmv_drain" in ktimes else None
 
+    # ---- cold caches: each call after a 512 MiB write that evicts L2 and MALL
+    cold = None
+    if not args.no_cold:
+        flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        cold = {}
+        for prob, fn in (("sssp", sssp), ("spmv", spmv)):
+            times = []
+            for _ in range(5):
+                flush.fill_(1)
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn(args.mode)
+                b.record(stream)
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b))
+            cold[prob + "_ms_median"] = round(float(np.median(times)), 4)
+        del flush
+        print(f"[bench] cold caches: {cold}", file=sys.stderr, flush=True)
+
     # ---- context for the drains: a bare gather of x over the same CSR columns
     # (torch.index_select, int64 indices), and over the columns sorted (the same
     # bytes with perfect locality); untimed for `value`
@@ -504,6 +536,12 @@ def main():
                "cores": 1, "kind": "oracle",
                "sample": f"binary-heap Dijkstra from vertex 0 on the full scale-{scale} graph, {reps} runs "
                          f"(mean {dt:.2f} s each)"}
+        # context: the oracle's fp64 SpMV on the same matrix (one core) and the host
+        t1 = time.perf_counter()
+        oracle.spmv_f64(g.row_ptr, g.col, val, x)
+        cpu["spmv_f64_s"] = round(time.perf_counter() - t1, 3)
+        cpu["host_cpu"] = host_cpu_model()
+        cpu["host_threads"] = os.cpu_count()
 
     out = {
         "metric": "GTEPS (SSSP) + GB/s vs HBM peak, consolidated vs flat; p99 batched latency",
@@ -528,6 +566,7 @@ def main():
         "roofline": roofline,
         "spmv_roofline": spmv_roofline,
         "gather_ceiling": gather_ceiling,
+        "cold_caches": cold,
         "sssp_work": {"edges_relaxed": sst["edges_processed"], "edges_by_consolidated_child": sst["edges_buffered"],
                       "updates": sst["updates"], "updates_by_consolidated_child": sst["updates_buffered"],
                       "rounds": sst["rounds"], "items_buffered": sst["items_buffered"]},
