@@ -42,6 +42,7 @@ def _load():
         "orc_sssp_reached_edges": (c.c_int64, [c.c_int32, i32p, u32p]),
         "orc_spmv_f64": (None, [c.c_int32, i32p, i32p, f32p, f32p, f64p, f64p]),
         "orc_spmv_check": (c.c_int64, [c.c_int32, f64p, f64p, f32p, c.c_double, pi64]),
+        "orc_pagerank_f64": (c.c_int, [c.c_int32, i32p, i32p, i32p, c.c_int32, c.c_double, f64p]),
         "orc_tree_validate": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
         "orc_tree_descendants": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
         "orc_tree_height": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
@@ -118,6 +119,34 @@ def spmv_f64(row_ptr, col, val, x):
 
 
 SPMV_RTOL = 1e-5
+
+
+def pagerank_f64(in_row_ptr, in_col, out_degree, iterations: int, damping: float = 0.85):
+    """Binary64 PageRank after `iterations` sweeps from 1/n (see orc_pagerank_f64)."""
+    n = len(in_row_ptr) - 1
+    r = np.empty(max(n, 1), dtype=np.float64)
+    if _load().orc_pagerank_f64(n, _i32(in_row_ptr), _nonempty(in_col, np.int32), _nonempty(out_degree, np.int32),
+                                int(iterations), float(damping), r) != 0:
+        raise MemoryError("orc_pagerank_f64")
+    return r[:n]
+
+
+# fp32 ranks against the binary64 oracle: each sweep's in-edge sum of positive
+# terms is computed with at most ~32 rounded additions along any path (lane
+# partials of up to 16 terms, a 64-lane butterfly, chunk partials of split
+# rows), a relative error below 32 * 2^-24 = 1.9e-6, plus a few roundings in the
+# update; the damping factor (< 1) keeps earlier errors from growing, so after
+# any number of sweeps the relative error stays below ~2.2e-6 / (1 - 0.85) =
+# 1.5e-5.  The bound used is 1e-4, relative to the oracle's rank (all ranks are
+# at least (1 - d) / n > 0).
+PAGERANK_RTOL = 1e-4
+
+
+def pagerank_check(r_ref, r, rtol: float = PAGERANK_RTOL):
+    """(bad_vertices, first_bad_vertex) for |r - r_ref| <= rtol * r_ref."""
+    r = np.asarray(r, dtype=np.float64)
+    bad = np.flatnonzero(~(np.abs(r - r_ref) <= rtol * r_ref))
+    return int(bad.size), int(bad[0]) if bad.size else -1
 
 
 def spmv_check(y_ref, b, y, rtol: float = SPMV_RTOL):

@@ -16,6 +16,9 @@
  *   SpMV  - y = A x in binary64 plus the per-row magnitude sum
  *           b[r] = sum |a_rj x_j| used by the tolerance test (Sec. V lists
  *           SpMV among the irregular-loop benchmarks).
+ *   PR    - damped PageRank iterations over the in-edges of each vertex (the
+ *           same irregular loop as SpMV, with the rank contributions of the
+ *           sources in place of a_ij x_j).
  *   TD/TH - per-node proper-descendant count and per-node height of a rooted
  *           tree (the recursion of Fig. 1(c): leaf work at nodes without
  *           children, post-work folding the children's results into the node).
@@ -235,6 +238,48 @@ int64_t orc_spmv_check(int32_t n, const double *y_ref, const double *b, const fl
         }
     }
     return bad;
+}
+
+/* ------------------------------------------------------------ PageRank ---- */
+
+/* PageRank, the PR benchmark of Sec. V.  The paper names it without a formula;
+ * this is the usual damped iteration in which the rank held by vertices without
+ * out-edges is spread evenly over all vertices, so the ranks always sum to 1.
+ * From rank = 1/n, `iterations` synchronous sweeps of
+ *   rank'[v] = (1 - d) / n + d * (sum over edges u -> v of rank[u] / outdeg(u) + D / n),
+ *   D = sum of rank[u] over the vertices u with outdeg(u) = 0.
+ * The graph comes as its in-edges: row v of (in_row_ptr, in_col) lists the
+ * source of every edge into v, with multiplicity; out_degree[u] is u's number
+ * of out-edges.  Binary64 throughout.  Returns 0, or -1 if memory runs out. */
+int orc_pagerank_f64(int32_t n, const int32_t *in_row_ptr, const int32_t *in_col, const int32_t *out_degree,
+                     int32_t iterations, double d, double *rank)
+{
+    double *cur = rank, *nxt = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!nxt) return -1;
+    for (int32_t v = 0; v < n; ++v) cur[v] = 1.0 / n;
+    for (int32_t it = 0; it < iterations; ++it) {
+        double dangling = 0.0;
+        for (int32_t u = 0; u < n; ++u)
+            if (out_degree[u] == 0) dangling += cur[u];
+        for (int32_t v = 0; v < n; ++v) {
+            double s = 0.0;
+            for (int32_t e = in_row_ptr[v]; e < in_row_ptr[v + 1]; ++e) {
+                int32_t u = in_col[e];
+                s += cur[u] / out_degree[u];
+            }
+            nxt[v] = (1.0 - d) / n + d * (s + dangling / n);
+        }
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != rank) {
+        memcpy(rank, cur, sizeof(double) * (size_t)n);
+        free(cur);
+    } else {
+        free(nxt);
+    }
+    return 0;
 }
 
 /* --------------------------------------------------------------- trees ---- */

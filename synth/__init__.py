@@ -242,6 +242,23 @@ def kary_tree(k: int, height: int) -> Tree:
     return tree_from_parent(parent)
 
 
+def transpose(g: CSR) -> CSR:
+    """The reversed graph: row v lists the sources u of the edges u -> v, in
+    increasing u (multi-edges kept).  A data-layout step for in-edge (pull)
+    iterations; holds no arithmetic of the method."""
+    n = g.n
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr).astype(np.int64))
+    dst = g.col.astype(np.int64)
+    order = np.lexsort((src, dst))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, dst + 1, 1)
+    return CSR(n, np.cumsum(row_ptr).astype(np.int32), src[order].astype(np.int32))
+
+
+def out_degree(g: CSR) -> np.ndarray:
+    return np.diff(g.row_ptr).astype(np.int32)
+
+
 def graph_from_edges(n: int, edges, w=None):
     """Small directed graph from an explicit (u, v) list; returns (CSR, weights) with the
     weights permuted into CSR order."""
