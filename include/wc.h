@@ -149,6 +149,22 @@ wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, 
 wc_status wc_spmv(wc_ctx *ctx, const wc_csr *a, const float *val, const float *x, float *y, wc_mode mode,
                   const wc_tune *tune, hipStream_t stream, wc_stats *stats);
 
+/* PageRank (the PR benchmark of Sec. V, an irregular loop like SpMV): from
+ * rank = 1/n, `iterations` synchronous sweeps of
+ *   rank'[v] = (1 - damping) / n + damping * (sum over edges u -> v of rank[u] / outdeg(u) + D / n),
+ * D = the rank held by vertices without out-edges (spread over all vertices, so
+ * the ranks keep summing to 1).  in_graph holds the in-edges: row v lists the
+ * source u of every edge u -> v (the transpose of the out-edge CSR);
+ * out_degree[n] (int32, device) is each vertex's number of out-edges.  Each
+ * sweep's loop over a vertex's in-edges is consolidated per `mode` exactly as
+ * in wc_spmv (unit values).  rank[n] (fp32, device) is written.  fp32 sums in
+ * an order fixed by mode and tune: bit-identical across runs for a fixed mode
+ * and tune.  stats->rounds = iterations.  WC_EINVAL for negative sizes or
+ * iterations, damping outside [0, 1] or NULL arrays. */
+wc_status wc_pagerank(wc_ctx *ctx, const wc_csr *in_graph, const int32_t *out_degree, int32_t iterations,
+                      float damping, float *rank, wc_mode mode, const wc_tune *tune, hipStream_t stream,
+                      wc_stats *stats);
+
 /* Tree descendants (recursion of Fig. 1(c)): desc[v] = number of proper
  * descendants of v.  A node with children is a recursive call whose work is
  * consolidated per `mode`; a leaf gets 0; the post-work folds each child c

@@ -40,7 +40,7 @@ constexpr int kCols = 9;
 struct SpmvArgs {
     const int *row_ptr;
     const int *col;
-    const float *val;
+    const float *val;  // nullptr: every stored entry is 1 (the in-edge sums of PageRank)
     const float *x;
     float *y;
     int n;
@@ -77,7 +77,7 @@ __device__ __forceinline__ float dot_strided_u(const SpmvArgs &a, int first, int
             const int e = e0 + k * stride;
             const bool ok = e < end;
             c[k] = ok ? a.col[e] : -1;
-            v[k] = ok ? a.val[e] : 0.f;
+            v[k] = ok ? (a.val ? a.val[e] : 1.f) : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) xv[k] = c[k] >= 0 ? a.x[c[k]] : 0.f;
@@ -457,6 +457,143 @@ SpmvKernels pick(wc_mode mode, int block)
     }
 }
 
+
+// A planned product y = A x: the tune resolved, the kernels picked and the
+// workspace carved from the pool (plus `extra_bytes` left reserved for the
+// caller).  x and y may be set after planning.
+struct SpmvPlan {
+    SpmvArgs a;
+    SpmvKernels ks;
+    Config cfg;
+    wc_mode mode;
+    int grid, dgrid;
+};
+
+wc_status spmv_plan(wc_ctx *ctx, const wc_csr *g, const float *val, wc_mode mode, const wc_tune *tune,
+                    size_t extra_bytes, hipStream_t stream, wc_stats *stats, SpmvPlan *p)
+{
+    int block = (tune && tune->block_threads > 0) ? tune->block_threads : 256;
+    p->mode = mode;
+    p->ks = pick(mode, block);
+    int resident = resident_blocks(ctx, p->ks.parent, block);
+    wc_status st = resolve_tune(ctx, "spmv", mode, tune, resident, &p->cfg);
+    if (st != WC_OK) return st;
+    const Config &cfg = p->cfg;
+    if (cfg.block != block) {
+        p->ks = pick(mode, cfg.block);
+        resident = resident_blocks(ctx, p->ks.parent, cfg.block);
+    }
+    const long long n = g->n, m = g->m;
+    const int chunk = kWave * cfg.items_per_lane;
+    long long cap_full = n + m / chunk + 1;
+    long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
+    long long rows_cap = mode == WC_GRID ? n : 1;
+    long long mcap = mode == WC_GRID ? n : 1;
+    p->grid = (int)std::max<long long>(1, std::min<long long>(cfg.grid, (n + cfg.block - 1) / cfg.block));
+    p->dgrid = std::max(1, std::min(cfg.grid, resident));
+    size_t need = 2 * padded((size_t)p->grid * kCols * 4) + padded(kCols * 4) + padded(rows_cap * 16) +
+                  padded(cap * 16) + padded(cap * 4) + padded(mcap * 16) + extra_bytes;
+    st = pool_reserve(ctx, need, stream);
+    if (st != WC_OK) return st;
+    SpmvArgs &a = p->a;
+    std::memset(&a, 0, sizeof(a));
+    a.row_ptr = g->row_ptr;
+    a.col = g->col;
+    a.val = val;
+    a.n = (int)n;
+    a.threshold = cfg.threshold;
+    a.ipl = cfg.items_per_lane;
+    a.chunk = chunk;
+    a.big = cfg.block * cfg.items_per_lane;
+    a.blk_count = pool_take<int>(ctx, (size_t)p->grid * kCols);
+    a.blk_off = pool_take<int>(ctx, (size_t)p->grid * kCols);
+    a.bin_total = pool_take<int>(ctx, kCols);
+    a.rows_buf = pool_take<int4>(ctx, rows_cap);
+    a.rows_cap = rows_cap;
+    a.chunks = pool_take<int4>(ctx, cap);
+    a.chunk_cap = cap;
+    a.partials = pool_take<float>(ctx, cap);
+    a.multi = pool_take<int4>(ctx, mcap);
+    a.multi_cap = mcap;
+    a.stats = ctx->dstats;
+    a.want_stats = stats != nullptr;
+    return WC_OK;
+}
+
+// The kernels of one product (parent; in grid mode classify, scan, parent,
+// drain, combine).
+wc_status spmv_launch(wc_ctx *ctx, SpmvPlan *p, hipStream_t stream)
+{
+    const Config &cfg = p->cfg;
+    void *args[] = {&p->a};
+    if (p->mode != WC_GRID) {
+        static const char *names[] = {"spmv_parent_flat", "spmv_parent_wave", "spmv_parent_block"};
+        return launch(ctx, names[p->mode], p->ks.parent, dim3(p->grid), dim3(cfg.block), args, stream);
+    }
+    int nblocks = p->grid;
+    void *sargs[] = {&p->a, &nblocks};
+    wc_status st = launch(ctx, "spmv_classify", p->ks.classify, dim3(p->grid), dim3(cfg.block), args, stream);
+    if (st == WC_OK)
+        st = launch(ctx, "spmv_scan", reinterpret_cast<const void *>(&spmv_scan), dim3(1), dim3(kCols * kWave), sargs,
+                    stream);
+    if (st == WC_OK)
+        st = launch(ctx, "spmv_parent_grid", p->ks.parent_grid, dim3(p->grid), dim3(cfg.block), args, stream);
+    if (st == WC_OK) st = launch(ctx, "spmv_drain", p->ks.drain, dim3(p->dgrid), dim3(cfg.block), args, stream);
+    if (st == WC_OK) st = launch(ctx, "spmv_combine", p->ks.combine, dim3(p->dgrid), dim3(cfg.block), args, stream);
+    return st;
+}
+
+// ---------------------------------------------------------------- PageRank
+
+struct PrArgs {
+    const int *out_degree;
+    float *rank;
+    float *contrib;   // rank[u] / outdeg(u), the x of the in-edge sums
+    const float *sums;  // sum over the in-edges of v of contrib[u]
+    float *dpart;     // per block of pr_contrib: rank held by vertices without out-edges
+    int nparts;
+    int n;
+    float base;       // (1 - d) / n
+    float damping;
+    float inv_n;
+};
+
+constexpr int kPrBlock = 256;
+
+__global__ __launch_bounds__(kPrBlock) void pr_init(PrArgs p)
+{
+    for (int v = blockIdx.x * kPrBlock + threadIdx.x; v < p.n; v += gridDim.x * kPrBlock) p.rank[v] = p.inv_n;
+}
+
+// contrib[u] = rank[u] / outdeg(u); the ranks of vertices without out-edges
+// are summed per block in a fixed order into dpart[blockIdx.x].
+__global__ __launch_bounds__(kPrBlock) void pr_contrib(PrArgs p)
+{
+    __shared__ float red[kPrBlock / kWave];
+    float dang = 0.f;
+    for (int u = blockIdx.x * kPrBlock + threadIdx.x; u < p.n; u += gridDim.x * kPrBlock) {
+        const float r = p.rank[u];
+        const int od = p.out_degree[u];
+        p.contrib[u] = od > 0 ? r / (float)od : 0.f;
+        if (od == 0) dang += r;
+    }
+    dang = block_sum<kPrBlock>(dang, red);
+    if (threadIdx.x == 0) p.dpart[blockIdx.x] = dang;
+}
+
+// rank'[v] = (1 - d) / n + d * (sums[v] + D / n), D the sum of dpart in block
+// order (every block computes the same D).
+__global__ __launch_bounds__(kPrBlock) void pr_update(PrArgs p)
+{
+    __shared__ float red[kPrBlock / kWave];
+    float dsum = 0.f;
+    for (int i = threadIdx.x; i < p.nparts; i += kPrBlock) dsum += p.dpart[i];
+    dsum = block_sum<kPrBlock>(dsum, red);
+    const float spread = dsum * p.inv_n;
+    for (int v = blockIdx.x * kPrBlock + threadIdx.x; v < p.n; v += gridDim.x * kPrBlock)
+        p.rank[v] = p.base + p.damping * (p.sums[v] + spread);
+}
+
 }  // namespace
 }  // namespace wc
 
@@ -474,71 +611,64 @@ extern "C" wc_status wc_spmv(wc_ctx *ctx, const wc_csr *g, const float *val, con
     }
     if (!g->row_ptr || !x || !y || (g->m > 0 && (!g->col || !val))) return fail(WC_EINVAL, "wc_spmv: NULL array");
     WC_HIP(hipSetDevice(ctx->device));
-    int block = (tune && tune->block_threads > 0) ? tune->block_threads : 256;
-    SpmvKernels ks = pick(mode, block);
-    int resident = resident_blocks(ctx, ks.parent, block);
-    Config cfg;
-    wc_status st = resolve_tune(ctx, "spmv", mode, tune, resident, &cfg);
+    SpmvPlan p;
+    wc_status st = spmv_plan(ctx, g, val, mode, tune, 0, stream, stats, &p);
     if (st != WC_OK) return st;
-    if (cfg.block != block) {
-        ks = pick(mode, cfg.block);
-        resident = resident_blocks(ctx, ks.parent, cfg.block);
-    }
-    const long long n = g->n, m = g->m;
-    const int chunk = kWave * cfg.items_per_lane;
-    long long cap_full = n + m / chunk + 1;
-    long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    long long rows_cap = mode == WC_GRID ? n : 1;
-    long long mcap = mode == WC_GRID ? n : 1;
-    const int grid = (int)std::max<long long>(1, std::min<long long>(cfg.grid, (n + cfg.block - 1) / cfg.block));
-    size_t need = 2 * padded((size_t)grid * kCols * 4) + padded(kCols * 4) + padded(rows_cap * 16) +
-                  padded(cap * 16) + padded(cap * 4) + padded(mcap * 16);
-    st = pool_reserve(ctx, need, stream);
+    p.a.x = x;
+    p.a.y = y;
+    st = begin_call(ctx, stream, stats);
+    if (st == WC_OK) st = spmv_launch(ctx, &p, stream);
     if (st != WC_OK) return st;
-    SpmvArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.row_ptr = g->row_ptr;
-    a.col = g->col;
-    a.val = val;
-    a.x = x;
-    a.y = y;
-    a.n = (int)n;
-    a.threshold = cfg.threshold;
-    a.ipl = cfg.items_per_lane;
-    a.chunk = chunk;
-    a.big = cfg.block * cfg.items_per_lane;
-    a.blk_count = pool_take<int>(ctx, (size_t)grid * kCols);
-    a.blk_off = pool_take<int>(ctx, (size_t)grid * kCols);
-    a.bin_total = pool_take<int>(ctx, kCols);
-    a.rows_buf = pool_take<int4>(ctx, rows_cap);
-    a.rows_cap = rows_cap;
-    a.chunks = pool_take<int4>(ctx, cap);
-    a.chunk_cap = cap;
-    a.partials = pool_take<float>(ctx, cap);
-    a.multi = pool_take<int4>(ctx, mcap);
-    a.multi_cap = mcap;
-    a.stats = ctx->dstats;
-    a.want_stats = stats != nullptr;
+    return end_call(ctx, stream, stats, 1, p.cfg.fail_on_overflow);
+}
 
+extern "C" wc_status wc_pagerank(wc_ctx *ctx, const wc_csr *in_graph, const int32_t *out_degree, int32_t iterations,
+                                 float damping, float *rank, wc_mode mode, const wc_tune *tune, hipStream_t stream,
+                                 wc_stats *stats)
+{
+    if (!ctx || !in_graph) return fail(WC_EINVAL, "wc_pagerank: NULL context or graph");
+    if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "wc_pagerank: bad mode");
+    if (in_graph->n < 0 || in_graph->m < 0 || iterations < 0) return fail(WC_EINVAL, "wc_pagerank: negative size");
+    if (!(damping >= 0.f && damping <= 1.f)) return fail(WC_EINVAL, "wc_pagerank: damping outside [0, 1]");
+    if (in_graph->n == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return WC_OK;
+    }
+    if (!in_graph->row_ptr || !out_degree || !rank || (in_graph->m > 0 && !in_graph->col))
+        return fail(WC_EINVAL, "wc_pagerank: NULL array");
+    WC_HIP(hipSetDevice(ctx->device));
+    const long long n = in_graph->n;
+    const int pgrid = (int)std::min<long long>((n + kPrBlock - 1) / kPrBlock, 4 * (long long)ctx->num_cus);
+    SpmvPlan p;
+    wc_status st = spmv_plan(ctx, in_graph, nullptr, mode, tune, 2 * padded(n * 4) + padded((size_t)pgrid * 4), stream,
+                             stats, &p);
+    if (st != WC_OK) return st;
+    PrArgs q;
+    q.out_degree = out_degree;
+    q.rank = rank;
+    q.contrib = pool_take<float>(ctx, n);
+    float *sums = pool_take<float>(ctx, n);
+    q.sums = sums;
+    q.dpart = pool_take<float>(ctx, pgrid);
+    q.nparts = pgrid;
+    q.n = (int)n;
+    q.base = (float)((1.0 - (double)damping) / (double)n);
+    q.damping = damping;
+    q.inv_n = (float)(1.0 / (double)n);
+    p.a.x = q.contrib;
+    p.a.y = sums;
     st = begin_call(ctx, stream, stats);
     if (st != WC_OK) return st;
-    void *args[] = {&a};
-    if (mode != WC_GRID) {
-        static const char *names[] = {"spmv_parent_flat", "spmv_parent_wave", "spmv_parent_block"};
-        st = launch(ctx, names[mode], ks.parent, dim3(grid), dim3(cfg.block), args, stream);
-        if (st != WC_OK) return st;
-        return end_call(ctx, stream, stats, 1, cfg.fail_on_overflow);
-    }
-    const int dgrid = std::max(1, std::min(cfg.grid, resident));
-    int nblocks = grid;
-    void *sargs[] = {&a, &nblocks};
-    st = launch(ctx, "spmv_classify", ks.classify, dim3(grid), dim3(cfg.block), args, stream);
-    if (st == WC_OK)
-        st = launch(ctx, "spmv_scan", reinterpret_cast<const void *>(&spmv_scan), dim3(1), dim3(kCols * kWave), sargs,
+    void *args[] = {&q};
+    st = launch(ctx, "pr_init", reinterpret_cast<const void *>(&pr_init), dim3(pgrid), dim3(kPrBlock), args, stream);
+    for (int it = 0; it < iterations && st == WC_OK; ++it) {
+        st = launch(ctx, "pr_contrib", reinterpret_cast<const void *>(&pr_contrib), dim3(pgrid), dim3(kPrBlock), args,
                     stream);
-    if (st == WC_OK) st = launch(ctx, "spmv_parent_grid", ks.parent_grid, dim3(grid), dim3(cfg.block), args, stream);
-    if (st == WC_OK) st = launch(ctx, "spmv_drain", ks.drain, dim3(dgrid), dim3(cfg.block), args, stream);
-    if (st == WC_OK) st = launch(ctx, "spmv_combine", ks.combine, dim3(dgrid), dim3(cfg.block), args, stream);
+        if (st == WC_OK) st = spmv_launch(ctx, &p, stream);
+        if (st == WC_OK)
+            st = launch(ctx, "pr_update", reinterpret_cast<const void *>(&pr_update), dim3(pgrid), dim3(kPrBlock),
+                        args, stream);
+    }
     if (st != WC_OK) return st;
-    return end_call(ctx, stream, stats, 1, cfg.fail_on_overflow);
+    return end_call(ctx, stream, stats, iterations, p.cfg.fail_on_overflow);
 }

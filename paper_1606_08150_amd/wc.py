@@ -21,7 +21,7 @@ MODES = {"flat": FLAT, "wave": WAVE, "block": BLOCK, "grid": GRID}
 STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: "WC_ETIMEOUT", -5: "WC_EHIP"}
 
 # C-ABI symbols declared in include/wc.h
-EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_spmv", "wc_tree_descendants", "wc_tree_height",
+EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_spmv", "wc_pagerank", "wc_tree_descendants", "wc_tree_height",
            "wc_sssp_batch",
            "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size",
            "wc_kc_config", "wc_default_tune")
@@ -83,6 +83,9 @@ def load_library():
     lib.wc_sssp.argtypes = [vp, c.POINTER(CCsr), vp, c.c_int32, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_spmv.restype = c.c_int
     lib.wc_spmv.argtypes = [vp, c.POINTER(CCsr), vp, vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_pagerank.restype = c.c_int
+    lib.wc_pagerank.argtypes = [vp, c.POINTER(CCsr), vp, c.c_int32, c.c_float, vp, c.c_int, c.POINTER(Tune), vp,
+                                c.POINTER(Stats)]
     for name in ("wc_tree_descendants", "wc_tree_height"):
         fn = getattr(lib, name)
         fn.restype = c.c_int
@@ -289,6 +292,20 @@ class Context:
                                       y.data_ptr(), _mode(mode), ctypes.byref(tune) if tune else None,
                                       _stream_ptr(stream), ctypes.byref(st) if st else None))
         return (y, st.as_dict()) if stats else y
+
+    def pagerank(self, in_graph: DeviceCSR, out_degree: torch.Tensor, iterations: int, damping: float = 0.85,
+                 mode="grid", tune: Tune | None = None, out: torch.Tensor | None = None, stream=None,
+                 stats: bool = False):
+        """Ranks after `iterations` sweeps; in_graph is the transpose (in-edges) of
+        the graph, out_degree its vertices' out-degrees (int32, device)."""
+        r = out if out is not None else torch.empty(in_graph.n, dtype=torch.float32, device=in_graph.row_ptr.device)
+        st = Stats() if stats else None
+        cg = in_graph.c()
+        _check(load_library().wc_pagerank(self._ptr, ctypes.byref(cg), out_degree.data_ptr(), int(iterations),
+                                          float(damping), r.data_ptr(), _mode(mode),
+                                          ctypes.byref(tune) if tune else None, _stream_ptr(stream),
+                                          ctypes.byref(st) if st else None))
+        return (r, st.as_dict()) if stats else r
 
     def _tree(self, fn, t: DeviceTree, mode, tune, out, stream, stats):
         res = out if out is not None else torch.empty(t.n, dtype=torch.int32, device=t.parent.device)

@@ -1,0 +1,112 @@
+"""GPU parity of wc_pagerank against the binary64 oracle (relative bound
+oracle.PAGERANK_RTOL per vertex), every mode and tune, bit-identical repeats,
+special graphs, argument errors, and the scale-22 graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import say
+from paper_1606_08150_amd import wc
+
+pytestmark = pytest.mark.gpu
+MODES = ["flat", "wave", "block", "grid"]
+
+
+def upload(g):
+    t = synth.transpose(g)
+    return (wc.DeviceCSR.from_host(t.row_ptr, t.col), torch.from_numpy(synth.out_degree(g)).cuda(), t)
+
+
+def reference(g, t, iters, d=0.85):
+    return oracle.pagerank_f64(t.row_ptr, t.col, synth.out_degree(g), iters, d)
+
+
+@pytest.fixture(scope="module")
+def c1_pr(c1_graph):
+    g, _ = c1_graph
+    dg, od, t = upload(g)
+    return g, dg, od, t, {k: reference(g, t, k) for k in (0, 1, 10, 30)}
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_scale12_all_modes(ctx, c1_pr, mode):
+    g, dg, od, t, refs = c1_pr
+    for k, ref in refs.items():
+        say(f"pagerank scale 12 mode={mode} iterations={k}")
+        r = ctx.pagerank(dg, od, k, mode=mode)
+        torch.cuda.synchronize()
+        got = r.cpu().numpy()
+        assert oracle.pagerank_check(ref, got) == (0, -1), k
+        assert abs(float(got.astype(np.float64).sum()) - 1.0) < 1e-4
+
+
+@pytest.mark.parametrize("mode", ["block", "grid"])
+@pytest.mark.parametrize("tune", [dict(threshold=1), dict(threshold=100), dict(items_per_lane=1),
+                                  dict(items_per_lane=16), dict(block_threads=64), dict(block_threads=1024),
+                                  dict(grid_blocks=3)])
+def test_tune_sweep_and_repeats(ctx, c1_pr, mode, tune):
+    g, dg, od, t, refs = c1_pr
+    tt = wc.make_tune(**tune)
+    first = ctx.pagerank(dg, od, 10, mode=mode, tune=tt).cpu().numpy()
+    assert oracle.pagerank_check(refs[10], first) == (0, -1)
+    for _ in range(3):
+        again = ctx.pagerank(dg, od, 10, mode=mode, tune=tt).cpu().numpy()
+        assert np.array_equal(again.view(np.uint32), first.view(np.uint32))
+
+
+def special_graphs():
+    yield "single", synth.graph_from_edges(1, [])[0]
+    yield "no_edges", synth.graph_from_edges(50, [])[0]
+    yield "cycle", synth.graph_from_edges(9, [(i, (i + 1) % 9) for i in range(9)])[0]
+    yield "star_in", synth.graph_from_edges(3000, [(i, 0) for i in range(1, 3000)])[0]
+    yield "star_out", synth.graph_from_edges(3000, [(0, i) for i in range(1, 3000)])[0]
+    yield "self_and_multi", synth.graph_from_edges(5, [(0, 0), (0, 1), (0, 1), (1, 2), (2, 0), (3, 3)])[0]
+    yield "hub_in_one_window", synth.graph_from_edges(
+        700, [(u, v) for u in range(0, 700, 7) for v in range(600, 700)])[0]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_special_graphs(ctx, mode):
+    for name, g in special_graphs():
+        dg, od, t = upload(g)
+        for k in (0, 3, 20):
+            ref = reference(g, t, k)
+            got = ctx.pagerank(dg, od, k, mode=mode).cpu().numpy()
+            assert oracle.pagerank_check(ref, got) == (0, -1), (name, k)
+
+
+def test_invalid_arguments(ctx, c1_pr):
+    g, dg, od, t, refs = c1_pr
+    for kw in (dict(iterations=-1), dict(damping=1.5), dict(damping=float("nan"))):
+        args = dict(iterations=3, damping=0.85)
+        args.update(kw)
+        with pytest.raises(wc.WcError):
+            ctx.pagerank(dg, od, args["iterations"], damping=args["damping"])
+    with pytest.raises(wc.WcError):
+        ctx.pagerank(dg, od, 3, mode=9)
+
+
+def test_stats(ctx, c1_pr):
+    g, dg, od, t, refs = c1_pr
+    _, st = ctx.pagerank(dg, od, 10, mode="grid", stats=True)
+    assert st["rounds"] == 10 and st["edges_processed"] == 10 * t.row_ptr[-1]
+    assert 0 < st["edges_buffered"] < st["edges_processed"]
+
+
+@pytest.fixture(scope="module")
+def c2_pr():
+    say("generating scale-22 graph for PageRank")
+    g = synth.rmat_csr(22, 1 << 26)
+    dg, od, t = upload(g)
+    say("oracle PageRank at scale 22 (10 sweeps)")
+    return g, dg, od, reference(g, t, 10)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_scale22(ctx, c2_pr, mode):
+    g, dg, od, ref = c2_pr
+    say(f"pagerank scale 22 mode={mode}")
+    got = ctx.pagerank(dg, od, 10, mode=mode).cpu().numpy()
+    assert oracle.pagerank_check(ref, got) == (0, -1)
