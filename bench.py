@@ -50,6 +50,7 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=4000, help="requests per arrival rate")
     p.add_argument("--no-gather-ceiling", action="store_true", help="skip the bare-gather reference timing")
     p.add_argument("--no-cold", action="store_true", help="skip the cold-cache (L2 and MALL flushed) timings")
+    p.add_argument("--no-pagerank", action="store_true", help="skip the PageRank section")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -179,6 +180,35 @@ def summarize_profiles(fetch_dir, write_dir, copy_mb, workload, command):
                 json.dump(rec, f, indent=1)
             out[k] = rec
     print(json.dumps(out, indent=1))
+
+
+def run_pagerank(ctx, torch, synth, wc, stream, g, iters=10, reps=3):
+    """PageRank sweeps over the in-edges of the scale-22 graph: per sweep 8 B
+    per edge (source index, contribution gather) + 20 B per vertex (rank read,
+    out-degree, contribution write, in-edge sum write and read, rank write)."""
+    t = synth.transpose(g)
+    dg = wc.DeviceCSR.from_host(t.row_ptr, t.col)
+    od = torch.from_numpy(synth.out_degree(g)).cuda()
+    del t
+    r = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    alg = iters * (8.0 * g.m + 24.0 * g.n)
+    res = {}
+    for mode in ("flat", "wave", "block", "grid"):
+        ctx.pagerank(dg, od, iters, mode=mode, out=r)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ctx.pagerank(dg, od, iters, mode=mode, out=r)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        res[mode] = {"ms": round(ms, 3), "sweep_ms": round(ms / iters, 4),
+                     "gedges_s": round(iters * g.m / (ms * 1e-3) / 1e9, 2),
+                     "alg_gbs": round(alg / (ms * 1e-3) / 1e9, 1)}
+        print(f"[bench] pagerank {mode}: {res[mode]}", file=sys.stderr, flush=True)
+    return {"workload": f"PageRank, damping 0.85, {iters} sweeps over the in-edges of the scale-22 R-MAT graph",
+            "modes": res}
 
 
 def run_trees(ctx, torch, synth, wc, stream, n=1 << 22, reps=5):
@@ -507,6 +537,11 @@ def main():
             modes[mode] = res
             print(f"[bench] mode {mode}: {res}", file=sys.stderr, flush=True)
 
+    # ---- PageRank on the same graph (in-edges), 10 sweeps, every mode
+    pagerank = None
+    if not args.no_pagerank:
+        pagerank = run_pagerank(ctx, torch, synth, wc, stream, g)
+
     # ---- trees: descendants and heights on the 2^22-node random tree, every mode
     trees = None
     if not args.no_trees:
@@ -572,6 +607,7 @@ def main():
                       "rounds": sst["rounds"], "items_buffered": sst["items_buffered"]},
         "kernels": kernels,
         "modes": modes,
+        "pagerank": pagerank,
         "trees": trees,
         "batch": batch,
         "serving": serving,
