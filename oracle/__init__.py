@@ -43,6 +43,7 @@ def _load():
         "orc_spmv_f64": (None, [c.c_int32, i32p, i32p, f32p, f32p, f64p, f64p]),
         "orc_spmv_check": (c.c_int64, [c.c_int32, f64p, f64p, f32p, c.c_double, pi64]),
         "orc_pagerank_f64": (c.c_int, [c.c_int32, i32p, i32p, i32p, c.c_int32, c.c_double, f64p]),
+        "orc_bfs": (c.c_int, [c.c_int32, i32p, i32p, c.c_int32, u32p]),
         "orc_tree_validate": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
         "orc_tree_descendants": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
         "orc_tree_height": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
@@ -107,6 +108,15 @@ def sssp_reached_edges(row_ptr, dist) -> int:
 
 
 # ---- SpMV ---------------------------------------------------------------------------------------
+
+def bfs(row_ptr, col, src: int):
+    """Breadth-first levels (uint32, INF unreachable)."""
+    n = len(row_ptr) - 1
+    lv = np.empty(max(n, 1), dtype=np.uint32)
+    if _load().orc_bfs(n, _i32(row_ptr), _nonempty(col, np.int32), int(src), lv) != 0:
+        raise MemoryError("orc_bfs")
+    return lv[:n]
+
 
 def spmv_f64(row_ptr, col, val, x):
     """(y_ref, b): binary64 product and per-row sum of |a_ij x_j|."""

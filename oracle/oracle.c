@@ -13,6 +13,8 @@
  *           with positive integer weights (the irregular loop of Fig. 1(b)).
  *           Binary-heap Dijkstra; Bellman-Ford as a brute-force cross-check;
  *           an O(m) optimality certificate usable at any size.
+ *   BFS   - breadth-first levels from one source (the recursive BFS of
+ *           Sec. V reaches the same levels).  A FIFO queue.
  *   SpMV  - y = A x in binary64 plus the per-row magnitude sum
  *           b[r] = sum |a_rj x_j| used by the tolerance test (Sec. V lists
  *           SpMV among the irregular-loop benchmarks).
@@ -202,6 +204,34 @@ int64_t orc_sssp_reached_edges(int32_t n, const int32_t *row_ptr, const uint32_t
     for (int32_t v = 0; v < n; ++v)
         if (dist[v] != ORC_INF) s += row_ptr[v + 1] - row_ptr[v];
     return s;
+}
+
+/* ----------------------------------------------------------------- BFS ---- */
+
+/* Breadth-first levels from src (the BFS-Rec benchmark of Sec. V computes the
+ * same levels by recursion): level[v] = number of edges on a shortest path, or
+ * ORC_INF if v is unreachable.  A FIFO queue.  Returns 0, or -1 if memory runs
+ * out. */
+int orc_bfs(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t src, uint32_t *level)
+{
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return -1;
+    for (int32_t v = 0; v < n; ++v) level[v] = ORC_INF;
+    int32_t head = 0, tail = 0;
+    level[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int32_t v = col[e];
+            if (level[v] == ORC_INF) {
+                level[v] = level[u] + 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    free(queue);
+    return 0;
 }
 
 /* ---------------------------------------------------------------- SpMV ---- */
