@@ -400,6 +400,9 @@ def main():
     def spmv(mode):
         ctx.spmv(dg, dval, dx, mode=mode, out=y)
 
+    def bfs(mode):
+        ctx.bfs(dg, 0, mode=mode, out=dist)
+
     # reached edges (GTEPS numerator) from the GPU result: out-edges of vertices with finite distance
     sssp(args.mode)
     torch.cuda.synchronize()
@@ -520,7 +523,7 @@ def main():
     if not args.no_modes:
         for mode in ("flat", "wave", "block", "grid"):
             res = {}
-            for prob, fn in (("sssp", sssp), ("spmv", spmv)):
+            for prob, fn in (("sssp", sssp), ("spmv", spmv), ("bfs", bfs)):
                 fn(mode)
                 torch.cuda.synchronize()
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -534,6 +537,8 @@ def main():
                 res[prob + "_ms"] = round(ms, 3)
             res["sssp_gteps"] = round(m_reached / (res["sssp_ms"] * 1e-3) / 1e9, 3)
             res["spmv_gbs"] = round(spmv_bytes / (res["spmv_ms"] * 1e-3) / 1e9, 1)
+            # BFS from vertex 0 reaches the same vertices as the SSSP: same edge count
+            res["bfs_gteps"] = round(m_reached / (res["bfs_ms"] * 1e-3) / 1e9, 3)
             modes[mode] = res
             print(f"[bench] mode {mode}: {res}", file=sys.stderr, flush=True)
 

@@ -142,6 +142,15 @@ wc_status wc_ctx_destroy(wc_ctx *ctx);
 wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, uint32_t *dist, wc_mode mode,
                   const wc_tune *tune, hipStream_t stream, wc_stats *stats);
 
+/* Breadth-first levels (recursive BFS, the BFS-Rec benchmark of Sec. V): level[v]
+ * = number of edges on a shortest path src -> v, UINT32_MAX if v is unreachable.
+ * A visit of v is a recursive call whose children are the neighbours it brings
+ * to a lower level; consolidation groups the calls of one depth (the frontier)
+ * per `mode`, so this is wc_sssp with every edge weighing 1, on the same
+ * kernels.  level[n] is written entirely. */
+wc_status wc_bfs(wc_ctx *ctx, const wc_csr *g, int32_t src, uint32_t *level, wc_mode mode, const wc_tune *tune,
+                 hipStream_t stream, wc_stats *stats);
+
 /* Sparse matrix-vector product y = A x, A in CSR with values val[m] (fp32),
  * x[n] and y[n] fp32 (square n x n).  A row with more than `threshold`
  * nonzeros is consolidated per `mode`; a lighter row is summed inline by one

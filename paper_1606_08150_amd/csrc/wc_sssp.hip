@@ -41,7 +41,7 @@ constexpr int kUnroll = 4;  // edges in flight per lane
 struct SsspArgs {
     const int *row_ptr;
     const int *col;
-    const uint32_t *w;
+    const uint32_t *w;  // nullptr: unit weights (breadth-first levels)
     uint32_t *dist;
     int *stamp;       // stamp[v] == r: v is a frontier vertex of round r
     uint32_t *relaxed_at;  // grid mode: the largest distance v's edges were last relaxed with;
@@ -57,6 +57,9 @@ struct SsspArgs {
     DevStats *stats;
     int want_stats;
 };
+
+// Edge weight; without weights (breadth-first levels) every edge weighs 1.
+__device__ __forceinline__ uint32_t weight(const SsspArgs &a, int e) { return a.w ? a.w[e] : 1u; }
 
 __device__ __forceinline__ uint32_t add_sat(uint32_t du, uint32_t w)
 {
@@ -94,7 +97,7 @@ __device__ __forceinline__ int relax_batch(const SsspArgs &a, int first, int str
         const int e = first + k * stride;
         const bool ok = e < end;
         v[k] = ok ? a.col[e] : -1;
-        wt[k] = ok ? a.w[e] : 0u;
+        wt[k] = ok ? weight(a, e) : 0u;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
@@ -143,7 +146,7 @@ __device__ __forceinline__ int relax_wave2(const SsspArgs &a, int u0, int cb0, i
             const int e = (k < kUnroll ? cb0 : cb1) + o + (k % kUnroll) * kWave;
             const bool ok = e < (k < kUnroll ? ce0 : ce1);
             v[k] = ok ? a.col[e] : -1;
-            wt[k] = ok ? a.w[e] : 0u;
+            wt[k] = ok ? weight(a, e) : 0u;
         }
         const uint32_t du0 = a.dist[u0];
         const uint32_t du1 = cb1 < ce1 ? a.dist[u1] : 0u;
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
                         while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
                         const int e = sb.beg[it] + (j - sb.pre[it]);
                         v[q] = a.col[e];
-                        nd[q] = add_sat(sb.du[it], a.w[e]);
+                        nd[q] = add_sat(sb.du[it], weight(a, e));
                     }
                 }
 #pragma unroll
@@ -282,7 +285,7 @@ __device__ __forceinline__ int relax_lane2(const SsspArgs &a, int b0, int e0, ui
             const int e = (k < U ? b0 : b1) + o + (k % U);
             const bool ok = e < (k < U ? e0 : e1);
             v[k] = ok ? a.col[e] : -1;
-            nd[k] = ok ? add_sat(k < U ? du0 : du1, a.w[e]) : 0u;
+            nd[k] = ok ? add_sat(k < U ? du0 : du1, weight(a, e)) : 0u;
         }
 #pragma unroll
         for (int k = 0; k < 2 * U; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
@@ -524,18 +527,14 @@ KernelSet pick(wc_mode mode, int block)
 
 using namespace wc;
 
-extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, uint32_t *dist,
-                             wc_mode mode, const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+namespace wc {
+namespace {
+
+// Shortest paths from src with weights w, or breadth-first levels when w is
+// NULL (every edge weighs 1).  Arguments are validated by the callers.
+wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, uint32_t *dist, wc_mode mode,
+                   const wc_tune *tune, hipStream_t stream, wc_stats *stats)
 {
-    if (!ctx || !g) return fail(WC_EINVAL, "wc_sssp: NULL context or graph");
-    if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "wc_sssp: bad mode");
-    if (g->n < 0 || g->m < 0) return fail(WC_EINVAL, "wc_sssp: negative size");
-    if (g->n == 0) {
-        if (stats) std::memset(stats, 0, sizeof(*stats));
-        return WC_OK;
-    }
-    if (src < 0 || src >= g->n) return fail(WC_EINVAL, "wc_sssp: source out of range");
-    if (!g->row_ptr || !dist || (g->m > 0 && (!g->col || !w))) return fail(WC_EINVAL, "wc_sssp: NULL array");
     WC_HIP(hipSetDevice(ctx->device));
 
     Config cfg;
@@ -615,4 +614,45 @@ extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, in
         if (rounds > n + 1) return fail(WC_ETIMEOUT, "wc_sssp: more rounds than vertices");
     }
     return end_call(ctx, stream, stats, rounds, cfg.fail_on_overflow);
+}
+
+// Validation shared by both entry points.
+wc_status check_args(const char *who, wc_ctx *ctx, const wc_csr *g, int32_t src, const uint32_t *dist, wc_mode mode)
+{
+    const std::string w(who);
+    if (!ctx || !g) return fail(WC_EINVAL, w + ": NULL context or graph");
+    if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, w + ": bad mode");
+    if (g->n < 0 || g->m < 0) return fail(WC_EINVAL, w + ": negative size");
+    if (g->n > 0 && (src < 0 || src >= g->n)) return fail(WC_EINVAL, w + ": source out of range");
+    if (g->n > 0 && (!g->row_ptr || !dist || (g->m > 0 && !g->col))) return fail(WC_EINVAL, w + ": NULL array");
+    return WC_OK;
+}
+
+}  // namespace
+}  // namespace wc
+
+extern "C" wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, uint32_t *dist,
+                             wc_mode mode, const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+{
+    wc_status st = check_args("wc_sssp", ctx, g, src, dist, mode);
+    if (st != WC_OK) return st;
+    if (g->n > 0 && g->m > 0 && !w) return fail(WC_EINVAL, "wc_sssp: NULL weights");
+    if (g->n == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return WC_OK;
+    }
+    // without edges w may be NULL: the result does not depend on weights
+    return run_sssp(ctx, g, w, src, dist, mode, tune, stream, stats);
+}
+
+extern "C" wc_status wc_bfs(wc_ctx *ctx, const wc_csr *g, int32_t src, uint32_t *level, wc_mode mode,
+                            const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+{
+    wc_status st = check_args("wc_bfs", ctx, g, src, level, mode);
+    if (st != WC_OK) return st;
+    if (g->n == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return WC_OK;
+    }
+    return run_sssp(ctx, g, nullptr, src, level, mode, tune, stream, stats);
 }

@@ -21,7 +21,8 @@ MODES = {"flat": FLAT, "wave": WAVE, "block": BLOCK, "grid": GRID}
 STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: "WC_ETIMEOUT", -5: "WC_EHIP"}
 
 # C-ABI symbols declared in include/wc.h
-EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_spmv", "wc_pagerank", "wc_tree_descendants", "wc_tree_height",
+EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_pagerank", "wc_tree_descendants",
+           "wc_tree_height",
            "wc_sssp_batch",
            "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size",
            "wc_kc_config", "wc_default_tune")
@@ -81,6 +82,8 @@ def load_library():
     lib.wc_ctx_destroy.argtypes = [vp]
     lib.wc_sssp.restype = c.c_int
     lib.wc_sssp.argtypes = [vp, c.POINTER(CCsr), vp, c.c_int32, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_bfs.restype = c.c_int
+    lib.wc_bfs.argtypes = [vp, c.POINTER(CCsr), c.c_int32, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_spmv.restype = c.c_int
     lib.wc_spmv.argtypes = [vp, c.POINTER(CCsr), vp, vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_pagerank.restype = c.c_int
@@ -282,6 +285,17 @@ class Context:
         _check(load_library().wc_sssp_batch(self._ptr, k, cg, cw, cs, cd, cm, ct, graph_rounds, _stream_ptr(stream),
                                             ctypes.byref(st) if st else None))
         return (outs, st.as_dict()) if stats else outs
+
+    def bfs(self, g: DeviceCSR, src: int, mode="grid", tune: Tune | None = None, out: torch.Tensor | None = None,
+            stream=None, stats: bool = False):
+        """Breadth-first levels from src (int32 view of uint32; -1 = unreachable)."""
+        lv = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+        st = Stats() if stats else None
+        cg = g.c()
+        _check(load_library().wc_bfs(self._ptr, ctypes.byref(cg), int(src), lv.data_ptr(), _mode(mode),
+                                     ctypes.byref(tune) if tune else None, _stream_ptr(stream),
+                                     ctypes.byref(st) if st else None))
+        return (lv, st.as_dict()) if stats else lv
 
     def spmv(self, a: DeviceCSR, val: torch.Tensor, x: torch.Tensor, mode="grid", tune: Tune | None = None,
              out: torch.Tensor | None = None, stream=None, stats: bool = False):
