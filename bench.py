@@ -51,6 +51,7 @@ def parse():
     p.add_argument("--no-gather-ceiling", action="store_true", help="skip the bare-gather reference timing")
     p.add_argument("--no-cold", action="store_true", help="skip the cold-cache (L2 and MALL flushed) timings")
     p.add_argument("--no-pagerank", action="store_true", help="skip the PageRank section")
+    p.add_argument("--no-ablation", action="store_true", help="skip the basic dynamic parallelism comparison")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -209,6 +210,38 @@ def run_pagerank(ctx, torch, synth, wc, stream, g, iters=10, reps=3):
         print(f"[bench] pagerank {mode}: {res[mode]}", file=sys.stderr, flush=True)
     return {"workload": f"PageRank, damping 0.85, {iters} sweeps over the in-edges of the scale-22 R-MAT graph",
             "modes": res}
+
+
+def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
+    """The paper's comparison against basic dynamic parallelism (Fig. 7, Fig. 8's
+    launch counts), on this GPU: SSSP with one host-launched child per buffered
+    vertex (tune driver 2, no consolidation) beside flat and the three
+    consolidation levels, on smaller R-MAT graphs (the per-vertex launches make
+    the basic variant slow)."""
+    out = {}
+    for scale in scales:
+        g = synth.rmat_csr(scale, 16 << scale)
+        w = synth.weights(g.m)
+        dg = wc.DeviceCSR.from_host(g.row_ptr, g.col)
+        dw = torch.from_numpy(w.view(np.int32)).cuda()
+        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        row = {}
+        for name, mode, tune in (("basic_dp", "grid", wc.make_tune(driver=2)), ("flat", "flat", None),
+                                 ("wave", "wave", None), ("block", "block", None), ("grid", "grid", None)):
+            _, st = ctx.sssp(dg, dw, 0, mode=mode, tune=tune, out=dist, stats=True)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                ctx.sssp(dg, dw, 0, mode=mode, tune=tune, out=dist)
+            b.record(stream)
+            torch.cuda.synchronize()
+            row[name] = {"ms": round(a.elapsed_time(b) / reps, 3), "child_dispatches": st["dispatches"]}
+        for name in ("flat", "wave", "block", "grid"):
+            row[name]["speedup_vs_basic_dp"] = round(row["basic_dp"]["ms"] / row[name]["ms"], 1)
+        out[f"rmat{scale}"] = row
+        print(f"[bench] ablation scale {scale}: {row}", file=sys.stderr, flush=True)
+    return {"workload": "SSSP from vertex 0 on R-MAT graphs of 2^12 and 2^16 vertices, degree 16", "results": out}
 
 
 def run_trees(ctx, torch, synth, wc, stream, n=1 << 22, reps=5):
@@ -547,6 +580,11 @@ def main():
     if not args.no_pagerank:
         pagerank = run_pagerank(ctx, torch, synth, wc, stream, g)
 
+    # ---- consolidated vs basic dynamic parallelism (per-vertex child launches)
+    ablation = None
+    if not args.no_ablation:
+        ablation = run_ablation(ctx, torch, synth, wc, stream)
+
     # ---- trees: descendants and heights on the 2^22-node random tree, every mode
     trees = None
     if not args.no_trees:
@@ -613,6 +651,7 @@ def main():
         "kernels": kernels,
         "modes": modes,
         "pagerank": pagerank,
+        "basic_dp_ablation": ablation,
         "trees": trees,
         "batch": batch,
         "serving": serving,

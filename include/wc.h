@@ -100,7 +100,12 @@ typedef struct {
                                items per drain lane; grid-level chunks hold
                                64 * items_per_lane elements; <= 0: 4 */
     int32_t driver;         /* 0: one launch per round/level (host relaunch);
-                               1: one persistent co-resident launch with a grid barrier */
+                               1: one persistent co-resident launch with a grid barrier
+                                  (refused: WC_EINVAL);
+                               2: SSSP grid mode only, for comparison: basic dynamic
+                                  parallelism emulated, one host-launched child per
+                                  buffered vertex, no consolidation (stats->dispatches
+                                  counts the child launches) */
     int32_t allow_fallback; /* on buffer overflow: >= 0 (default) the item that does not fit
                                is processed inline and stats->overflowed is set;
                                < 0 the call returns WC_EOVERFLOW after its work ends */

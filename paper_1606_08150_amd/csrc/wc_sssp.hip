@@ -25,6 +25,7 @@
 // and schedule yields identical results.
 #include <cstring>
 #include <algorithm>
+#include <vector>
 
 
 #include "wc_block.h"
@@ -473,6 +474,22 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
     }
 }
 
+// basic dynamic parallelism, emulated for comparison (driver 2): the child of
+// ONE buffered vertex, thread-mapped over its edges, launched per vertex by
+// the host.  Same relaxation as the drain.
+__global__ __launch_bounds__(256) void sssp_child_basic(SsspArgs a, int r, int u, int beg, int end)
+{
+    const int e = beg + blockIdx.x * 256 + threadIdx.x;
+    const uint32_t du = a.dist[u];
+    int upd = 0;
+    if (e < end) {
+        const int v = a.col[e];
+        upd = relax_loaded<false>(a, v, add_sat(du, weight(a, e)), a.dist[v], r + 1);
+    }
+    if (threadIdx.x == 0) atomic_max_dev_noret(&a.relaxed_at[u], du);
+    mark_active(a, r, upd > 0);
+}
+
 __global__ void sssp_init(SsspArgs a, int src)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -545,6 +562,8 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     if (st != WC_OK) return st;
     if (cfg.driver == 1)
         return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
+    if (cfg.driver == 2 && mode != WC_GRID)
+        return fail(WC_EINVAL, "the basic driver (driver = 2) emulates per-item child launches of grid mode only");
     if (cfg.block != block) {
         ks = pick(mode, cfg.block);
         resident = resident_blocks(ctx, ks.round, cfg.block);
@@ -589,6 +608,50 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
         st = launch(ctx, "sssp_init", reinterpret_cast<const void *>(&sssp_init), dim3(init_grid), dim3(256), args,
                     stream);
         if (st != WC_OK) return st;
+    }
+    if (cfg.driver == 2) {
+        // Basic dynamic parallelism, emulated: after each parent round the host
+        // reads the buffered vertices back and launches one child per vertex
+        // (no consolidation), then waits for the round to end.
+        std::vector<int4> items;
+        int rounds = 0;
+        for (int r = 0;; ++r) {
+            void *args[] = {&a, &r};
+            st = launch(ctx, "sssp_round_grid", ks.round, dim3(grid), dim3(cfg.block), args, stream);
+            if (st != WC_OK) return st;
+            int tail = 0, act = 0;
+            WC_HIP(hipMemcpyAsync(&tail, a.chunk_tail + (r % 3) * kPad, sizeof(int), hipMemcpyDeviceToHost, stream));
+            WC_HIP(hipStreamSynchronize(stream));
+            const int count = (int)std::min<long long>(tail, a.chunk_cap);
+            items.resize((size_t)std::max(count, 1));
+            if (count > 0)
+                WC_HIP(hipMemcpy(items.data(), a.chunks, sizeof(int4) * (size_t)count, hipMemcpyDeviceToHost));
+            chain_break(ctx);
+            long long launches = 0;
+            for (int i = 0; i < count;) {
+                // a vertex's chunks are consecutive: one child over all its edges
+                int j = i + 1;
+                while (j < count && items[j].x == items[i].x && items[j].y == items[j - 1].z) ++j;
+                int u = items[i].x, beg = items[i].y, end = items[j - 1].z;
+                void *cargs[] = {&a, &r, &u, &beg, &end};
+                st = launch(ctx, "sssp_child_basic", reinterpret_cast<const void *>(&sssp_child_basic),
+                            dim3((end - beg + 255) / 256), dim3(256), cargs, stream);
+                if (st != WC_OK) return st;
+                ++launches;
+                i = j;
+            }
+            if (stats) stats->dispatches += launches;
+            WC_HIP(hipMemcpyAsync(&act, a.active + ((r + 1) % 3) * kPad, sizeof(int), hipMemcpyDeviceToHost, stream));
+            WC_HIP(hipStreamSynchronize(stream));
+            chain_break(ctx);
+            ++rounds;
+            if (!act) break;
+            if (rounds > n + 1) return fail(WC_ETIMEOUT, "wc_sssp: more rounds than vertices");
+        }
+        const int64_t launches = stats ? stats->dispatches : 0;
+        st = end_call(ctx, stream, stats, rounds, cfg.fail_on_overflow);
+        if (stats) stats->dispatches = launches;
+        return st;
     }
     // Relaunch driver: keep `window` rounds in flight; each round kernel
     // publishes whether its frontier is non-empty to pinned host memory, and the

@@ -111,6 +111,22 @@ def test_persistent_driver_is_refused(ctx, c1):
     assert ei.value.status == -1
 
 
+def test_basic_driver_emulates_per_vertex_children(ctx, c1):
+    """driver = 2: one host-launched child per buffered vertex (the unconsolidated
+    basic-dp baseline); same distances, and one dispatch per heavy expansion."""
+    g, w, ref = c1
+    dg, dw = upload(g, w)
+    d, st = ctx.sssp(dg, dw, 0, mode="grid", tune=wc.make_tune(driver=2), stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev_to_u32(d), ref)
+    assert st["dispatches"] == st["items_buffered"] >= 1
+    for mode in ("flat", "wave", "block"):
+        with pytest.raises(wc.WcError):
+            ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(driver=2))
+    with pytest.raises(wc.WcError):
+        ctx.sssp(dg, dw, 0, mode="grid", tune=wc.make_tune(driver=3))
+
+
 def test_invalid_arguments(ctx, c1):
     g, w, _ = c1
     dg, dw = upload(g, w)
