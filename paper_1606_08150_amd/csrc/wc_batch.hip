@@ -346,17 +346,16 @@ __global__ __launch_bounds__(BLOCK) void batch_drain(BatchArgs a, int r)
     bool any = false;
     // two chunks per wave and step; the next pair's entries are fetched before
     // the current pair's edges
-    const int4 zero = make_int4(0, 0, 0, 0);
-    int4 q0 = gw < total ? a.chunks[gw] : zero;
-    int4 q1 = gw + nw < total ? a.chunks[gw + nw] : zero;
+    int4 q0 = load_or_zero(a.chunks, gw, gw < total);
+    int4 q1 = load_or_zero(a.chunks, gw + nw, gw + nw < total);
     for (int c = gw; c < total; c += 2 * nw) {
         const int g0 = __builtin_amdgcn_readfirstlane(q0.x), i0 = __builtin_amdgcn_readfirstlane(q0.w);
         const int cb0 = __builtin_amdgcn_readfirstlane(q0.y), ce0 = __builtin_amdgcn_readfirstlane(q0.z);
         const int g1 = __builtin_amdgcn_readfirstlane(q1.x), i1 = __builtin_amdgcn_readfirstlane(q1.w);
         const int cb1 = __builtin_amdgcn_readfirstlane(q1.y), ce1 = __builtin_amdgcn_readfirstlane(q1.z);
         const int cn = c + 2 * nw;
-        q0 = cn < total ? a.chunks[cn] : zero;
-        q1 = cn + nw < total ? a.chunks[cn + nw] : zero;
+        q0 = load_or_zero(a.chunks, cn, cn < total);
+        q1 = load_or_zero(a.chunks, cn + nw, cn + nw < total);
         uint32_t du0, du1;
         any |= relax_pair(a, g0, i0, cb0, ce0, g1, i1, cb1, ce1, next, du0, du1);
         if (lane_id() == 0) {

@@ -30,6 +30,16 @@ __device__ __forceinline__ uint32_t readlane_u(uint32_t v, int lane)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
+// ---- guarded loads ---------------------------------------------------------------------------
+// arr[i] when ok, else zero, without a select between a global address and a
+// local temporary (which the compiler would otherwise materialise on the stack).
+__device__ __forceinline__ int4 load_or_zero(const int4 *arr, long long i, bool ok)
+{
+    int4 v = make_int4(0, 0, 0, 0);
+    if (ok) v = arr[i];
+    return v;
+}
+
 // ---- scoped atomics ---------------------------------------------------------------------------
 __device__ __forceinline__ int atomic_add_dev(int *p, int v)
 {

@@ -450,15 +450,15 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
     int upd = 0;
     // two chunks per wave and step; the next pair's entries are fetched before
     // the current pair's edges
-    int4 d0 = gw < total ? a.chunks[gw] : make_int4(0, 0, 0, 0);
-    int4 d1 = gw + nw < total ? a.chunks[gw + nw] : make_int4(0, 0, 0, 0);
+    int4 d0 = load_or_zero(a.chunks, gw, gw < total);
+    int4 d1 = load_or_zero(a.chunks, gw + nw, gw + nw < total);
     for (int c = gw; c < total; c += 2 * nw) {
         const int u0 = __builtin_amdgcn_readfirstlane(d0.x), u1 = __builtin_amdgcn_readfirstlane(d1.x);
         const int cb0 = __builtin_amdgcn_readfirstlane(d0.y), ce0 = __builtin_amdgcn_readfirstlane(d0.z);
         const int cb1 = __builtin_amdgcn_readfirstlane(d1.y), ce1 = __builtin_amdgcn_readfirstlane(d1.z);
         const int cn = c + 2 * nw;
-        d0 = cn < total ? a.chunks[cn] : make_int4(0, 0, 0, 0);
-        d1 = cn + nw < total ? a.chunks[cn + nw] : make_int4(0, 0, 0, 0);
+        d0 = load_or_zero(a.chunks, cn, cn < total);
+        d1 = load_or_zero(a.chunks, cn + nw, cn + nw < total);
         uint32_t du0, du1;
         upd += relax_wave2(a, u0, cb0, ce0, u1, cb1, ce1, next, du0, du1);
         if (lane_id() == 0) {
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
     mark_active(a, r, upd > 0);
     if (a.want_stats) {
         StatAcc acc;
-        acc.updates = acc.updates_buffered = (unsigned long long)upd;
+        acc.updates = acc.updates_buffered = (unsigned int)upd;
         stat_flush(a.stats, acc);
     }
 }

@@ -8,8 +8,10 @@
 
 namespace wc {
 
+// 32-bit per thread: a thread's share of one kernel's work is bounded by the
+// int32 edge and vertex counts of the CSR; the block sums are 64-bit.
 struct StatAcc {
-    unsigned long long items = 0, dispatches = 0, edges = 0, buffered = 0, updates = 0, updates_buffered = 0;
+    unsigned int items = 0, dispatches = 0, edges = 0, buffered = 0, updates = 0, updates_buffered = 0;
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -26,7 +28,8 @@ __device__ __forceinline__ void stat_flush(DevStats *s, const StatAcc &acc)
     __shared__ unsigned long long sh[K];
     if (threadIdx.x < K) sh[threadIdx.x] = 0;
     __syncthreads();
-    unsigned long long v[K] = {acc.items, acc.dispatches, acc.edges, acc.buffered, acc.updates, acc.updates_buffered};
+    unsigned long long v[K] = {acc.items, acc.dispatches, acc.edges, acc.buffered, acc.updates,
+                               acc.updates_buffered};
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum_u64(v[k]);
     if (lane_id() == 0) {
