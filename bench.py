@@ -244,10 +244,10 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
     return {"workload": "SSSP from vertex 0 on R-MAT graphs of 2^12 and 2^16 vertices, degree 16", "results": out}
 
 
-def run_trees(ctx, torch, synth, wc, stream, n=1 << 22, reps=5):
-    """Tree descendants and heights, 20 B per node per pass (child_ptr, child,
-    output, buffer entry): two passes (down and up) per call."""
-    t = synth.random_tree(n)
+def time_tree(ctx, torch, wc, stream, t, reps):
+    """Every mode on one tree: descendants and heights, 20 B per node per pass
+    (child_ptr, child, output, buffer entry), two passes (down and up) per call."""
+    n = t.n
     dt = wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     res = {}
@@ -267,8 +267,28 @@ def run_trees(ctx, torch, synth, wc, stream, n=1 << 22, reps=5):
             row[what + "_gnodes_s"] = round(n / (ms * 1e-3) / 1e9, 3)
             row[what + "_alg_gbs"] = round(2 * 20.0 * n / (ms * 1e-3) / 1e9, 1)
         res[mode] = row
-        print(f"[bench] tree {mode}: {row}", file=sys.stderr, flush=True)
-    return {"workload": f"random tree, {n} nodes, power-law fanout (alpha 2, max 4096), depth cap 24", "modes": res}
+    return res
+
+
+def run_trees(ctx, torch, synth, wc, stream, n=1 << 22, reps=5):
+    """The 2^22-node random tree, and two fixed-depth trees in the manner of the
+    paper's tree sets (Sec. V): fanout 128..256 with half of the inner nodes
+    having children, and fanout 32..128 with all of them, each 4 levels deep."""
+    out = {}
+    for name, make, what in (
+            ("random", lambda: synth.random_tree(n),
+             f"random tree, {n} nodes, power-law fanout (alpha 2, max 4096), depth cap 24"),
+            ("layered_half", lambda: synth.layered_tree(3, 128, 256, 0.5),
+             "layered tree, 3 levels below the root, fanout 128..256, half of the inner nodes with children"),
+            ("layered_full", lambda: synth.layered_tree(4, 32, 128, 1.0),
+             "layered tree, 4 levels below the root, fanout 32..128, every inner node with children")):
+        t = make()
+        res = time_tree(ctx, torch, wc, stream, t, reps)
+        out[name] = {"workload": what, "nodes": t.n, "modes": res}
+        for mode, row in res.items():
+            print(f"[bench] tree {name} {mode}: {row}", file=sys.stderr, flush=True)
+        del t
+    return out
 
 
 def run_batch(args, ctx, torch, synth, wc):

@@ -164,6 +164,35 @@ def random_tree(n: int, seed: int = SEED_TREE, kmax: int = 4096, alpha: float = 
     return Tree(n, parent, child_ptr, child, depth)
 
 
+def layered_tree(levels: int, fan_lo: int, fan_hi: int, internal_fraction: float = 1.0, seed: int = SEED_TREE,
+                 stream: int = 500) -> Tree:
+    """Tree of fixed depth in the manner of the paper's tree sets (Sec. V):
+    every node above the last level has children with probability
+    internal_fraction (the root always), and then a fanout drawn uniformly from
+    [fan_lo, fan_hi]; nodes are numbered level by level, a node's children
+    consecutively.  Level d's draws come from streams (stream + 2d, stream + 2d + 1)."""
+    if not (1 <= fan_lo <= fan_hi) or levels < 0:
+        raise ValueError("bad layered tree parameters")
+    parent = [np.array([-1], dtype=np.int64)]
+    level = np.array([0], dtype=np.int64)
+    next_id = 1
+    for d in range(levels):
+        k = level.size
+        r1 = rand_u64(seed, stream + 2 * d, k)
+        r2 = rand_u64(seed, stream + 2 * d + 1, k)
+        has = (r1 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53 < internal_fraction
+        if d == 0:
+            has[:] = True
+        fan = np.where(has, fan_lo + (r2 % np.uint64(fan_hi - fan_lo + 1)).astype(np.int64), 0)
+        total = int(fan.sum())
+        if next_id + total > 2 ** 31 - 1:
+            raise ValueError("layered tree larger than int32 ids allow")
+        parent.append(np.repeat(level, fan))
+        level = np.arange(next_id, next_id + total, dtype=np.int64)
+        next_id += total
+    return tree_from_parent(np.concatenate(parent).astype(np.int32))
+
+
 # ---- batches of independent instances ----------------------------------------------------------
 
 def batch_sizes(count: int, lo_log2: float = 10.0, hi_log2: float = 18.0, seed: int = SEED_GRAPH,

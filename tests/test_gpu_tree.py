@@ -57,6 +57,9 @@ def shapes():
     yield "kary7", synth.kary_tree(7, 4)
     yield "wide_fanout", synth.random_tree(20000, seed=77, kmax=4096, alpha=1.2)
     yield "narrow", synth.random_tree(20000, seed=78, kmax=3, alpha=0.5, max_depth=1 << 20)
+    # fixed-depth trees in the manner of the paper's tree sets (Sec. V)
+    yield "layered_half", synth.layered_tree(3, 8, 16, 0.5, seed=79)
+    yield "layered_full", synth.layered_tree(2, 128, 256, 1.0, seed=80)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -153,3 +156,19 @@ def test_level_graph_replays(ctx, mode):
             e = ctx.tree_height(other_dt, mode="grid")
             torch.cuda.synchronize()
             assert np.array_equal(e.cpu().numpy(), other_ref)
+
+
+@pytest.fixture(scope="module")
+def dataset1_like():
+    say("generating the dataset1-like layered tree")
+    t = synth.layered_tree(3, 128, 256, 0.5)
+    return t, oracle.tree_descendants(t.child_ptr, t.child), oracle.tree_height(t.child_ptr, t.child)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_dataset1_like_tree(ctx, dataset1_like, mode):
+    """Depth 3 below the root, fanout 128..256, half of the inner nodes with
+    children (about 1.7M nodes)."""
+    t, d, h = dataset1_like
+    assert np.array_equal(run(ctx, t, "desc", mode), d)
+    assert np.array_equal(run(ctx, t, "height", mode), h)

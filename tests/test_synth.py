@@ -74,3 +74,27 @@ def test_small_shapes():
     t = synth.kary_tree(3, 2)
     assert t.n == 13 and oracle.tree_validate(t.parent, t.child_ptr, t.child) == 0
     assert oracle.tree_validate(*[getattr(synth.chain_tree(5), k) for k in ("parent", "child_ptr", "child")]) == 0
+
+
+def test_layered_tree_shape():
+    for levels, lo, hi, frac in ((3, 8, 16, 0.5), (2, 32, 128, 1.0), (4, 2, 3, 1.0)):
+        t = synth.layered_tree(levels, lo, hi, frac, seed=9)
+        u = synth.layered_tree(levels, lo, hi, frac, seed=9)
+        assert np.array_equal(t.parent, u.parent)  # seeded
+        fan = np.diff(t.child_ptr)
+        assert fan[0] >= lo and np.all((fan == 0) | ((fan >= lo) & (fan <= hi)))
+        # depth of every node, from the parent array (parents have smaller ids)
+        depth = np.zeros(t.n, dtype=np.int64)
+        for v in range(1, t.n):
+            depth[v] = depth[t.parent[v]] + 1
+        assert depth.max() == levels
+        assert np.all(fan[depth == levels] == 0)
+        if frac == 1.0:
+            assert np.all(fan[depth < levels] > 0)
+        else:
+            inner = fan[(depth > 0) & (depth < levels)] > 0
+            assert 0.3 < inner.mean() < 0.7
+        # children of a node are consecutive ids (level-by-level numbering)
+        for v in np.flatnonzero(fan)[:50]:
+            ch = t.child[t.child_ptr[v]:t.child_ptr[v + 1]]
+            assert np.array_equal(ch, np.arange(ch[0], ch[0] + ch.size))
