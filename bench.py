@@ -227,7 +227,8 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
         dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
         row = {}
         for name, mode, tune in (("basic_dp", "grid", wc.make_tune(driver=2)), ("flat", "flat", None),
-                                 ("wave", "wave", None), ("block", "block", None), ("grid", "grid", None)):
+                                 ("wave", "wave", None), ("block", "block", None), ("grid", "grid", None),
+                                 ("grid_1to1", "grid", wc.make_tune(driver=3))):
             _, st = ctx.sssp(dg, dw, 0, mode=mode, tune=tune, out=dist, stats=True)
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -237,7 +238,7 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
             b.record(stream)
             torch.cuda.synchronize()
             row[name] = {"ms": round(a.elapsed_time(b) / reps, 3), "child_dispatches": st["dispatches"]}
-        for name in ("flat", "wave", "block", "grid"):
+        for name in ("flat", "wave", "block", "grid", "grid_1to1"):
             row[name]["speedup_vs_basic_dp"] = round(row["basic_dp"]["ms"] / row[name]["ms"], 1)
         out[f"rmat{scale}"] = row
         print(f"[bench] ablation scale {scale}: {row}", file=sys.stderr, flush=True)

@@ -105,7 +105,11 @@ typedef struct {
                                2: SSSP grid mode only, for comparison: basic dynamic
                                   parallelism emulated, one host-launched child per
                                   buffered vertex, no consolidation (stats->dispatches
-                                  counts the child launches) */
+                                  counts the child launches);
+                               3: SSSP grid mode only, for comparison: the "1-1 mapping"
+                                  configuration of Sec. V.B, the consolidated child
+                                  launched with one wave per buffered chunk (the host
+                                  reads the buffer size after every parent) */
     int32_t allow_fallback; /* on buffer overflow: >= 0 (default) the item that does not fit
                                is processed inline and stats->overflowed is set;
                                < 0 the call returns WC_EOVERFLOW after its work ends */

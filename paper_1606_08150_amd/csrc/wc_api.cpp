@@ -157,10 +157,11 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
     if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
         return fail(WC_EINVAL, "block_threads must be one of 64, 128, 256, 512, 1024");
     if (t.items_per_lane > 64) return fail(WC_EINVAL, "items_per_lane must be at most 64");
-    if (t.driver < 0 || t.driver > 2)
-        return fail(WC_EINVAL, "driver must be 0 (relaunch), 1 (persistent) or 2 (basic, SSSP grid mode)");
-    if (t.driver == 2 && strcmp(problem, "sssp"))
-        return fail(WC_EINVAL, "the basic driver (driver = 2) exists for SSSP only");
+    if (t.driver < 0 || t.driver > 3)
+        return fail(WC_EINVAL,
+                    "driver must be 0 (relaunch), 1 (persistent), 2 (basic) or 3 (1-1 mapping; 2 and 3 SSSP grid only)");
+    if (t.driver >= 2 && strcmp(problem, "sssp"))
+        return fail(WC_EINVAL, "drivers 2 and 3 exist for SSSP only");
     out->threshold = t.threshold;
     out->block = t.block_threads;
     out->grid = t.grid_blocks;

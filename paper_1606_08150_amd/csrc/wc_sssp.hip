@@ -562,8 +562,8 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     if (st != WC_OK) return st;
     if (cfg.driver == 1)
         return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
-    if (cfg.driver == 2 && mode != WC_GRID)
-        return fail(WC_EINVAL, "the basic driver (driver = 2) emulates per-item child launches of grid mode only");
+    if ((cfg.driver == 2 || cfg.driver == 3) && mode != WC_GRID)
+        return fail(WC_EINVAL, "drivers 2 and 3 are comparison variants of grid mode only");
     if (cfg.block != block) {
         ks = pick(mode, cfg.block);
         resident = resident_blocks(ctx, ks.round, cfg.block);
@@ -652,6 +652,33 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
         st = end_call(ctx, stream, stats, rounds, cfg.fail_on_overflow);
         if (stats) stats->dispatches = launches;
         return st;
+    }
+    if (cfg.driver == 3) {
+        // 1-1 mapping (Sec. V.B, for comparison): the consolidated child is
+        // launched with one wave per buffered chunk instead of the resident
+        // grid, which needs the buffer's size on the host after every parent.
+        const int waves_per_block = cfg.block / kWave;
+        int rounds = 0;
+        for (int r = 0;; ++r) {
+            void *args[] = {&a, &r};
+            st = launch(ctx, "sssp_round_grid", ks.round, dim3(grid), dim3(cfg.block), args, stream);
+            if (st != WC_OK) return st;
+            int tail = 0, act = 0;
+            WC_HIP(hipMemcpyAsync(&tail, a.chunk_tail + (r % 3) * kPad, sizeof(int), hipMemcpyDeviceToHost, stream));
+            WC_HIP(hipStreamSynchronize(stream));
+            chain_break(ctx);
+            const long long count = std::min<long long>(tail, a.chunk_cap);
+            const int blocks = (int)std::max<long long>(1, (count + waves_per_block - 1) / waves_per_block);
+            st = launch(ctx, "sssp_drain", ks.drain, dim3(blocks), dim3(cfg.block), args, stream);
+            if (st != WC_OK) return st;
+            WC_HIP(hipMemcpyAsync(&act, a.active + ((r + 1) % 3) * kPad, sizeof(int), hipMemcpyDeviceToHost, stream));
+            WC_HIP(hipStreamSynchronize(stream));
+            chain_break(ctx);
+            ++rounds;
+            if (!act) break;
+            if (rounds > n + 1) return fail(WC_ETIMEOUT, "wc_sssp: more rounds than vertices");
+        }
+        return end_call(ctx, stream, stats, rounds, cfg.fail_on_overflow);
     }
     // Relaunch driver: keep `window` rounds in flight; each round kernel
     // publishes whether its frontier is non-empty to pinned host memory, and the

@@ -124,7 +124,19 @@ def test_basic_driver_emulates_per_vertex_children(ctx, c1):
         with pytest.raises(wc.WcError):
             ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(driver=2))
     with pytest.raises(wc.WcError):
-        ctx.sssp(dg, dw, 0, mode="grid", tune=wc.make_tune(driver=3))
+        ctx.sssp(dg, dw, 0, mode="grid", tune=wc.make_tune(driver=4))
+
+
+def test_one_to_one_mapped_child(ctx, c1):
+    """driver = 3: the drain launched with one wave per buffered chunk."""
+    g, w, ref = c1
+    dg, dw = upload(g, w)
+    for tune in (dict(driver=3), dict(driver=3, block_threads=64, items_per_lane=1)):
+        d = ctx.sssp(dg, dw, 0, mode="grid", tune=wc.make_tune(**tune))
+        torch.cuda.synchronize()
+        assert np.array_equal(dev_to_u32(d), ref), tune
+    with pytest.raises(wc.WcError):
+        ctx.sssp(dg, dw, 0, mode="block", tune=wc.make_tune(driver=3))
 
 
 def test_invalid_arguments(ctx, c1):
