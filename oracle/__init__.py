@@ -44,6 +44,8 @@ def _load():
         "orc_spmv_check": (c.c_int64, [c.c_int32, f64p, f64p, f32p, c.c_double, pi64]),
         "orc_pagerank_f64": (c.c_int, [c.c_int32, i32p, i32p, i32p, c.c_int32, c.c_double, f64p]),
         "orc_bfs": (c.c_int, [c.c_int32, i32p, i32p, c.c_int32, u32p]),
+        "orc_color_jp": (c.c_int32, [c.c_int32, i32p, i32p, u32p, i32p]),
+        "orc_color_certify": (c.c_int64, [c.c_int32, i32p, i32p, u32p, i32p, pi64]),
         "orc_tree_validate": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
         "orc_tree_descendants": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
         "orc_tree_height": (c.c_int, [c.c_int32, i32p, i32p, i32p]),
@@ -116,6 +118,25 @@ def bfs(row_ptr, col, src: int):
     if _load().orc_bfs(n, _i32(row_ptr), _nonempty(col, np.int32), int(src), lv) != 0:
         raise MemoryError("orc_bfs")
     return lv[:n]
+
+
+def color_jp(row_ptr, col, prio):
+    """(color int32[n], rounds): Jones-Plassmann rounds (see orc_color_jp)."""
+    n = len(row_ptr) - 1
+    c = np.empty(max(n, 1), dtype=np.int32)
+    k = _load().orc_color_jp(n, _i32(row_ptr), _nonempty(col, np.int32), _nonempty(prio, np.uint32), c)
+    if k < 0:
+        raise MemoryError("orc_color_jp")
+    return c[:n], int(k)
+
+
+def color_certify(row_ptr, col, prio, color):
+    """(violations, first_violating_vertex) of the recurrence that fixes the coloring."""
+    n = len(row_ptr) - 1
+    first = ctypes.c_int64(-1)
+    bad = _load().orc_color_certify(n, _i32(row_ptr), _nonempty(col, np.int32), _nonempty(prio, np.uint32),
+                                    _nonempty(color, np.int32), ctypes.byref(first))
+    return int(bad), int(first.value)
 
 
 def spmv_f64(row_ptr, col, val, x):

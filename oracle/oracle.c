@@ -15,6 +15,8 @@
  *           an O(m) optimality certificate usable at any size.
  *   BFS   - breadth-first levels from one source (the recursive BFS of
  *           Sec. V reaches the same levels).  A FIFO queue.
+ *   GC    - Jones-Plassmann coloring rounds over a symmetric graph with
+ *           given priorities, and the recurrence that certifies it.
  *   SpMV  - y = A x in binary64 plus the per-row magnitude sum
  *           b[r] = sum |a_rj x_j| used by the tolerance test (Sec. V lists
  *           SpMV among the irregular-loop benchmarks).
@@ -232,6 +234,70 @@ int orc_bfs(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t src, 
     }
     free(queue);
     return 0;
+}
+
+/* ------------------------------------------------------- graph coloring ---- */
+
+/* Graph coloring, the GC benchmark of Sec. V (named, not defined there): the
+ * Jones-Plassmann rounds in which every uncolored vertex that outranks all of
+ * its still-uncolored neighbours takes the round's number as its color.  A
+ * vertex outranks another if its priority is larger, or equal with the larger
+ * id.  g must be symmetric; self-loops are ignored.  color[v] = round of v.
+ * Returns the number of rounds (colors), or -1 if memory runs out. */
+static int outranks(const uint32_t *prio, int32_t a, int32_t b)
+{
+    return prio[a] > prio[b] || (prio[a] == prio[b] && a > b);
+}
+
+int32_t orc_color_jp(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *prio, int32_t *color)
+{
+    int32_t *ready = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!ready) return -1;
+    for (int32_t v = 0; v < n; ++v) color[v] = -1;
+    int32_t left = n, round = 0;
+    while (left > 0) {
+        int32_t k = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (color[v] >= 0) continue;
+            int ok = 1;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1] && ok; ++e) {
+                int32_t u = col[e];
+                if (u != v && color[u] < 0 && outranks(prio, u, v)) ok = 0;
+            }
+            if (ok) ready[k++] = v;
+        }
+        for (int32_t i = 0; i < k; ++i) color[ready[i]] = round;
+        left -= k;
+        ++round;
+    }
+    free(ready);
+    return round;
+}
+
+/* The recurrence that fixes the coloring above: color[v] = 0 if no neighbour
+ * outranks v, else 1 + the largest color among the neighbours that outrank v.
+ * Returns the number of vertices violating it (or a neighbour sharing the
+ * color); *first gets the first one (or -1). */
+int64_t orc_color_certify(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *prio,
+                          const int32_t *color, int64_t *first)
+{
+    int64_t bad = 0;
+    *first = -1;
+    for (int32_t v = 0; v < n; ++v) {
+        int32_t want = 0;
+        int clash = 0;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t u = col[e];
+            if (u == v) continue;
+            if (outranks(prio, u, v) && color[u] + 1 > want) want = color[u] + 1;
+            if (color[u] == color[v]) clash = 1;
+        }
+        if (clash || color[v] != want) {
+            if (bad == 0) *first = v;
+            ++bad;
+        }
+    }
+    return bad;
 }
 
 /* ---------------------------------------------------------------- SpMV ---- */

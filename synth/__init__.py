@@ -284,6 +284,28 @@ def transpose(g: CSR) -> CSR:
     return CSR(n, np.cumsum(row_ptr).astype(np.int32), src[order].astype(np.int32))
 
 
+def symmetrize(g: CSR) -> CSR:
+    """The undirected graph: every edge in both directions, self-loops and
+    repeated edges dropped, rows sorted.  A data-layout step; no arithmetic of
+    the method."""
+    n = g.n
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr).astype(np.int64))
+    dst = g.col.astype(np.int64)
+    keep = src != dst
+    a = np.concatenate([src[keep], dst[keep]])
+    b = np.concatenate([dst[keep], src[keep]])
+    key = np.unique(a * n + b)
+    a, b = key // n, key % n
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, a + 1, 1)
+    return CSR(n, np.cumsum(row_ptr).astype(np.int32), b.astype(np.int32))
+
+
+def priorities(n: int, seed: int = SEED_GRAPH, stream: int = 600) -> np.ndarray:
+    """Seeded uint32 vertex priorities for the coloring rounds."""
+    return (rand_u64(seed, stream, n) >> np.uint64(32)).astype(np.uint32)
+
+
 def out_degree(g: CSR) -> np.ndarray:
     return np.diff(g.row_ptr).astype(np.int32)
 
