@@ -51,6 +51,7 @@ def parse():
     p.add_argument("--no-gather-ceiling", action="store_true", help="skip the bare-gather reference timing")
     p.add_argument("--no-cold", action="store_true", help="skip the cold-cache (L2 and MALL flushed) timings")
     p.add_argument("--no-pagerank", action="store_true", help="skip the PageRank section")
+    p.add_argument("--no-coloring", action="store_true", help="skip the graph coloring section")
     p.add_argument("--no-ablation", action="store_true", help="skip the basic dynamic parallelism comparison")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
@@ -210,6 +211,37 @@ def run_pagerank(ctx, torch, synth, wc, stream, g, iters=10, reps=3):
         print(f"[bench] pagerank {mode}: {res[mode]}", file=sys.stderr, flush=True)
     return {"workload": f"PageRank, damping 0.85, {iters} sweeps over the in-edges of the scale-22 R-MAT graph",
             "modes": res}
+
+
+def run_coloring(ctx, torch, synth, wc, stream, g, reps=3):
+    """Jones-Plassmann coloring (the GC benchmark) in every mode on a scale-16
+    symmetric R-MAT graph shaped like the paper's Kron_log16 input, and on the
+    symmetrized scale-22 graph (grid, wave and block: flat takes seconds there)."""
+    out = {}
+    for name, sg, modes in (("kron16", synth.symmetrize(synth.rmat_csr(16, 1 << 21)), ("flat", "wave", "block", "grid")),
+                            ("rmat22", synth.symmetrize(g), ("wave", "block", "grid"))):
+        dg = wc.DeviceCSR.from_host(sg.row_ptr, sg.col)
+        dp = torch.from_numpy(synth.priorities(sg.n).view(np.int32)).cuda()
+        col = torch.empty(sg.n, dtype=torch.int32, device="cuda")
+        row = {"vertices": sg.n, "edges": sg.m}
+        for mode in modes:
+            _, st = ctx.color(dg, dp, mode=mode, out=col, stats=True)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                ctx.color(dg, dp, mode=mode, out=col)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            row[mode] = {"ms": round(ms, 3), "colors": st["rounds"], "us_per_round": round(1e3 * ms / st["rounds"], 1),
+                         "gedges_s": round(2 * sg.m / (ms * 1e-3) / 1e9, 3)}
+        out[name] = row
+        print(f"[bench] coloring {name}: {row}", file=sys.stderr, flush=True)
+        del dg, dp, col, sg
+    return {"workload": "Jones-Plassmann coloring, seeded uint32 priorities, symmetric R-MAT graphs "
+                        "(scale 16 with 2^21 sampled edges; the scale-22 graph symmetrized)",
+            "note": "gedges_s counts each edge twice (count pass and release)", "results": out}
 
 
 def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
@@ -601,6 +633,11 @@ def main():
     if not args.no_pagerank:
         pagerank = run_pagerank(ctx, torch, synth, wc, stream, g)
 
+    # ---- graph coloring (Jones-Plassmann), every mode
+    coloring = None
+    if not args.no_coloring:
+        coloring = run_coloring(ctx, torch, synth, wc, stream, g)
+
     # ---- consolidated vs basic dynamic parallelism (per-vertex child launches)
     ablation = None
     if not args.no_ablation:
@@ -672,6 +709,7 @@ def main():
         "kernels": kernels,
         "modes": modes,
         "pagerank": pagerank,
+        "coloring": coloring,
         "basic_dp_ablation": ablation,
         "trees": trees,
         "batch": batch,

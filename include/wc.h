@@ -183,6 +183,25 @@ wc_status wc_pagerank(wc_ctx *ctx, const wc_csr *in_graph, const int32_t *out_de
                       float damping, float *rank, wc_mode mode, const wc_tune *tune, hipStream_t stream,
                       wc_stats *stats);
 
+/* Graph coloring (the GC benchmark of Sec. V, an irregular loop): Jones-Plassmann
+ * colors of a symmetric graph g (every edge u -> v matched by a v -> u, with the
+ * same multiplicity; self-loops are ignored).  Vertex u outranks v when
+ * prio[u] > prio[v], or the priorities are equal and u > v.  In round r = 0, 1, ...
+ * every uncolored vertex that outranks each of its uncolored neighbours takes
+ * color r; equivalently color[v] = 0 if no neighbour outranks v, else 1 + the
+ * largest color of an outranking neighbour.  Computed data-driven: a vertex
+ * colored in round r releases the neighbours it outranks, and one whose last
+ * outranking neighbour that was is colored r + 1; the release loop of a vertex
+ * with more than `threshold` neighbours is consolidated per `mode`.  color[n]
+ * (int32, device) is written entirely; prio[n] (uint32, device) is read only.
+ * The colors do not depend on mode, tune or schedule.  stats->rounds = number
+ * of colors.  Only the relaunch driver exists (tune->driver 0).  WC_EINVAL for
+ * negative sizes, NULL arrays, or a graph in which some vertex was never
+ * colored (not symmetric; such vertices keep -1); the colors of other
+ * asymmetric graphs are unspecified. */
+wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio, int32_t *color, wc_mode mode,
+                   const wc_tune *tune, hipStream_t stream, wc_stats *stats);
+
 /* Tree descendants (recursion of Fig. 1(c)): desc[v] = number of proper
  * descendants of v.  A node with children is a recursive call whose work is
  * consolidated per `mode`; a leaf gets 0; the post-work folds each child c
@@ -250,7 +269,7 @@ int64_t wc_per_buffer_size(int64_t total_thread, int64_t total_buff_var, int64_t
 /* KC_X of Sec. IV.E: (blocks, threads) downgraded to (ceil(blocks / x), threads). */
 void wc_kc_config(int64_t blocks, int64_t threads, int64_t x, int64_t *out_blocks, int64_t *out_threads);
 
-/* Fill `out` with the library's defaults for a problem ("sssp", "spmv", "tree")
+/* Fill `out` with the library's defaults for a problem ("sssp", "spmv", "tree", "color")
  * and mode, given the occupancy-derived resident workgroup count.  Returns
  * WC_EINVAL for an unknown problem or mode. */
 wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_blocks, wc_tune *out);

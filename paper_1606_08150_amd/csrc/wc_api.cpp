@@ -133,7 +133,11 @@ static int default_threshold(const char *problem, wc_mode mode)
     if (!strcmp(problem, "tree")) return 0;  // every node with children is a recursive call (Fig. 1(c))
     // grid level drains with lane groups sized to each item, so only very short
     // items stay inline; wave and block levels drain with whole groups
-    if (mode == WC_GRID) return 8;
+    if (mode == WC_GRID && strcmp(problem, "color")) return 8;
+    // coloring rounds are short and latency-bound: at grid level a vertex with
+    // more than two neighbours is buffered, so no lane walks a long chain in
+    // the parent (measured on a scale-16 and a scale-22 symmetric R-MAT graph)
+    if (mode == WC_GRID) return 2;
     return 32;
 }
 
@@ -316,7 +320,7 @@ void wc_kc_config(int64_t blocks, int64_t threads, int64_t x, int64_t *out_block
 wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_blocks, wc_tune *out)
 {
     if (!problem || !out) return fail(WC_EINVAL, "NULL argument");
-    if (strcmp(problem, "sssp") && strcmp(problem, "spmv") && strcmp(problem, "tree"))
+    if (strcmp(problem, "sssp") && strcmp(problem, "spmv") && strcmp(problem, "tree") && strcmp(problem, "color"))
         return fail(WC_EINVAL, std::string("unknown problem ") + problem);
     if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "mode must be flat, wave, block or grid");
     out->threshold = default_threshold(problem, mode);

@@ -21,7 +21,7 @@ MODES = {"flat": FLAT, "wave": WAVE, "block": BLOCK, "grid": GRID}
 STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: "WC_ETIMEOUT", -5: "WC_EHIP"}
 
 # C-ABI symbols declared in include/wc.h
-EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_pagerank", "wc_tree_descendants",
+EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_pagerank", "wc_color", "wc_tree_descendants",
            "wc_tree_height",
            "wc_sssp_batch",
            "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size",
@@ -86,6 +86,8 @@ def load_library():
     lib.wc_bfs.argtypes = [vp, c.POINTER(CCsr), c.c_int32, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_spmv.restype = c.c_int
     lib.wc_spmv.argtypes = [vp, c.POINTER(CCsr), vp, vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_color.restype = c.c_int
+    lib.wc_color.argtypes = [vp, c.POINTER(CCsr), vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_pagerank.restype = c.c_int
     lib.wc_pagerank.argtypes = [vp, c.POINTER(CCsr), vp, c.c_int32, c.c_float, vp, c.c_int, c.POINTER(Tune), vp,
                                 c.POINTER(Stats)]
@@ -320,6 +322,20 @@ class Context:
                                           ctypes.byref(tune) if tune else None, _stream_ptr(stream),
                                           ctypes.byref(st) if st else None))
         return (r, st.as_dict()) if stats else r
+
+    def color(self, g: DeviceCSR, prio: torch.Tensor, mode="grid", tune: Tune | None = None,
+              out: torch.Tensor | None = None, stream=None, stats: bool = False):
+        """Jones-Plassmann colors of a symmetric graph (int32); prio holds the
+        vertices' priorities (uint32 values in an int32 or int64 tensor, device)."""
+        if prio.dtype not in (torch.int32, torch.uint32) or prio.numel() != g.n:
+            raise ValueError("prio must hold n 32-bit priorities")
+        c = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+        st = Stats() if stats else None
+        cg = g.c()
+        _check(load_library().wc_color(self._ptr, ctypes.byref(cg), prio.data_ptr(), c.data_ptr(), _mode(mode),
+                                       ctypes.byref(tune) if tune else None, _stream_ptr(stream),
+                                       ctypes.byref(st) if st else None))
+        return (c, st.as_dict()) if stats else c
 
     def _tree(self, fn, t: DeviceTree, mode, tune, out, stream, stats):
         res = out if out is not None else torch.empty(t.n, dtype=torch.int32, device=t.parent.device)

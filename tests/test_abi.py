@@ -44,6 +44,9 @@ def test_default_tune_and_errors():
     assert wc.default_tune("tree", "block", 100)["threshold"] == 0
     t = wc.default_tune("tree", "grid", 100)
     assert t["block_threads"] == 512 and t["items_per_lane"] == 2
+    t = wc.default_tune("color", "grid", 100)
+    assert t["threshold"] == 2 and t["block_threads"] == 512 and t["items_per_lane"] == 4
+    assert wc.default_tune("color", "wave", 100)["threshold"] == 32
     try:
         wc.default_tune("nope", "grid", 1)
     except wc.WcError as e:
