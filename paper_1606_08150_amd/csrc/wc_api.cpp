@@ -134,10 +134,9 @@ static int default_threshold(const char *problem, wc_mode mode)
     // grid level drains with lane groups sized to each item, so only very short
     // items stay inline; wave and block levels drain with whole groups
     if (mode == WC_GRID && strcmp(problem, "color")) return 8;
-    // coloring rounds are short and latency-bound: at grid level a vertex with
-    // more than two neighbours is buffered, so no lane walks a long chain in
-    // the parent (measured on a scale-16 and a scale-22 symmetric R-MAT graph)
-    if (mode == WC_GRID) return 2;
+    // coloring at grid level buffers every readied vertex's range; the
+    // threshold applies to its count pass, where lanes walk up to 64 entries
+    if (mode == WC_GRID) return 64;
     return 32;
 }
 
@@ -325,14 +324,18 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "mode must be flat, wave, block or grid");
     out->threshold = default_threshold(problem, mode);
     // grid level: 512-thread workgroups measured fastest (scale-22 graph,
-    // 2^22-node tree); everything else 256
-    out->block_threads = mode == WC_GRID ? 512 : 256;
+    // 2^22-node tree) except for coloring; everything else 256
+    out->block_threads = mode == WC_GRID && strcmp(problem, "color") ? 512 : 256;
     // The drain grid of every mode is the resident maximum (KC_1 of Sec. IV.E):
     // wave- and block-level drains run inside the parent groups, which are
     // already resident, so no downgrade for concurrency is needed.
     out->grid_blocks = resident_blocks > 0 ? resident_blocks : 1;
     out->items_per_lane = 4;  // "const" of Sec. IV.E
     if (mode == WC_GRID && !strcmp(problem, "spmv")) out->items_per_lane = 8;
+    // coloring rounds are short and bound by their dependent chain of loads and
+    // atomics: 128-neighbour chunks in 256-thread groups measured fastest
+    // (symmetric R-MAT graphs of scale 16 and 22)
+    if (mode == WC_GRID && !strcmp(problem, "color")) out->items_per_lane = 2;
     // tree items are child ranges: most nodes have a few children, and shorter
     // chunks split the few wide nodes over more waves (measured on 2^22 nodes)
     if (mode == WC_GRID && !strcmp(problem, "tree")) out->items_per_lane = 2;

@@ -19,8 +19,14 @@
 //   block - thread-ordered LDS buffer; after the barrier the block walks the
 //           concatenated neighbour ranges.
 //   grid  - global buffer of (vertex, neighbour range) chunks drained by a
-//           moldable grid after the kernel boundary, one wave per chunk.
+//           moldable grid after the kernel boundary, one wave per chunk.  The
+//           thread that readies a vertex buffers its range right away, so the
+//           drain of round r is also the parent of round r + 1: one kernel
+//           per round.
 //   flat  - every vertex walks all of its neighbours itself.
+// Outside grid mode every vertex is buffered (walked) regardless of the
+// threshold in the count pass and the rounds alike; in grid mode `threshold`
+// applies to the count pass, and every readied vertex's range is buffered.
 #include <algorithm>
 #include <cstring>
 
@@ -45,8 +51,10 @@ struct ColorArgs {
     int *queue1;      // ... in odd rounds
     int *qtail;       // ring of 3 (stride kPad): size of the queue of round r
     int *chunk_tail;  // ring of 3 (stride kPad)
-    int4 *chunks;     // (v, begin, end, prio[v])
+    int4 *chunks;     // (v, begin, end, prio[v]); grid: the chunks of even rounds
+    int4 *chunks1;    // grid: the chunks of odd rounds
     long long chunk_cap;
+    int *colored;     // grid: vertices colored so far
     int n;
     int threshold;
     int chunk;
@@ -60,13 +68,72 @@ __device__ __forceinline__ bool above(uint32_t pu, int u, uint32_t pv, int v)
     return pu > pv || (pu == pv && u > v);
 }
 
+// Where readied vertices go: the next round's vertex queue, or (grid mode)
+// the next round's chunk buffer, with the queue taking vertices whose chunks
+// do not fit (buffer full).
+struct Next {
+    int *queue;
+    int *queue_tail;
+    int4 *chunks;
+    int *chunk_tail;
+};
+
+// Readied vertex w (priority pw) takes color_next and is queued.  Every active
+// lane of the wave calls this together.
+template <bool CHUNKED>
+__device__ __forceinline__ void push_ready(const ColorArgs &a, bool ready, int w, uint32_t pw, int color_next,
+                                           const Next &nx, int &readied)
+{
+    if (ready) {
+        a.color[w] = color_next;
+        ++readied;
+    }
+    if constexpr (!CHUNKED) {
+        const int s = wave_reserve(ready, nx.queue_tail);
+        if (ready) nx.queue[s] = w;
+    } else {
+        int beg = 0, end = 0;
+        if (ready) {
+            beg = a.row_ptr[w];
+            end = a.row_ptr[w + 1];
+        }
+        const int nch = (end - beg + a.chunk - 1) / a.chunk;
+        const bool one = ready && nch == 1;
+        const int s = wave_reserve(one, nx.chunk_tail);
+        bool defer = false;
+        if (one) {
+            if (s < a.chunk_cap) nx.chunks[s] = make_int4(w, beg, end, (int)pw);
+            else defer = true;
+        } else if (ready && nch > 1) {
+            const long long base = atomic_add_dev(nx.chunk_tail, nch);
+            if (base + nch <= a.chunk_cap) {
+                for (int c = 0; c < nch; ++c) {
+                    const int cb = beg + c * a.chunk;
+                    nx.chunks[base + c] = make_int4(w, cb, min(end, cb + a.chunk), (int)pw);
+                }
+            } else {
+                // reserved slots below the capacity get empty ranges (the drain
+                // reads no stale chunk there)
+                for (long long c = base; c < base + nch && c < a.chunk_cap; ++c) nx.chunks[c] = make_int4(w, 0, 0, 0);
+                defer = true;
+            }
+        }
+        if (defer) {
+            // buffer full: the next round walks w with one lane (fallback)
+            a.stats->overflowed = 1;
+            nx.queue[atomic_add_dev(nx.queue_tail, 1)] = w;
+        }
+    }
+}
+
 // v (priority pv, colored in round r) releases its neighbours e = first +
 // k * stride < end that it outranks; a neighbour whose count reaches zero is
-// appended to the next round's queue with color r + 1.  Every active lane of
-// the wave calls this together (the appends are wave-aggregated); v, first,
-// stride and end may differ per lane.  Returns the number of releases.
+// readied with color r + 1.  Every active lane of the wave calls this together
+// (the appends are wave-aggregated); v, first, stride and end may differ per
+// lane.  Returns the number of releases.
+template <bool CHUNKED>
 __device__ __forceinline__ int release_range(const ColorArgs &a, int v, uint32_t pv, int first, int stride, int end,
-                                             int *next, int *next_tail, int color_next)
+                                             int color_next, const Next &nx, int &readied)
 {
     int rel = 0;
     for (int e0 = first; e0 < end; e0 += kUnroll * stride) {
@@ -87,29 +154,19 @@ __device__ __forceinline__ int release_range(const ColorArgs &a, int v, uint32_t
             rel += out ? 1 : 0;
         }
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-            const bool ready = old[k] == 1;
-            const int s = wave_reserve(ready, next_tail);
-            if (ready) {
-                next[s] = w[k];
-                a.color[w[k]] = color_next;
-            }
-        }
+        for (int k = 0; k < kUnroll; ++k) push_ready<CHUNKED>(a, old[k] == 1, w[k], pw[k], color_next, nx, readied);
     }
     return rel;
 }
 
 // One neighbour w of v (block-level drain, one edge per thread).
-__device__ __forceinline__ int release_one(const ColorArgs &a, int v, uint32_t pv, int w, int *next, int *next_tail,
-                                           int color_next)
+__device__ __forceinline__ int release_one(const ColorArgs &a, int v, uint32_t pv, int w, int color_next,
+                                           const Next &nx, int &readied)
 {
-    const bool out = w != v && above(pv, v, a.prio[w], w);
+    const uint32_t pw = a.prio[w];
+    const bool out = w != v && above(pv, v, pw, w);
     const bool ready = out && atomic_add_dev(&a.wait[w], -1) == 1;
-    const int s = wave_reserve(ready, next_tail);
-    if (ready) {
-        next[s] = w;
-        a.color[w] = color_next;
-    }
+    push_ready<false>(a, ready, w, pw, color_next, nx, readied);
     return out ? 1 : 0;
 }
 
@@ -123,7 +180,8 @@ struct ColorLds {
     int base;
 };
 
-// Round r: thread i takes the i-th vertex of the round's queue (colored r).
+// Round r outside grid mode: thread i takes the i-th vertex of the round's
+// queue (colored r).
 template <int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
 {
@@ -131,14 +189,13 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
     const int size = a.qtail[(r % 3) * kPad];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.qtail[((r + 2) % 3) * kPad] = 0;
-        a.chunk_tail[((r + 1) % 3) * kPad] = 0;
         store_system(&a.host_ring[r % kHostRing], size);
     }
     if (size == 0) return;
     const int *q = (r & 1) ? a.queue1 : a.queue0;
-    int *next = (r & 1) ? a.queue0 : a.queue1;
-    int *next_tail = &a.qtail[((r + 1) % 3) * kPad];
+    const Next nx{(r & 1) ? a.queue0 : a.queue1, &a.qtail[((r + 1) % 3) * kPad], nullptr, nullptr};
     const int lane = lane_id();
+    int readied = 0;
     StatAcc acc;
     for (int base = blockIdx.x * BLOCK; base < size; base += gridDim.x * BLOCK) {
         const int i = base + threadIdx.x;
@@ -159,14 +216,15 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
             acc.items += heavy ? 1 : 0;
             if (MODE == WC_WAVE && __ballot(heavy) && lane == 0) acc.dispatches += 1;
         }
-        if (member && !heavy) acc.updates += release_range(a, v, pv, beg, 1, end, next, next_tail, r + 1);
+        if (member && !heavy) acc.updates += release_range<false>(a, v, pv, beg, 1, end, r + 1, nx, readied);
         if constexpr (MODE == WC_WAVE) {
             uint64_t mask = __ballot(heavy);
             while (mask) {
                 const int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                acc.updates_buffered += release_range(a, readlane(v, b), readlane_u(pv, b), readlane(beg, b) + lane,
-                                                      kWave, readlane(end, b), next, next_tail, r + 1);
+                acc.updates_buffered += release_range<false>(a, readlane(v, b), readlane_u(pv, b),
+                                                             readlane(beg, b) + lane, kWave, readlane(end, b), r + 1,
+                                                             nx, readied);
             }
         } else if constexpr (MODE == WC_BLOCK) {
             int k, off, nb, total;
@@ -186,61 +244,59 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
             for (int j = threadIdx.x; j < total; j += BLOCK) {
                 while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
                 const int w = a.col[sb.beg[it] + (j - sb.pre[it])];
-                acc.updates_buffered += release_one(a, sb.v[it], sb.p[it], w, next, next_tail, r + 1);
+                acc.updates_buffered += release_one(a, sb.v[it], sb.p[it], w, r + 1, nx, readied);
             }
             __syncthreads();  // the LDS buffer is reused by the next window
-        } else if constexpr (MODE == WC_GRID) {
-            if (__syncthreads_or(heavy ? 1 : 0)) {
-                const int nch = heavy ? (deg + a.chunk - 1) / a.chunk : 0;
-                int excl, unused, tot, unused2;
-                block_scan2<BLOCK>(nch, 0, sb.scan_tmp, excl, unused, tot, unused2);
-                if (threadIdx.x == 0) sb.base = tot ? atomic_add_dev(&a.chunk_tail[(r % 3) * kPad], tot) : 0;
-                __syncthreads();
-                const long long slot = (long long)sb.base + excl;
-                const bool fits = slot + nch <= a.chunk_cap;
-                if (heavy) {
-                    if (fits) {
-                        for (int c = 0; c < nch; ++c) {
-                            const int cb = beg + c * a.chunk;
-                            a.chunks[slot + c] = make_int4(v, cb, min(end, cb + a.chunk), (int)pv);
-                        }
-                    } else {
-                        // buffer full: the reserved slots below the capacity get
-                        // empty ranges (the drain reads no stale chunk there) and
-                        // this vertex is walked inline (fallback)
-                        a.stats->overflowed = 1;
-                        for (long long c = slot; c < slot + nch && c < a.chunk_cap; ++c)
-                            a.chunks[c] = make_int4(v, 0, 0, 0);
-                    }
-                }
-                if (heavy && !fits) acc.updates += release_range(a, v, pv, beg, 1, end, next, next_tail, r + 1);
-                __syncthreads();  // sb.base is rewritten by the next window
-            }
         }
     }
     if (a.want_stats) stat_flush(a.stats, acc);
 }
 
-// Consolidated child of grid mode: one wave per chunk.
+// Round r in grid mode: one wave per buffered chunk (a readied vertex's
+// neighbour range, buffered while round r - 1 ran), then one lane per vertex
+// the buffer could not take.  Vertices readied here buffer their ranges for
+// round r + 1.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void color_drain(ColorArgs a, int r)
+__global__ __launch_bounds__(BLOCK) void color_round_grid(ColorArgs a, int r)
 {
-    if (a.qtail[(r % 3) * kPad] == 0) return;
-    const int tail = a.chunk_tail[(r % 3) * kPad];
-    const int total = (long long)tail < a.chunk_cap ? tail : (int)a.chunk_cap;
-    int *next = (r & 1) ? a.queue0 : a.queue1;
-    int *next_tail = &a.qtail[((r + 1) % 3) * kPad];
+    const int nchunks = a.chunk_tail[(r % 3) * kPad];
+    const int ndefer = a.qtail[(r % 3) * kPad];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.chunk_tail[((r + 2) % 3) * kPad] = 0;
+        a.qtail[((r + 2) % 3) * kPad] = 0;
+        store_system(&a.host_ring[r % kHostRing], (nchunks != 0 || ndefer != 0) ? 1 : 0);
+    }
+    if (nchunks == 0 && ndefer == 0) return;
+    const int total = (long long)nchunks < a.chunk_cap ? nchunks : (int)a.chunk_cap;
+    const int4 *cur = (r & 1) ? a.chunks1 : a.chunks;
+    const Next nx{(r & 1) ? a.queue0 : a.queue1, &a.qtail[((r + 1) % 3) * kPad], (r & 1) ? a.chunks : a.chunks1,
+                  &a.chunk_tail[((r + 1) % 3) * kPad]};
     const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
     const int nw = gridDim.x * (BLOCK / kWave);
+    int readied = 0;
     StatAcc acc;
     if (a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0) acc.dispatches = 1;
     for (int c = gw; c < total; c += nw) {
-        const int4 d = a.chunks[c];
-        acc.updates_buffered += release_range(
-            a, __builtin_amdgcn_readfirstlane(d.x), (uint32_t)__builtin_amdgcn_readfirstlane(d.w),
-            __builtin_amdgcn_readfirstlane(d.y) + lane_id(), kWave, __builtin_amdgcn_readfirstlane(d.z), next,
-            next_tail, r + 1);
+        const int4 d = cur[c];
+        const int beg = __builtin_amdgcn_readfirstlane(d.y), end = __builtin_amdgcn_readfirstlane(d.z);
+        if (a.want_stats && lane_id() == 0) {
+            acc.items += 1;
+            acc.buffered += end - beg;
+            acc.edges += end - beg;
+        }
+        const int v = __builtin_amdgcn_readfirstlane(d.x);
+        const uint32_t pv = (uint32_t)__builtin_amdgcn_readfirstlane(d.w);
+        acc.updates_buffered += release_range<true>(a, v, pv, beg + lane_id(), kWave, end, r + 1, nx, readied);
     }
+    const int *dq = (r & 1) ? a.queue1 : a.queue0;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < ndefer; i += gridDim.x * BLOCK) {
+        const int v = dq[i];
+        const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+        if (a.want_stats) acc.edges += end - beg;
+        acc.updates += release_range<true>(a, v, a.prio[v], beg, 1, end, r + 1, nx, readied);
+    }
+    readied = wave_sum_i(readied);
+    if (lane_id() == 0 && readied) (void)atomic_add_dev(a.colored, readied);
     if (a.want_stats) stat_flush(a.stats, acc);
 }
 
@@ -251,6 +307,13 @@ __global__ void color_reset(ColorArgs a)
         a.qtail[threadIdx.x * kPad] = 0;
         a.chunk_tail[threadIdx.x * kPad] = 0;
     }
+    if (threadIdx.x == 0) *a.colored = 0;
+}
+
+// Grid mode: hands the number of colored vertices to the host.
+__global__ void color_publish(ColorArgs a)
+{
+    if (threadIdx.x == 0) store_system(&a.host_ring[kHostSlotGraph], *a.colored);
 }
 
 // Neighbours e = first + k * stride < end of v (priority pv) that outrank v.
@@ -380,9 +443,11 @@ __global__ __launch_bounds__(BLOCK) void color_count_drain(ColorArgs a)
     }
 }
 
-// Vertices that no neighbour outranks take color 0 and form the queue of
-// round 0; the others start uncolored.  One queue reservation per block step.
+// Vertices that no neighbour outranks take color 0 and form round 0 (grid:
+// their neighbour ranges are buffered as chunks); the others start
+// uncolored.  One reservation per block step.
 constexpr int kSeedBlock = 256;
+template <bool CHUNKED>
 __global__ __launch_bounds__(kSeedBlock) void color_seed(ColorArgs a)
 {
     __shared__ int scan_tmp[2 * (kSeedBlock / kWave)];
@@ -392,24 +457,53 @@ __global__ __launch_bounds__(kSeedBlock) void color_seed(ColorArgs a)
         const bool member = v < a.n;
         const bool first = member && a.wait[v] == 0;
         if (member) a.color[v] = first ? 0 : -1;
-        int k, unused, tot, unused2;
-        block_scan2<kSeedBlock>(first ? 1 : 0, 0, scan_tmp, k, unused, tot, unused2);
-        if (threadIdx.x == 0 && tot) s_base = atomic_add_dev(&a.qtail[0], tot);
-        __syncthreads();
-        if (first) a.queue0[s_base + k] = v;
+        if constexpr (!CHUNKED) {
+            int k, unused, tot, unused2;
+            block_scan2<kSeedBlock>(first ? 1 : 0, 0, scan_tmp, k, unused, tot, unused2);
+            if (threadIdx.x == 0 && tot) s_base = atomic_add_dev(&a.qtail[0], tot);
+            __syncthreads();
+            if (first) a.queue0[s_base + k] = v;
+        } else {
+            int beg = 0, end = 0;
+            if (first) {
+                beg = a.row_ptr[v];
+                end = a.row_ptr[v + 1];
+            }
+            const int nch = (end - beg + a.chunk - 1) / a.chunk;
+            int k, unused, tot, nfirst;
+            block_scan2<kSeedBlock>(nch, first ? 1 : 0, scan_tmp, k, unused, tot, nfirst);
+            if (threadIdx.x == 0) {
+                if (tot) s_base = atomic_add_dev(&a.chunk_tail[0], tot);
+                if (nfirst) (void)atomic_add_dev(a.colored, nfirst);
+            }
+            __syncthreads();
+            if (nch) {
+                const long long slot = (long long)s_base + k;
+                if (slot + nch <= a.chunk_cap) {
+                    for (int c = 0; c < nch; ++c) {
+                        const int cb = beg + c * a.chunk;
+                        a.chunks[slot + c] = make_int4(v, cb, min(end, cb + a.chunk), (int)a.prio[v]);
+                    }
+                } else {
+                    a.stats->overflowed = 1;
+                    for (long long c = slot; c < slot + nch && c < a.chunk_cap; ++c)
+                        a.chunks[c] = make_int4(v, 0, 0, 0);
+                    a.queue0[atomic_add_dev(&a.qtail[0], 1)] = v;
+                }
+            }
+        }
         __syncthreads();  // s_base is rewritten by the next step
     }
 }
 
 struct ColorKernels {
-    const void *round, *drain, *count, *count_drain;
+    const void *round, *count, *count_drain;
 };
 
 template <int BLOCK>
 ColorKernels pick_block(wc_mode mode)
 {
-    ColorKernels k{nullptr, reinterpret_cast<const void *>(&color_drain<BLOCK>), nullptr,
-                   reinterpret_cast<const void *>(&color_count_drain<BLOCK>)};
+    ColorKernels k{nullptr, nullptr, reinterpret_cast<const void *>(&color_count_drain<BLOCK>)};
     switch (mode) {
     case WC_FLAT:
         k.round = reinterpret_cast<const void *>(&color_round<WC_FLAT, BLOCK>);
@@ -424,7 +518,7 @@ ColorKernels pick_block(wc_mode mode)
         k.count = reinterpret_cast<const void *>(&color_count<WC_BLOCK, BLOCK>);
         break;
     default:
-        k.round = reinterpret_cast<const void *>(&color_round<WC_GRID, BLOCK>);
+        k.round = reinterpret_cast<const void *>(&color_round_grid<BLOCK>);
         k.count = reinterpret_cast<const void *>(&color_count<WC_GRID, BLOCK>);
         break;
     }
@@ -474,10 +568,11 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
     const int chunk = kWave * cfg.items_per_lane;
     const bool grid_mode = mode == WC_GRID;
     // every vertex has ceil(deg / chunk) <= deg / chunk + 1 chunks in the one
-    // round that colors it, so n + m / chunk + 1 entries never overflow
+    // round that colors it (and in the count pass), so n + m / chunk + 1
+    // entries per buffer never overflow
     const long long cap_full = n + m / chunk + 1;
     const long long cap = grid_mode ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    const size_t need = 3 * padded(n * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
+    const size_t need = 3 * padded(n * 4) + 3 * padded(3 * kPad * 4) + 2 * padded(cap * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     ColorArgs a;
@@ -492,7 +587,9 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
     a.qtail = pool_take<int>(ctx, 3 * kPad);
     a.chunk_tail = pool_take<int>(ctx, 3 * kPad);
     a.chunks = pool_take<int4>(ctx, cap);
+    a.chunks1 = grid_mode ? pool_take<int4>(ctx, cap) : nullptr;
     a.chunk_cap = cap;
+    a.colored = pool_take<int>(ctx, 3 * kPad);
     a.n = (int)n;
     a.threshold = cfg.threshold;
     a.chunk = chunk;
@@ -511,13 +608,14 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
         if (st == WC_OK && grid_mode)
             st = launch(ctx, "color_count_drain", ks.count_drain, dim3(dgrid), dim3(cfg.block), args, stream);
         const int sg = (int)std::min<long long>((n + kSeedBlock - 1) / kSeedBlock, 4096);
-        if (st == WC_OK)
-            st = launch(ctx, "color_seed", reinterpret_cast<const void *>(&color_seed), dim3(sg), dim3(kSeedBlock),
-                        args, stream);
+        const void *seed = grid_mode ? reinterpret_cast<const void *>(&color_seed<true>)
+                                     : reinterpret_cast<const void *>(&color_seed<false>);
+        if (st == WC_OK) st = launch(ctx, "color_seed", seed, dim3(sg), dim3(kSeedBlock), args, stream);
         if (st != WC_OK) return st;
     }
     static const char *names[] = {"color_round_flat", "color_round_wave", "color_round_block", "color_round_grid"};
-    // relaunch driver: rounds kept in flight (each publishes its queue size);
+    // relaunch driver: rounds kept in flight (each publishes whether it has
+    // work: its queue size, or in grid mode whether chunks or vertices wait);
     // the first empty round ends the loop
     const int window = 4;
     int rounds = 0, launched = 0;
@@ -526,9 +624,7 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
         while (launched < rounds + window) {
             clear_round_slot(ctx, launched);
             void *args[] = {&a, &launched};
-            st = launch(ctx, names[mode], ks.round, dim3(grid), dim3(cfg.block), args, stream);
-            if (st == WC_OK && grid_mode)
-                st = launch(ctx, "color_drain", ks.drain, dim3(dgrid), dim3(cfg.block), args, stream);
+            st = launch(ctx, names[mode], ks.round, dim3(grid_mode ? dgrid : grid), dim3(cfg.block), args, stream);
             if (st != WC_OK) return st;
             ++launched;
         }
@@ -538,7 +634,22 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
         if (c == 0) break;
         colored += c;
         ++rounds;
-        if (colored > n) return fail(WC_EINVAL, "wc_color: more queued vertices than vertices");
+        if (!grid_mode && colored > n) return fail(WC_EINVAL, "wc_color: more queued vertices than vertices");
+        if (rounds > n + 1) return fail(WC_ETIMEOUT, "wc_color: more rounds than vertices");
+    }
+    if (grid_mode) {
+        // the last round with work colored the vertices of the largest color;
+        // a graph without edges has one color and no round with work
+        rounds = std::max(rounds, 1);
+        clear_host_slot(ctx, kHostSlotGraph);
+        void *args[] = {&a};
+        st = launch(ctx, "color_publish", reinterpret_cast<const void *>(&color_publish), dim3(1), dim3(64), args,
+                    stream);
+        if (st != WC_OK) return st;
+        int c = 0;
+        st = wait_host_slot(ctx, kHostSlotGraph, &c);
+        if (st != WC_OK) return st;
+        colored = c;
     }
     st = end_call(ctx, stream, stats, rounds, cfg.fail_on_overflow);
     if (st != WC_OK) return st;

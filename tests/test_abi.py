@@ -45,7 +45,7 @@ def test_default_tune_and_errors():
     t = wc.default_tune("tree", "grid", 100)
     assert t["block_threads"] == 512 and t["items_per_lane"] == 2
     t = wc.default_tune("color", "grid", 100)
-    assert t["threshold"] == 2 and t["block_threads"] == 512 and t["items_per_lane"] == 4
+    assert t["threshold"] == 64 and t["block_threads"] == 256 and t["items_per_lane"] == 2
     assert wc.default_tune("color", "wave", 100)["threshold"] == 32
     try:
         wc.default_tune("nope", "grid", 1)
