@@ -28,6 +28,7 @@
 // threshold in the count pass and the rounds alike; in grid mode `threshold`
 // applies to the count pass, and every readied vertex's range is buffered.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 
 #include "wc_block.h"
@@ -40,6 +41,7 @@ namespace {
 
 constexpr int kPad = 32;        // ring entries on separate 128-byte lines
 constexpr int kUnroll = 4;      // neighbours in flight per lane
+constexpr int kNoRelease = INT_MIN;  // rcol flag: nothing to release along this edge
 
 struct ColorArgs {
     const int *row_ptr;
@@ -47,11 +49,12 @@ struct ColorArgs {
     const uint32_t *prio;
     int *color;       // -1 while uncolored
     int *wait;        // outranking neighbours not yet colored
+    int *rcol;        // col with bit 31 set where the row's vertex does not outrank the neighbour
     int *queue0;      // vertices colored in even rounds
     int *queue1;      // ... in odd rounds
     int *qtail;       // ring of 3 (stride kPad): size of the queue of round r
     int *chunk_tail;  // ring of 3 (stride kPad)
-    int4 *chunks;     // (v, begin, end, prio[v]); grid: the chunks of even rounds
+    int4 *chunks;     // (v, begin, end, count pass: prio[v]); grid: the chunks of even rounds
     int4 *chunks1;    // grid: the chunks of odd rounds
     long long chunk_cap;
     int *colored;     // grid: vertices colored so far
@@ -81,8 +84,8 @@ struct Next {
 // Readied vertex w (priority pw) takes color_next and is queued.  Every active
 // lane of the wave calls this together.
 template <bool CHUNKED>
-__device__ __forceinline__ void push_ready(const ColorArgs &a, bool ready, int w, uint32_t pw, int color_next,
-                                           const Next &nx, int &readied)
+__device__ __forceinline__ void push_ready(const ColorArgs &a, bool ready, int w, int color_next, const Next &nx,
+                                           int &readied)
 {
     if (ready) {
         a.color[w] = color_next;
@@ -102,14 +105,14 @@ __device__ __forceinline__ void push_ready(const ColorArgs &a, bool ready, int w
         const int s = wave_reserve(one, nx.chunk_tail);
         bool defer = false;
         if (one) {
-            if (s < a.chunk_cap) nx.chunks[s] = make_int4(w, beg, end, (int)pw);
+            if (s < a.chunk_cap) nx.chunks[s] = make_int4(w, beg, end, 0);
             else defer = true;
         } else if (ready && nch > 1) {
             const long long base = atomic_add_dev(nx.chunk_tail, nch);
             if (base + nch <= a.chunk_cap) {
                 for (int c = 0; c < nch; ++c) {
                     const int cb = beg + c * a.chunk;
-                    nx.chunks[base + c] = make_int4(w, cb, min(end, cb + a.chunk), (int)pw);
+                    nx.chunks[base + c] = make_int4(w, cb, min(end, cb + a.chunk), 0);
                 }
             } else {
                 // reserved slots below the capacity get empty ranges (the drain
@@ -126,14 +129,15 @@ __device__ __forceinline__ void push_ready(const ColorArgs &a, bool ready, int w
     }
 }
 
-// v (priority pv, colored in round r) releases its neighbours e = first +
-// k * stride < end that it outranks; a neighbour whose count reaches zero is
-// readied with color r + 1.  Every active lane of the wave calls this together
-// (the appends are wave-aggregated); v, first, stride and end may differ per
-// lane.  Returns the number of releases.
+// A vertex colored in round r releases the neighbours e = first + k * stride
+// < end of its row that it outranks (the count pass flagged the others in
+// rcol); a neighbour whose count reaches zero is readied with color r + 1.
+// Every active lane of the wave calls this together (the appends are
+// wave-aggregated); first, stride and end may differ per lane.  Returns the
+// number of releases.
 template <bool CHUNKED>
-__device__ __forceinline__ int release_range(const ColorArgs &a, int v, uint32_t pv, int first, int stride, int end,
-                                             int color_next, const Next &nx, int &readied)
+__device__ __forceinline__ int release_range(const ColorArgs &a, int first, int stride, int end, int color_next,
+                                             const Next &nx, int &readied)
 {
     int rel = 0;
     for (int e0 = first; e0 < end; e0 += kUnroll * stride) {
@@ -141,40 +145,31 @@ __device__ __forceinline__ int release_range(const ColorArgs &a, int v, uint32_t
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
             const int e = e0 + k * stride;
-            w[k] = e < end ? a.col[e] : v;
+            w[k] = e < end ? a.rcol[e] : kNoRelease;
         }
-        uint32_t pw[kUnroll];
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) pw[k] = w[k] != v ? a.prio[w[k]] : 0u;
         int old[kUnroll];
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
-            const bool out = w[k] != v && above(pv, v, pw[k], w[k]);
-            old[k] = out ? atomic_add_dev(&a.wait[w[k]], -1) : 0;
-            rel += out ? 1 : 0;
+            old[k] = w[k] >= 0 ? atomic_add_dev(&a.wait[w[k]], -1) : 0;
+            rel += w[k] >= 0 ? 1 : 0;
         }
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) push_ready<CHUNKED>(a, old[k] == 1, w[k], pw[k], color_next, nx, readied);
+        for (int k = 0; k < kUnroll; ++k) push_ready<CHUNKED>(a, old[k] == 1, w[k], color_next, nx, readied);
     }
     return rel;
 }
 
-// One neighbour w of v (block-level drain, one edge per thread).
-__device__ __forceinline__ int release_one(const ColorArgs &a, int v, uint32_t pv, int w, int color_next,
-                                           const Next &nx, int &readied)
+// One flagged neighbour w (block-level drain, one edge per thread).
+__device__ __forceinline__ int release_one(const ColorArgs &a, int w, int color_next, const Next &nx, int &readied)
 {
-    const uint32_t pw = a.prio[w];
-    const bool out = w != v && above(pv, v, pw, w);
-    const bool ready = out && atomic_add_dev(&a.wait[w], -1) == 1;
-    push_ready<false>(a, ready, w, pw, color_next, nx, readied);
-    return out ? 1 : 0;
+    const bool ready = w >= 0 && atomic_add_dev(&a.wait[w], -1) == 1;
+    push_ready<false>(a, ready, w, color_next, nx, readied);
+    return w >= 0 ? 1 : 0;
 }
 
 template <int BLOCK>
 struct ColorLds {
-    int v[BLOCK];
     int beg[BLOCK];
-    uint32_t p[BLOCK];
     int pre[BLOCK + 1];
     int scan_tmp[2 * (BLOCK / kWave)];
     int base;
@@ -200,13 +195,11 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
     for (int base = blockIdx.x * BLOCK; base < size; base += gridDim.x * BLOCK) {
         const int i = base + threadIdx.x;
         const bool member = i < size;
-        int v = 0, beg = 0, end = 0;
-        uint32_t pv = 0;
+        int beg = 0, end = 0;
         if (member) {
-            v = q[i];
+            const int v = q[i];
             beg = a.row_ptr[v];
             end = a.row_ptr[v + 1];
-            pv = a.prio[v];
         }
         const int deg = end - beg;
         const bool heavy = MODE != WC_FLAT && deg > a.threshold;
@@ -216,23 +209,20 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
             acc.items += heavy ? 1 : 0;
             if (MODE == WC_WAVE && __ballot(heavy) && lane == 0) acc.dispatches += 1;
         }
-        if (member && !heavy) acc.updates += release_range<false>(a, v, pv, beg, 1, end, r + 1, nx, readied);
+        if (member && !heavy) acc.updates += release_range<false>(a, beg, 1, end, r + 1, nx, readied);
         if constexpr (MODE == WC_WAVE) {
             uint64_t mask = __ballot(heavy);
             while (mask) {
                 const int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                acc.updates_buffered += release_range<false>(a, readlane(v, b), readlane_u(pv, b),
-                                                             readlane(beg, b) + lane, kWave, readlane(end, b), r + 1,
-                                                             nx, readied);
+                acc.updates_buffered +=
+                    release_range<false>(a, readlane(beg, b) + lane, kWave, readlane(end, b), r + 1, nx, readied);
             }
         } else if constexpr (MODE == WC_BLOCK) {
             int k, off, nb, total;
             block_scan2<BLOCK>(heavy ? 1 : 0, heavy ? deg : 0, sb.scan_tmp, k, off, nb, total);
             if (heavy) {
-                sb.v[k] = v;
                 sb.beg[k] = beg;
-                sb.p[k] = pv;
                 sb.pre[k] = off;
             }
             if (threadIdx.x == 0) {
@@ -243,8 +233,8 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
             int it = 0;
             for (int j = threadIdx.x; j < total; j += BLOCK) {
                 while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
-                const int w = a.col[sb.beg[it] + (j - sb.pre[it])];
-                acc.updates_buffered += release_one(a, sb.v[it], sb.p[it], w, r + 1, nx, readied);
+                const int w = a.rcol[sb.beg[it] + (j - sb.pre[it])];
+                acc.updates_buffered += release_one(a, w, r + 1, nx, readied);
             }
             __syncthreads();  // the LDS buffer is reused by the next window
         }
@@ -284,16 +274,14 @@ __global__ __launch_bounds__(BLOCK) void color_round_grid(ColorArgs a, int r)
             acc.buffered += end - beg;
             acc.edges += end - beg;
         }
-        const int v = __builtin_amdgcn_readfirstlane(d.x);
-        const uint32_t pv = (uint32_t)__builtin_amdgcn_readfirstlane(d.w);
-        acc.updates_buffered += release_range<true>(a, v, pv, beg + lane_id(), kWave, end, r + 1, nx, readied);
+        acc.updates_buffered += release_range<true>(a, beg + lane_id(), kWave, end, r + 1, nx, readied);
     }
     const int *dq = (r & 1) ? a.queue1 : a.queue0;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < ndefer; i += gridDim.x * BLOCK) {
         const int v = dq[i];
         const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
         if (a.want_stats) acc.edges += end - beg;
-        acc.updates += release_range<true>(a, v, a.prio[v], beg, 1, end, r + 1, nx, readied);
+        acc.updates += release_range<true>(a, beg, 1, end, r + 1, nx, readied);
     }
     readied = wave_sum_i(readied);
     if (lane_id() == 0 && readied) (void)atomic_add_dev(a.colored, readied);
@@ -316,6 +304,15 @@ __global__ void color_publish(ColorArgs a)
     if (threadIdx.x == 0) store_system(&a.host_ring[kHostSlotGraph], *a.colored);
 }
 
+// Edge e of v's row toward u: does u outrank v?  Flags the edge in rcol when
+// v has nothing to release along it (u outranks v, or a self-loop).
+__device__ __forceinline__ bool count_edge(const ColorArgs &a, int v, uint32_t pv, int u, int e)
+{
+    const bool o = u != v && above(a.prio[u], u, pv, v);
+    a.rcol[e] = (o || u == v) ? (u | kNoRelease) : u;
+    return o;
+}
+
 // Neighbours e = first + k * stride < end of v (priority pv) that outrank v.
 __device__ __forceinline__ int count_range(const ColorArgs &a, int v, uint32_t pv, int first, int stride, int end)
 {
@@ -328,7 +325,10 @@ __device__ __forceinline__ int count_range(const ColorArgs &a, int v, uint32_t p
             u[k] = e < end ? a.col[e] : v;
         }
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) cnt += u[k] != v && above(a.prio[u[k]], u[k], pv, v) ? 1 : 0;
+        for (int k = 0; k < kUnroll; ++k) {
+            const int e = e0 + k * stride;
+            if (e < end) cnt += count_edge(a, v, pv, u[k], e) ? 1 : 0;
+        }
     }
     return cnt;
 }
@@ -390,8 +390,8 @@ __global__ __launch_bounds__(BLOCK) void color_count(ColorArgs a)
             int it = 0;
             for (int j = threadIdx.x; j < total; j += BLOCK) {
                 while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
-                const int u = a.col[sb.beg[it] + (j - sb.pre[it])];
-                if (u != sb.v[it] && above(a.prio[u], u, sb.p[it], sb.v[it])) atomicAdd(&sb.cnt[it], 1);
+                const int e = sb.beg[it] + (j - sb.pre[it]);
+                if (count_edge(a, sb.v[it], sb.p[it], a.col[e], e)) atomicAdd(&sb.cnt[it], 1);
             }
             __syncthreads();
             if (heavy) cnt = sb.cnt[k];
@@ -572,7 +572,7 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
     // entries per buffer never overflow
     const long long cap_full = n + m / chunk + 1;
     const long long cap = grid_mode ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    const size_t need = 3 * padded(n * 4) + 3 * padded(3 * kPad * 4) + 2 * padded(cap * 16);
+    const size_t need = 3 * padded(n * 4) + padded(m * 4) + 3 * padded(3 * kPad * 4) + 2 * padded(cap * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     ColorArgs a;
@@ -582,6 +582,7 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
     a.prio = prio;
     a.color = color;
     a.wait = pool_take<int>(ctx, n);
+    a.rcol = pool_take<int>(ctx, m);
     a.queue0 = pool_take<int>(ctx, n);
     a.queue1 = pool_take<int>(ctx, n);
     a.qtail = pool_take<int>(ctx, 3 * kPad);
