@@ -274,7 +274,28 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
             row[name]["speedup_vs_basic_dp"] = round(row["basic_dp"]["ms"] / row[name]["ms"], 1)
         out[f"rmat{scale}"] = row
         print(f"[bench] ablation scale {scale}: {row}", file=sys.stderr, flush=True)
-    return {"workload": "SSSP from vertex 0 on R-MAT graphs of 2^12 and 2^16 vertices, degree 16", "results": out}
+        # SpMV on the same matrix: one child launch per heavy row (driver 2)
+        val = torch.from_numpy(synth.values(g.m)).cuda()
+        x = torch.from_numpy(synth.vector_x(g.n)).cuda()
+        y = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        srow = {}
+        for name, mode, tune in (("basic_dp", "grid", wc.make_tune(driver=2)), ("flat", "flat", None),
+                                 ("wave", "wave", None), ("block", "block", None), ("grid", "grid", None)):
+            _, st = ctx.spmv(dg, val, x, mode=mode, tune=tune, out=y, stats=True)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                ctx.spmv(dg, val, x, mode=mode, tune=tune, out=y)
+            b.record(stream)
+            torch.cuda.synchronize()
+            srow[name] = {"ms": round(a.elapsed_time(b) / reps, 3), "child_dispatches": st["dispatches"]}
+        for name in ("flat", "wave", "block", "grid"):
+            srow[name]["speedup_vs_basic_dp"] = round(srow["basic_dp"]["ms"] / srow[name]["ms"], 1)
+        out[f"spmv_rmat{scale}"] = srow
+        print(f"[bench] ablation spmv scale {scale}: {srow}", file=sys.stderr, flush=True)
+    return {"workload": "SSSP from vertex 0, and SpMV, on R-MAT graphs of 2^12 and 2^16 vertices, degree 16",
+            "results": out}
 
 
 def time_tree(ctx, torch, wc, stream, t, reps):

@@ -22,6 +22,7 @@
 // stays within 1e-5 of the row's magnitude sum of the exact product.
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "wc_block.h"
 #include "wc_device.h"
@@ -426,6 +427,41 @@ __global__ __launch_bounds__(BLOCK) void spmv_combine(SpmvArgs a)
     }
 }
 
+// basic dynamic parallelism, emulated for comparison (driver 2): the parent
+// sums the light rows inline and lists the heavy ones; the host then launches
+// one child per listed row (no consolidation).
+constexpr int kBasicBlock = 256;
+__global__ __launch_bounds__(kBasicBlock) void spmv_parent_basic(SpmvArgs a)
+{
+    for (int base = blockIdx.x * kBasicBlock; base < a.n; base += gridDim.x * kBasicBlock) {
+        const int r = base + threadIdx.x;
+        const bool valid = r < a.n;
+        int beg = 0, end = 0;
+        if (valid) {
+            beg = a.row_ptr[r];
+            end = a.row_ptr[r + 1];
+        }
+        const bool heavy = valid && end - beg > a.threshold;
+        if (valid && !heavy) a.y[r] = dot_strided(a, beg, 1, end);
+        const int s = wave_reserve(heavy, &a.bin_total[0]);
+        if (heavy && s < a.rows_cap) a.rows_buf[s] = make_int4(r, beg, end, 0);
+    }
+}
+
+// The child of ONE heavy row: one workgroup strides over the row, then a
+// fixed-order workgroup sum.
+__global__ __launch_bounds__(kBasicBlock) void spmv_child_basic(SpmvArgs a, int r, int beg, int end)
+{
+    __shared__ float tmp[kBasicBlock / kWave];
+    const float s = block_sum<kBasicBlock>(dot_strided(a, beg + (int)threadIdx.x, kBasicBlock, end), tmp);
+    if (threadIdx.x == 0) a.y[r] = s;
+}
+
+__global__ void spmv_basic_reset(SpmvArgs a)
+{
+    if (threadIdx.x == 0) a.bin_total[0] = 0;
+}
+
 struct SpmvKernels {
     const void *parent, *classify, *parent_grid, *drain, *combine;
 };
@@ -616,8 +652,43 @@ extern "C" wc_status wc_spmv(wc_ctx *ctx, const wc_csr *g, const float *val, con
     if (st != WC_OK) return st;
     p.a.x = x;
     p.a.y = y;
+    if (p.cfg.driver == 1 || p.cfg.driver == 3 || (p.cfg.driver == 2 && mode != WC_GRID))
+        return fail(WC_EINVAL, "wc_spmv: driver 2 needs grid mode; drivers 1 and 3 do not apply");
     st = begin_call(ctx, stream, stats);
-    if (st == WC_OK) st = spmv_launch(ctx, &p, stream);
+    if (st != WC_OK) return st;
+    if (p.cfg.driver == 2) {
+        // Basic dynamic parallelism, emulated: the host reads the heavy rows back
+        // and launches one child per row.
+        void *args[] = {&p.a};
+        st = launch(ctx, "spmv_basic_reset", reinterpret_cast<const void *>(&spmv_basic_reset), dim3(1), dim3(64),
+                    args, stream);
+        const int bgrid = (int)std::min<long long>((g->n + kBasicBlock - 1) / kBasicBlock, 4LL * ctx->num_cus);
+        if (st == WC_OK)
+            st = launch(ctx, "spmv_parent_basic", reinterpret_cast<const void *>(&spmv_parent_basic), dim3(bgrid),
+                        dim3(kBasicBlock), args, stream);
+        if (st != WC_OK) return st;
+        int tail = 0;
+        WC_HIP(hipMemcpyAsync(&tail, p.a.bin_total, sizeof(int), hipMemcpyDeviceToHost, stream));
+        WC_HIP(hipStreamSynchronize(stream));
+        const int count = (int)std::min<long long>(tail, p.a.rows_cap);
+        std::vector<int4> rows((size_t)std::max(count, 1));
+        if (count > 0) WC_HIP(hipMemcpy(rows.data(), p.a.rows_buf, sizeof(int4) * (size_t)count, hipMemcpyDeviceToHost));
+        chain_break(ctx);
+        for (int i = 0; i < count; ++i) {
+            int r = rows[i].x, beg = rows[i].y, end = rows[i].z;
+            void *cargs[] = {&p.a, &r, &beg, &end};
+            st = launch(ctx, "spmv_child_basic", reinterpret_cast<const void *>(&spmv_child_basic), dim3(1),
+                        dim3(kBasicBlock), cargs, stream);
+            if (st != WC_OK) return st;
+        }
+        st = end_call(ctx, stream, stats, 1, p.cfg.fail_on_overflow);
+        if (stats) {
+            stats->items_buffered = count;
+            stats->dispatches = count;
+        }
+        return st;
+    }
+    st = spmv_launch(ctx, &p, stream);
     if (st != WC_OK) return st;
     return end_call(ctx, stream, stats, 1, p.cfg.fail_on_overflow);
 }
@@ -643,6 +714,7 @@ extern "C" wc_status wc_pagerank(wc_ctx *ctx, const wc_csr *in_graph, const int3
     wc_status st = spmv_plan(ctx, in_graph, nullptr, mode, tune, 2 * padded(n * 4) + padded((size_t)pgrid * 4), stream,
                              stats, &p);
     if (st != WC_OK) return st;
+    if (p.cfg.driver != 0) return fail(WC_EINVAL, "wc_pagerank: only the relaunch driver (driver = 0) applies");
     PrArgs q;
     q.out_degree = out_degree;
     q.rank = rank;

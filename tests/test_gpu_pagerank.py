@@ -86,6 +86,9 @@ def test_invalid_arguments(ctx, c1_pr):
             ctx.pagerank(dg, od, args["iterations"], damping=args["damping"])
     with pytest.raises(wc.WcError):
         ctx.pagerank(dg, od, 3, mode=9)
+    for driver in (1, 2, 3):
+        with pytest.raises(wc.WcError):
+            ctx.pagerank(dg, od, 3, mode="grid", tune=wc.make_tune(driver=driver))
 
 
 def test_stats(ctx, c1_pr):

@@ -95,6 +95,25 @@ def test_bookkeeping_matches_oracle_plan(ctx, c1):
         assert st["items_buffered"] == 0 and st["dispatches"] == 0
 
 
+def test_basic_driver_emulates_per_row_children(ctx, c1):
+    """Driver 2 (basic dynamic parallelism emulated: one host-launched child per
+    heavy row) gives the same bound and one child launch per row above the
+    threshold; it is reproducible run to run."""
+    g, val, x, y_ref, b = c1
+    lens = np.diff(g.row_ptr)
+    for th in (8, 64):
+        y1, st = run(ctx, g, val, x, "grid", stats=True, driver=2, threshold=th)
+        y2 = run(ctx, g, val, x, "grid", driver=2, threshold=th)
+        assert oracle.spmv_check(y_ref, b, y1) == (0, -1)
+        assert np.array_equal(y1.view(np.uint32), y2.view(np.uint32))
+        assert st["dispatches"] == st["items_buffered"] == int((lens > th).sum())
+    da = wc.DeviceCSR.from_host(g.row_ptr, g.col)
+    for mode, tune in (("block", dict(driver=2)), ("grid", dict(driver=3)), ("grid", dict(driver=1))):
+        with pytest.raises(wc.WcError):
+            ctx.spmv(da, f32_to_dev(val), f32_to_dev(x), mode=mode, tune=wc.make_tune(**tune))
+    torch.cuda.synchronize()
+
+
 def test_fig2_worked_example(ctx):
     """Two heavy rows of 326 and 234 nonzeros in one scope: one consolidated
     dispatch carrying both (Sec. IV.A, Fig. 2)."""
