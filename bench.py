@@ -247,9 +247,9 @@ def run_coloring(ctx, torch, synth, wc, stream, g, reps=3):
 def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
     """The paper's comparison against basic dynamic parallelism (Fig. 7, Fig. 8's
     launch counts), on this GPU: SSSP with one host-launched child per buffered
-    vertex (tune driver 2, no consolidation) beside flat and the three
-    consolidation levels, on smaller R-MAT graphs (the per-vertex launches make
-    the basic variant slow)."""
+    vertex and SpMV with one per heavy row (tune driver 2, no consolidation)
+    beside flat and the three consolidation levels, on smaller R-MAT graphs (the
+    per-item launches make the basic variant slow)."""
     out = {}
     for scale in scales:
         g = synth.rmat_csr(scale, 16 << scale)
