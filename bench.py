@@ -247,9 +247,10 @@ def run_coloring(ctx, torch, synth, wc, stream, g, reps=3):
 def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
     """The paper's comparison against basic dynamic parallelism (Fig. 7, Fig. 8's
     launch counts), on this GPU: SSSP with one host-launched child per buffered
-    vertex and SpMV with one per heavy row (tune driver 2, no consolidation)
-    beside flat and the three consolidation levels, on smaller R-MAT graphs (the
-    per-item launches make the basic variant slow)."""
+    vertex, SpMV with one per heavy row and tree descendants with one per
+    internal node (tune driver 2, no consolidation) beside flat and the three
+    consolidation levels, on smaller inputs (the per-item launches make the
+    basic variant slow)."""
     out = {}
     for scale in scales:
         g = synth.rmat_csr(scale, 16 << scale)
@@ -294,8 +295,28 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
             srow[name]["speedup_vs_basic_dp"] = round(srow["basic_dp"]["ms"] / srow[name]["ms"], 1)
         out[f"spmv_rmat{scale}"] = srow
         print(f"[bench] ablation spmv scale {scale}: {srow}", file=sys.stderr, flush=True)
-    return {"workload": "SSSP from vertex 0, and SpMV, on R-MAT graphs of 2^12 and 2^16 vertices, degree 16",
-            "results": out}
+        # tree descendants on a random tree of the same size: one child launch per internal node
+        t = synth.random_tree(1 << scale)
+        dt = wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child)
+        desc = torch.empty(t.n, dtype=torch.int32, device="cuda")
+        trow = {}
+        for name, mode, tune in (("basic_dp", "grid", wc.make_tune(driver=2)), ("flat", "flat", None),
+                                 ("wave", "wave", None), ("block", "block", None), ("grid", "grid", None)):
+            _, st = ctx.tree_descendants(dt, mode=mode, tune=tune, out=desc, stats=True)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                ctx.tree_descendants(dt, mode=mode, tune=tune, out=desc)
+            b.record(stream)
+            torch.cuda.synchronize()
+            trow[name] = {"ms": round(a.elapsed_time(b) / reps, 3), "child_dispatches": st["dispatches"]}
+        for name in ("flat", "wave", "block", "grid"):
+            trow[name]["speedup_vs_basic_dp"] = round(trow["basic_dp"]["ms"] / trow[name]["ms"], 1)
+        out[f"td_tree{scale}"] = trow
+        print(f"[bench] ablation tree descendants 2^{scale} nodes: {trow}", file=sys.stderr, flush=True)
+    return {"workload": "SSSP from vertex 0 and SpMV on R-MAT graphs of 2^12 and 2^16 vertices, degree 16; "
+                        "tree descendants on random trees of 2^12 and 2^16 nodes", "results": out}
 
 
 def time_tree(ctx, torch, wc, stream, t, reps):

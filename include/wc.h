@@ -102,11 +102,13 @@ typedef struct {
     int32_t driver;         /* 0: one launch per round/level (host relaunch);
                                1: one persistent co-resident launch with a grid barrier
                                   (refused: WC_EINVAL);
-                               2: SSSP and SpMV grid mode only, for comparison: basic
-                                  dynamic parallelism emulated, one host-launched child
-                                  per buffered vertex (SSSP) or heavy row (SpMV, one
-                                  workgroup per row), no consolidation
-                                  (stats->dispatches counts the child launches);
+                               2: grid mode of SSSP, SpMV and the trees only, for
+                                  comparison: basic dynamic parallelism emulated, one
+                                  host-launched child per buffered vertex (SSSP), heavy
+                                  row (SpMV, one workgroup per row) or internal node
+                                  (trees, deepest first; the host reads the tree back),
+                                  no consolidation (stats->dispatches counts the child
+                                  launches);
                                3: SSSP grid mode only, for comparison: the "1-1 mapping"
                                   configuration of Sec. V.B, the consolidated child
                                   launched with one wave per buffered chunk (the host

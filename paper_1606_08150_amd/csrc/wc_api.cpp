@@ -162,10 +162,11 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
     if (t.items_per_lane > 64) return fail(WC_EINVAL, "items_per_lane must be at most 64");
     if (t.driver < 0 || t.driver > 3)
         return fail(WC_EINVAL,
-                    "driver must be 0 (relaunch), 1 (persistent), 2 (basic; SSSP and SpMV grid only) or 3 (1-1 "
-                    "mapping; SSSP grid only)");
-    if (t.driver >= 2 && strcmp(problem, "sssp") && !(t.driver == 2 && !strcmp(problem, "spmv")))
-        return fail(WC_EINVAL, "driver 2 exists for SSSP and SpMV, driver 3 for SSSP only");
+                    "driver must be 0 (relaunch), 1 (persistent), 2 (basic; grid mode of SSSP, SpMV and trees) or "
+                    "3 (1-1 mapping; SSSP grid only)");
+    if (t.driver >= 2 && strcmp(problem, "sssp") &&
+        !(t.driver == 2 && (!strcmp(problem, "spmv") || !strcmp(problem, "tree"))))
+        return fail(WC_EINVAL, "driver 2 exists for SSSP, SpMV and trees, driver 3 for SSSP only");
     out->threshold = t.threshold;
     out->block = t.block_threads;
     out->grid = t.grid_blocks;

@@ -29,6 +29,7 @@
 // gives identical results.
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "wc_block.h"
 #include "wc_device.h"
@@ -598,6 +599,33 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
     if (a.want_stats) stat_flush(a.stats, acc);
 }
 
+// basic dynamic parallelism, emulated for comparison (driver 2): every node
+// with children is a recursive call whose child kernel runs over its
+// children; the host launches one such kernel per internal node, bottom-up,
+// and the post-work folds the children (fixed-order workgroup reduction).
+constexpr int kBasicBlock = 256;
+template <int OP>
+__global__ __launch_bounds__(kBasicBlock) void tree_child_basic(TreeArgs a, int v)
+{
+    __shared__ int tmp[kBasicBlock / kWave];
+    const int beg = a.child_ptr[v], end = a.child_ptr[v + 1];
+    int acc = 0;
+    for (int i = beg + (int)threadIdx.x; i < end; i += kBasicBlock) acc = fold<OP>(acc, a.out[a.child[i]]);
+    acc = OP == OP_DESC ? wave_sum_i(acc) : wave_max_i(acc);
+    if (lane_id() == 0) tmp[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int k = 0; k < kBasicBlock / kWave; ++k) r = OP == OP_DESC ? r + tmp[k] : max(r, tmp[k]);
+        a.out[v] = r;
+    }
+}
+
+__global__ void tree_zero_out(TreeArgs a)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += gridDim.x * blockDim.x) a.out[v] = 0;
+}
+
 // ---------------------------------------------------------------- host side
 
 template <int OP, int BLOCK>
@@ -649,6 +677,48 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
     a.want_stats = stats != nullptr;
     a.bar_blocks = grid;
     a.work_cap = BLOCK * cfg.items_per_lane;
+    if (cfg.driver == 2) {
+        if (mode != WC_GRID) return fail(WC_EINVAL, "tree: driver 2 needs grid mode");
+        // Basic dynamic parallelism, emulated: the host walks the tree (read back
+        // once) and launches one child kernel per internal node, deepest first.
+        std::vector<int> cp((size_t)n + 1), ch((size_t)std::max<long long>(n - 1, 1));
+        WC_HIP(hipMemcpy(cp.data(), t->child_ptr, sizeof(int) * (size_t)(n + 1), hipMemcpyDeviceToHost));
+        if (n > 1) WC_HIP(hipMemcpy(ch.data(), t->child, sizeof(int) * (size_t)(n - 1), hipMemcpyDeviceToHost));
+        std::vector<int> order;
+        order.reserve((size_t)n);
+        order.push_back(0);
+        for (size_t i = 0; i < order.size(); ++i) {
+            const int v = order[i];
+            if (cp[v] < 0 || cp[v + 1] > n - 1 || cp[v] > cp[v + 1])
+                return fail(WC_EINVAL, "tree: child_ptr out of range");
+            for (int k = cp[v]; k < cp[v + 1]; ++k) {
+                if (ch[k] <= 0 || ch[k] >= n || (long long)order.size() >= n)
+                    return fail(WC_EINVAL, "tree: child list is not a tree rooted at 0");
+                order.push_back(ch[k]);
+            }
+        }
+        wc_status st = begin_call(ctx, stream, stats);
+        if (st != WC_OK) return st;
+        void *zargs[] = {&a};
+        st = launch(ctx, "tree_zero_out", reinterpret_cast<const void *>(&tree_zero_out),
+                    dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)), dim3(256), zargs, stream);
+        long long launches = 0;
+        for (size_t i = order.size(); i-- > 0 && st == WC_OK;) {
+            int v = order[i];
+            if (cp[v + 1] == cp[v]) continue;
+            void *cargs[] = {&a, &v};
+            st = launch(ctx, "tree_child_basic", reinterpret_cast<const void *>(&tree_child_basic<OP>), dim3(1),
+                        dim3(kBasicBlock), cargs, stream);
+            ++launches;
+        }
+        if (st != WC_OK) return st;
+        st = end_call(ctx, stream, stats, 0, cfg.fail_on_overflow);
+        if (stats) {
+            stats->dispatches = launches;
+            stats->items_buffered = launches;
+        }
+        return st;
+    }
     const bool queue_mode = mode == WC_WAVE || mode == WC_BLOCK;
     if (queue_mode) {
         a.work_cap = (mode == WC_WAVE ? kWave : BLOCK) * cfg.items_per_lane;
@@ -704,19 +774,8 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
                     dim3(1), dim3(64), args, stream);
         if (st != WC_OK) return st;
     }
-    if (cfg.driver == 1) {
+    if (cfg.driver == 1)
         return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
-        int ml = (int)std::min<long long>(max_levels, 0x7fffffff);
-        void *args[] = {&a, &ml};
-        WC_HIP(hipLaunchCooperativeKernel(ks.persistent, dim3(grid), dim3(BLOCK), args, 0, stream));
-        st = end_call(ctx, stream, stats, -1, cfg.fail_on_overflow);
-        if (stats && st == WC_OK) {
-            int r = 0;
-            WC_HIP(hipMemcpy(&r, &ctx->dstats->rounds, sizeof(int), hipMemcpyDeviceToHost));
-            stats->rounds = r;
-        }
-        return st;
-    }
     // A call repeated on the same tree replays a captured graph of all levels
     // (down to the recorded depth plus one empty level, then up); the empty
     // level publishes its count, and a non-zero count (a deeper tree at the same

@@ -80,6 +80,26 @@ def test_persistent_driver_is_refused(ctx, small_tree):
     torch.cuda.synchronize()
 
 
+def test_basic_driver_emulates_per_node_children(ctx, small_tree):
+    """Driver 2 (basic dynamic parallelism emulated: one host-launched child
+    kernel per internal node, deepest first) gives the oracle's results with one
+    launch per internal node."""
+    t, d, h = small_tree
+    internal = int((np.diff(t.child_ptr) > 0).sum())
+    got, st = run(ctx, t, "desc", "grid", stats=True, driver=2)
+    assert np.array_equal(got, d) and st["dispatches"] == internal
+    assert np.array_equal(run(ctx, t, "height", "grid", driver=2), h)
+    # a chain: one launch per node but the last, each after its child
+    ch = synth.chain_tree(300)
+    assert np.array_equal(run(ctx, ch, "desc", "grid", driver=2), oracle.tree_descendants(ch.child_ptr, ch.child))
+    assert np.array_equal(run(ctx, ch, "height", "grid", driver=2), oracle.tree_height(ch.child_ptr, ch.child))
+    with pytest.raises(wc.WcError):
+        run(ctx, t, "desc", "block", driver=2)
+    with pytest.raises(wc.WcError):
+        run(ctx, t, "desc", "grid", driver=3)
+    torch.cuda.synchronize()
+
+
 def test_bookkeeping(ctx, small_tree):
     t, d, h = small_tree
     internal = int((np.diff(t.child_ptr) > 0).sum())
