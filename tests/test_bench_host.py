@@ -1,0 +1,75 @@
+"""Host logic of bench.py (CPU only): the one-GPU guard, the algorithmic-byte
+models behind the roofline, the counter-file lookup keyed by the kernel sources,
+and the kernel-trace summary."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_algorithmic_bytes_models():
+    info = {"sssp_edges_buffered": 1000, "sssp_updates_buffered": 10, "sssp_calls": 3, "sssp_edges": 1200,
+            "sssp_updates": 15, "n": 50, "sssp_rounds": 4, "nnz_heavy": 700, "rows_heavy": 7, "nnz_light": 300}
+    b, _ = bench.algorithmic_bytes("sssp_drain", info, 6)
+    assert b == (12 * 1000 + 8 * 10) * 3 / 6
+    b, _ = bench.algorithmic_bytes("sssp_round_grid", info, 12)
+    assert b == (12 * 200 + 8 * 5 + 4 * 50 * 4) * 3 / 12
+    assert bench.algorithmic_bytes("spmv_drain", info, 1)[0] == 12 * 700 + 4 * 7
+    assert bench.algorithmic_bytes("spmv_parent_grid", info, 1)[0] == 12 * 300 + 8 * 50
+    assert bench.algorithmic_bytes("something_else", info, 1) is None
+
+
+def test_counter_traffic_follows_the_source_hash(tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_1606_08150_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "k.hip").write_text("// kernel v1\n")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h = bench.source_hash()
+    rec = {"kernel": "sssp_drain", "hbm_bytes_per_launch": 1234, "source_hash": h}
+    (tmp_path / "profiles" / "sssp_drain_w_pmc.json").write_text(json.dumps(rec))
+    assert bench.counter_traffic("sssp_drain", "w") == 1234
+    assert bench.counter_traffic("spmv_drain", "w") is None  # no file
+    (csrc / "k.hip").write_text("// kernel v2\n")  # sources changed since the counters were taken
+    assert bench.source_hash() != h
+    assert bench.counter_traffic("sssp_drain", "w") is None
+
+
+def test_kernel_stats_summary(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    csv_path = tmp_path / "stats.csv"
+    csv_path.write_text(
+        "Name,Calls,TotalDurationNs,AverageNs,Percentage,MinNs,MaxNs,StdDev\n"
+        "\"void wc::(anonymous namespace)::sssp_drain<512>(wc::(anonymous namespace)::SsspArgs, int)\","
+        "10,1000000,100000,75.0,3000,600000,1\n"
+        "\"wc::zero_stats(wc::DevStats*)\",5,10000,2000,25.0,1900,2100,1\n")
+    bench.summarize_kernel_stats(str(csv_path), "w", "rocprofv3 --kernel-trace --stats -- python3 bench.py", "ks_w")
+    text = (tmp_path / "profiles" / "ks_w.md").read_text()
+    assert "rocprofv3 --kernel-trace --stats -- python3 bench.py" in text
+    row = next(line for line in text.splitlines() if line.startswith("| sssp_drain"))
+    cells = [c.strip() for c in row.split("|")]
+    assert cells[2] == "10" and cells[3] == "100.00" and cells[6] == "1.000"
+    assert any(line.startswith("| zero_stats") for line in text.splitlines())
+
+
+@pytest.mark.parametrize("name,short", [
+    ("void wc::(anonymous namespace)::color_round_grid<256>(wc::(anonymous namespace)::ColorArgs, int)",
+     "color_round_grid"),
+    ("wc::zero_stats(wc::DevStats*)", "zero_stats"),
+])
+def test_short_kernel_names(name, short):
+    assert bench._short_kernel(name) == short
