@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--no-pagerank", action="store_true", help="skip the PageRank section")
     p.add_argument("--no-coloring", action="store_true", help="skip the graph coloring section")
     p.add_argument("--no-ablation", action="store_true", help="skip the basic dynamic parallelism comparison")
+    p.add_argument("--no-config-search", action="store_true",
+                   help="skip the comparison of the default configuration with exhaustive search")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -317,6 +319,60 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
         print(f"[bench] ablation tree descendants 2^{scale} nodes: {trow}", file=sys.stderr, flush=True)
     return {"workload": "SSSP from vertex 0 and SpMV on R-MAT graphs of 2^12 and 2^16 vertices, degree 16; "
                         "tree descendants on random trees of 2^12 and 2^16 nodes", "results": out}
+
+
+def run_config_search(ctx, torch, synth, wc, stream, g, w, val, x, reps=3):
+    """The configuration heuristic against exhaustive search (Sec. V.B compares
+    KC_X with the best configuration found by search): grid mode of SSSP, SpMV and
+    tree descendants on the headline inputs, every combination of workgroup size,
+    items per lane, threshold and drain grid (resident maximum, or fewer
+    workgroups as KC_X would give), against the library's defaults."""
+    import itertools
+    dg = wc.DeviceCSR.from_host(g.row_ptr, g.col)
+    dw = torch.from_numpy(w.view(np.int32)).cuda()
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    dval, dx = torch.from_numpy(val).cuda(), torch.from_numpy(x).cuda()
+    y = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    t = synth.random_tree(1 << 22)
+    dt = wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child)
+    desc = torch.empty(t.n, dtype=torch.int32, device="cuda")
+    calls = {"sssp": lambda tu: ctx.sssp(dg, dw, 0, mode="grid", tune=tu, out=dist),
+             "spmv": lambda tu: ctx.spmv(dg, dval, dx, mode="grid", tune=tu, out=y),
+             "tree_descendants": lambda tu: ctx.tree_descendants(dt, mode="grid", tune=tu, out=desc)}
+
+    def timed(fn, tu):
+        fn(tu)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn(tu)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {}
+    for name, fn in calls.items():
+        default_ms = timed(fn, None)
+        best = (default_ms, "defaults")
+        space = itertools.product((256, 512, 1024), (1, 2, 4, 8), (0, 4, 16, 32) if name != "tree_descendants"
+                                  else (0,), (0, 512, 256, 128))
+        tried = 0
+        for block, ipl, th, gb in space:
+            kw = dict(block_threads=block, items_per_lane=ipl)
+            if th:
+                kw["threshold"] = th
+            if gb:
+                kw["grid_blocks"] = gb
+            ms = timed(fn, wc.make_tune(**kw))
+            tried += 1
+            if ms < best[0]:
+                best = (ms, kw)
+        out[name] = {"default_ms": round(default_ms, 4), "best_ms": round(best[0], 4), "best_config": best[1],
+                     "default_vs_best": round(best[0] / default_ms, 3), "configs_tried": tried}
+        print(f"[bench] config search {name}: {out[name]}", file=sys.stderr, flush=True)
+    return {"workload": "grid mode on the scale-22 graph (SSSP from vertex 0, SpMV) and the 2^22-node tree "
+                        "(descendants); grid_blocks 0 = resident maximum (KC_1)", "results": out}
 
 
 def time_tree(ctx, torch, wc, stream, t, reps):
@@ -685,6 +741,11 @@ def main():
     if not args.no_ablation:
         ablation = run_ablation(ctx, torch, synth, wc, stream)
 
+    # ---- the configuration heuristic against exhaustive search (grid mode)
+    config_search = None
+    if not args.no_config_search:
+        config_search = run_config_search(ctx, torch, synth, wc, stream, g, w, val, x)
+
     # ---- trees: descendants and heights on the 2^22-node random tree, every mode
     trees = None
     if not args.no_trees:
@@ -753,6 +814,7 @@ def main():
         "pagerank": pagerank,
         "coloring": coloring,
         "basic_dp_ablation": ablation,
+        "config_search": config_search,
         "trees": trees,
         "batch": batch,
         "serving": serving,
