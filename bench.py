@@ -146,6 +146,95 @@ def summarize_kernel_stats(stats_csv, workload, command, out_name):
         f.write("\n".join(lines) + "\n")
 
 
+def static_resources(kernels):
+    """{kernel: (VGPRs, scratch B/lane, waves per SIMD, LDS B/block)} of the 512-thread
+    instantiations, from hipcc's kernel-resource-usage remarks on the sources."""
+    import re
+    import subprocess
+    csrc = os.path.join(ROOT, "paper_1606_08150_amd", "csrc")
+    out = {}
+    for src in ("wc_sssp.hip", "wc_spmv.hip"):
+        cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+               "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-c", os.path.join(csrc, src),
+               "-o", os.devnull, "-Rpass-analysis=kernel-resource-usage"]
+        text = subprocess.run(cmd, capture_output=True, text=True).stderr
+        cur = None
+        for line in text.splitlines():
+            m = re.search(r"Function Name: (\S+)", line)
+            if m:
+                name = m.group(1)
+                cur = next((k for k in kernels if f"{len(k)}{k}ILi512E" in name), None)
+                if cur:
+                    out[cur] = {}
+                continue
+            if cur is None:
+                continue
+            for key, pat in (("vgprs", r"VGPRs: (\d+)"), ("scratch", r"ScratchSize \[bytes/lane\]: (\d+)"),
+                             ("waves", r"Occupancy \[waves/SIMD\]: (\d+)"), ("lds", r"LDS Size \[bytes/block\]: (\d+)")):
+                m = re.search(pat, line)
+                if m:
+                    out[cur][key] = int(m.group(1))
+    return out
+
+
+def summarize_counters(sq_dir, tcc_dir, workload, command, out_name,
+                       kernels=("sssp_drain", "sssp_round_grid2", "spmv_drain", "spmv_parent_grid"),
+                       with_static=True):
+    """profiles/<out_name>.md: per-kernel wave, VALU, memory-instruction, L2 and
+    atomic counters from two rocprofv3 --pmc runs (SQ_* + GRBM_GUI_ACTIVE, then
+    TCC_*), summed over each kernel's dispatches, and the static resources
+    (registers, scratch, occupancy, LDS) from hipcc's resource-usage remarks."""
+    import csv
+    tot = {}
+    for d in (sq_dir, tcc_dir):
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                k = _short_kernel(r["Kernel_Name"])
+                if k not in kernels:
+                    continue
+                ent = tot.setdefault(k, {"dispatches": set(), "wg": int(r["Workgroup_Size"])})
+                ent["dispatches"].add((d, r["Dispatch_Id"]))
+                ent[r["Counter_Name"]] = ent.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    lines = [f"# Counters: {workload}", "", "Commands (two passes):", "", "```", command, "```", "",
+             "Sums over every dispatch of the kernel in the run. Ratios of SQ sums are relative measures "
+             "(the SQ counters are accumulated over all shader engines).", "",
+             "| kernel | dispatches | workgroup | waves | VALU insts / wave | VMEM reads / wave | wave-cycles / wave "
+             "| VALU-active / wave-cycles | waiting / wave-cycles | L2 hit rate | L2 atomics / dispatch "
+             "| EA atomics / dispatch |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+
+    def per(x, y):
+        return f"{x / y:.2f}" if y else "-"
+    for k in kernels:
+        if k not in tot:
+            continue
+        e = tot[k]
+        nd = len({i for (d, i) in e["dispatches"] if d == sq_dir}) or 1
+        ntcc = len({i for (d, i) in e["dispatches"] if d == tcc_dir}) or 1
+        waves, wcyc = e.get("SQ_WAVES", 0.0), e.get("SQ_WAVE_CYCLES", 0.0)
+        hit, miss = e.get("TCC_HIT_sum", 0.0), e.get("TCC_MISS_sum", 0.0)
+        lines.append(f"| {k} | {nd} | {e['wg']} | {waves:.0f} | {per(e.get('SQ_INSTS_VALU', 0.0), waves)} | "
+                     f"{per(e.get('SQ_INSTS_VMEM_RD', 0.0), waves)} | {per(wcyc, waves)} | "
+                     f"{per(e.get('SQ_ACTIVE_INST_VALU', 0.0), wcyc)} | {per(e.get('SQ_WAIT_INST_ANY', 0.0), wcyc)} | "
+                     f"{per(hit, hit + miss)} | {e.get('TCC_ATOMIC_sum', 0.0) / ntcc:.0f} | "
+                     f"{e.get('TCC_EA0_ATOMIC_sum', 0.0) / ntcc:.0f} |")
+    res = static_resources(kernels) if with_static else {}
+    if res:
+        lines += ["", "Static resources of the 512-thread kernels (`hipcc --offload-arch=gfx950 -O3 -std=c++17 "
+                  "-Xclang -target-feature -Xclang -packed-fp32-ops -c <wc_sssp.hip|wc_spmv.hip> "
+                  "-Rpass-analysis=kernel-resource-usage`):", "",
+                  "| kernel | VGPRs | scratch B/lane | waves/SIMD | LDS B/block |", "|---|---|---|---|---|"]
+        for k in kernels:
+            if k in res:
+                r = res[k]
+                lines.append(f"| {k} | {r.get('vgprs', '-')} | {r.get('scratch', '-')} | {r.get('waves', '-')} | "
+                             f"{r.get('lds', '-')} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return tot
+
+
 def summarize_profiles(fetch_dir, write_dir, copy_mb, workload, command):
     """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; csv output) of
     `command` into profiles/<kernel>_<workload>_pmc.json files: KiB per dispatch
@@ -520,6 +609,17 @@ def run_serving(args, torch, synth, wc):
 
 
 def main():
+    if "--summarize-counters" in sys.argv:
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--summarize-counters", action="store_true")
+        sp.add_argument("--sq-dir", required=True)
+        sp.add_argument("--tcc-dir", required=True)
+        sp.add_argument("--workload", default="rmat22")
+        sp.add_argument("--command", required=True)
+        sp.add_argument("--out-name", required=True)
+        a = sp.parse_args()
+        summarize_counters(a.sq_dir, a.tcc_dir, a.workload, a.command, a.out_name)
+        return
     if "--summarize-profiles" in sys.argv:
         sp = argparse.ArgumentParser()
         sp.add_argument("--summarize-profiles", action="store_true")

@@ -73,3 +73,31 @@ def test_kernel_stats_summary(tmp_path, monkeypatch):
 ])
 def test_short_kernel_names(name, short):
     assert bench._short_kernel(name) == short
+
+
+def test_counter_summary(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    head = ("Correlation_Id,Dispatch_Id,Agent_Id,Queue_Id,Process_Id,Thread_Id,Grid_Size,Kernel_Id,Kernel_Name,"
+            "Workgroup_Size,LDS_Block_Size,Scratch_Size,VGPR_Count,Accum_VGPR_Count,SGPR_Count,Counter_Name,"
+            "Counter_Value,Start_Timestamp,End_Timestamp\n")
+    name = "\"void wc::(anonymous namespace)::sssp_drain<512>(wc::(anonymous namespace)::SsspArgs, int)\""
+
+    def row(disp, counter, value):
+        return f"1,{disp},A,1,1,1,512,1,{name},512,0,0,24,0,16,{counter},{value},0,1\n"
+    sq, tcc = tmp_path / "sq", tmp_path / "tcc"
+    sq.mkdir()
+    tcc.mkdir()
+    (sq / "run_counter_collection.csv").write_text(
+        head + row(1, "SQ_WAVES", 100) + row(1, "SQ_INSTS_VALU", 5000) + row(1, "SQ_WAVE_CYCLES", 4000)
+        + row(2, "SQ_WAVES", 100) + row(2, "SQ_INSTS_VALU", 3000) + row(2, "SQ_WAVE_CYCLES", 4000))
+    (tcc / "run_counter_collection.csv").write_text(
+        head + row(1, "TCC_HIT_sum", 30) + row(1, "TCC_MISS_sum", 10) + row(1, "TCC_ATOMIC_sum", 8)
+        + row(2, "TCC_HIT_sum", 30) + row(2, "TCC_MISS_sum", 30) + row(2, "TCC_ATOMIC_sum", 4))
+    bench.summarize_counters(str(sq), str(tcc), "w", "cmd", "ctr_w", with_static=False)
+    line = next(x for x in (tmp_path / "profiles" / "ctr_w.md").read_text().splitlines()
+                if x.startswith("| sssp_drain"))
+    cells = [c.strip() for c in line.split("|")][1:-1]
+    # dispatches, waves, VALU per wave, wave-cycles per wave, L2 hit rate, atomics per dispatch
+    assert cells[1] == "2" and cells[3] == "200" and cells[4] == "40.00" and cells[6] == "40.00"
+    assert cells[9] == "0.60" and cells[10] == "6"
