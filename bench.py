@@ -12,6 +12,7 @@ Printed as one JSON line:
   modes        flat / wave / block / grid side by side (SSSP GTEPS, SpMV GB/s)
   roofline     the step's dominant kernel: algorithmic bytes per launch divided
                by its event-measured average launch duration, against 8 TB/s
+               (and against the attainable rate of a plain 1 GiB device copy)
   cpu_baseline the oracle (binary-heap Dijkstra) on this host, GTEPS
 """
 from __future__ import annotations
@@ -755,6 +756,25 @@ def main():
 
     roofline = roof(dominant[0])
     spmv_roofline = roof("spmv_drain") if "spmv_drain" in ktimes else None
+
+    # ---- attainable HBM bandwidth on this GPU: a plain 1 GiB device copy (read +
+    # write bytes over the event-timed copy), reported beside the published peak
+    src_c = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    dst_c = torch.empty_like(src_c)
+    dst_c.copy_(src_c)
+    torch.cuda.synchronize()
+    a_ev, b_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a_ev.record(stream)
+    for _ in range(5):
+        dst_c.copy_(src_c)
+    b_ev.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * src_c.numel() * 4 * 5 / (a_ev.elapsed_time(b_ev) * 1e-3) / 1e9
+    del src_c, dst_c
+    for rl in (roofline, spmv_roofline):
+        if rl is not None:
+            rl["attainable_copy"] = round(copy_gbs, 1)
+            rl["frac_of_attainable"] = round(rl["achieved"] / copy_gbs, 4)
 
     # ---- cold caches: each call after a 512 MiB write that evicts L2 and MALL
     cold = None
