@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--edge-factor", type=int, default=16)
     p.add_argument("--no-modes", action="store_true", help="skip the flat/wave/block/grid side-by-side table")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-reps", type=int, default=5)
+    p.add_argument("--cpu-reps", type=int, default=8)
     p.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched SSSP section")
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--batch-reps", type=int, default=10)
