@@ -38,7 +38,8 @@ def test_host_helpers_match_oracle():
 
 def test_default_tune_and_errors():
     t = wc.default_tune("sssp", "grid", 2048)
-    assert t["grid_blocks"] == 2048 and t["items_per_lane"] == 4 and t["block_threads"] == 512
+    assert t["grid_blocks"] == 2048 and t["items_per_lane"] == 2 and t["block_threads"] == 512
+    assert wc.default_tune("sssp", "block", 2048)["items_per_lane"] == 4
     assert wc.default_tune("sssp", "block", 2048)["block_threads"] == 256
     assert wc.default_tune("spmv", "grid", 1)["items_per_lane"] == 8
     assert wc.default_tune("tree", "block", 100)["threshold"] == 0
