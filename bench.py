@@ -822,7 +822,7 @@ def main():
         del col64, gout
         print(f"[bench] gather ceiling: {gather_ceiling}", file=sys.stderr, flush=True)
 
-    # ---- flat / wave / block / grid side by side (1 timed run each after 1 warm-up)
+    # ---- flat / wave / block / grid side by side (mean of 3 calls after 1 warm-up)
     modes = {}
     if not args.no_modes:
         for mode in ("flat", "wave", "block", "grid"):
