@@ -180,7 +180,7 @@ def static_resources(kernels):
 
 def summarize_counters(sq_dir, tcc_dir, workload, command, out_name,
                        kernels=("sssp_drain", "sssp_round_grid2", "spmv_drain", "spmv_parent_grid"),
-                       with_static=True):
+                       with_static=True, cyc_dir=None, cyc_command=None):
     """profiles/<out_name>.md: per-kernel wave, VALU, memory-instruction, L2 and
     atomic counters from two rocprofv3 --pmc runs (SQ_* + GRBM_GUI_ACTIVE, then
     TCC_*), summed over each kernel's dispatches, and the static resources
@@ -219,6 +219,23 @@ def summarize_counters(sq_dir, tcc_dir, workload, command, out_name,
                      f"{per(e.get('SQ_ACTIVE_INST_VALU', 0.0), wcyc)} | {per(e.get('SQ_WAIT_INST_ANY', 0.0), wcyc)} | "
                      f"{per(hit, hit + miss)} | {e.get('TCC_ATOMIC_sum', 0.0) / ntcc:.0f} | "
                      f"{e.get('TCC_EA0_ATOMIC_sum', 0.0) / ntcc:.0f} |")
+    if cyc_dir:
+        cyc = {}
+        with open(os.path.join(cyc_dir, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                k = _short_kernel(r["Kernel_Name"])
+                if k in kernels:
+                    cyc.setdefault(k, {})
+                    cyc[k][r["Counter_Name"]] = cyc[k].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        cols = ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_LDS")
+        lines += ["", "Where the wave-cycles go (each counter over SQ_WAVE_CYCLES, same units):", "", "```",
+                  cyc_command or "", "```", "",
+                  "| kernel | " + " | ".join(c.replace("SQ_", "").lower() for c in cols) + " |",
+                  "|---|" + "---|" * len(cols)]
+        for k in kernels:
+            if k in cyc and cyc[k].get("SQ_WAVE_CYCLES"):
+                wcy = cyc[k]["SQ_WAVE_CYCLES"]
+                lines.append(f"| {k} | " + " | ".join(f"{cyc[k].get(c, 0.0) / wcy:.3f}" for c in cols) + " |")
     res = static_resources(kernels) if with_static else {}
     if res:
         lines += ["", "Static resources of the 512-thread kernels (`hipcc --offload-arch=gfx950 -O3 -std=c++17 "
@@ -618,8 +635,11 @@ def main():
         sp.add_argument("--workload", default="rmat22")
         sp.add_argument("--command", required=True)
         sp.add_argument("--out-name", required=True)
+        sp.add_argument("--cyc-dir", default=None)
+        sp.add_argument("--cyc-command", default=None)
         a = sp.parse_args()
-        summarize_counters(a.sq_dir, a.tcc_dir, a.workload, a.command, a.out_name)
+        summarize_counters(a.sq_dir, a.tcc_dir, a.workload, a.command, a.out_name, cyc_dir=a.cyc_dir,
+                           cyc_command=a.cyc_command)
         return
     if "--summarize-profiles" in sys.argv:
         sp = argparse.ArgumentParser()
