@@ -380,33 +380,53 @@ int orc_pagerank_f64(int32_t n, const int32_t *in_row_ptr, const int32_t *in_col
 
 /* --------------------------------------------------------------- trees ---- */
 
-/* Structure check: root 0 with parent -1, child lists agree with parent[],
- * every node reachable from the root.  Returns 0 if valid. */
+/* Structure check of a rooted tree in the form the recursion of Fig. 1(c)
+ * walks: node 0 is the root (parent -1); child_ptr[0..n] is a non-decreasing
+ * offset array from 0 to n-1; every child entry names a node in [1, n) whose
+ * parent[] is the node listing it; no node is listed twice; and every node is
+ * reached from the root (so the parent links have no cycle).  Returns 0 for a
+ * tree; otherwise a code naming the first violation:
+ *   1 n < 1                      2 parent[0] != -1 or child_ptr[0] != 0
+ *   3 child_ptr[n] != n - 1      4 child_ptr decreases somewhere
+ *   5 child entry out of [1, n)  6 child entry whose parent[] is another node
+ *   7 node listed twice          8 node not reached from the root
+ *  -2 out of memory */
 int orc_tree_validate(int32_t n, const int32_t *parent, const int32_t *child_ptr, const int32_t *child)
 {
     if (n < 1) return 1;
-    if (parent[0] != -1 || child_ptr[0] != 0 || child_ptr[n] != n - 1) return 2;
+    if (parent[0] != -1 || child_ptr[0] != 0) return 2;
+    if (child_ptr[n] != n - 1) return 3;
+    for (int32_t p = 0; p < n; ++p)
+        if (child_ptr[p + 1] < child_ptr[p]) return 4;
+    /* from here on every offset lies in [0, n-1], so child[] is read in bounds */
+    uint8_t *listed = (uint8_t *)calloc((size_t)n, 1);
     int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    if (!queue) return -2;
-    int rc = 0;
-    for (int32_t p = 0; p < n && rc == 0; ++p) {
-        if (child_ptr[p + 1] < child_ptr[p]) rc = 3;
-        for (int32_t e = child_ptr[p]; e < child_ptr[p + 1] && rc == 0; ++e)
-            if (child[e] <= 0 || child[e] >= n || parent[child[e]] != p) rc = 4;
+    if (!listed || !queue) {
+        free(listed);
+        free(queue);
+        return -2;
     }
+    int rc = 0;
+    for (int32_t p = 0; p < n && rc == 0; ++p)
+        for (int32_t e = child_ptr[p]; e < child_ptr[p + 1] && rc == 0; ++e) {
+            const int32_t c = child[e];
+            if (c <= 0 || c >= n) rc = 5;
+            else if (parent[c] != p) rc = 6;
+            else if (listed[c]) rc = 7;
+            else listed[c] = 1;
+        }
     if (rc == 0) {
+        /* n - 1 distinct entries in [1, n): every non-root node is listed once;
+         * breadth-first from the root then visits each node at most once */
         int64_t head = 0, tail = 0;
         queue[tail++] = 0;
-        while (head < tail && tail <= n) {
-            int32_t u = queue[head++];
-            for (int32_t e = child_ptr[u]; e < child_ptr[u + 1]; ++e) {
-                if (tail >= n) { rc = 5; break; }
-                queue[tail++] = child[e];
-            }
-            if (rc) break;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            for (int32_t e = child_ptr[u]; e < child_ptr[u + 1]; ++e) queue[tail++] = child[e];
         }
-        if (rc == 0 && tail != n) rc = 6;
+        if (tail != n) rc = 8;
     }
+    free(listed);
     free(queue);
     return rc;
 }

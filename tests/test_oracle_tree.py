@@ -116,3 +116,88 @@ def test_planted_mistakes_break_the_invariants():
     bad[int(np.flatnonzero(np.diff(t.child_ptr) > 0)[3])] += 1
     assert not np.array_equal(bad, brute)
     assert bad.astype(np.int64).sum() != t.depth.astype(np.int64).sum()
+
+
+# ---- the structure check rejects what is not a tree ---------------------------------------------
+
+def _arrays(t):
+    return t.parent.copy(), t.child_ptr.copy(), t.child.copy()
+
+
+def test_validate_accepts_exactly_the_trees_among_tiny_parent_arrays():
+    """Brute force over every parent array of 5 nodes (parent[0] = -1, parent[v]
+    in 0..4): it is a tree iff following parents from every node reaches the
+    root, and the check must say so for each of the 5^4 arrays, with child lists
+    built from the parent array."""
+    import itertools
+    n = 5
+    for ps in itertools.product(range(n), repeat=n - 1):
+        parent = np.array((-1,) + ps, np.int32)
+        reaches_root = True
+        for v in range(1, n):
+            u, steps = v, 0
+            while u != 0 and steps <= n:
+                u, steps = parent[u], steps + 1
+            reaches_root = reaches_root and u == 0
+        counts = np.bincount(parent[1:], minlength=n)
+        child_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        child = np.argsort(parent[1:], kind="stable").astype(np.int32) + 1
+        rc = oracle.tree_validate(parent, child_ptr, child)
+        assert (rc == 0) == reaches_root, (ps, rc)
+        if not reaches_root:
+            assert rc == 8  # a cycle among non-root nodes: not reached from the root
+
+
+def test_validate_rejects_a_cycle():
+    # 0 -> 1 -> 2 is a tree; make 3 and 4 each other's parent (both listed, neither reached)
+    parent = np.array([-1, 0, 1, 4, 3], np.int32)
+    child_ptr = np.array([0, 1, 2, 2, 3, 4], np.int32)
+    child = np.array([1, 2, 4, 3], np.int32)
+    assert oracle.tree_validate(parent, child_ptr, child) == 8
+
+
+def test_validate_rejects_a_wrong_parent():
+    t = synth.kary_tree(3, 3)
+    parent, child_ptr, child = _arrays(t)
+    v = int(child[-1])
+    parent[v] = 0 if parent[v] != 0 else 1  # listed under one node, parent[] names another
+    assert oracle.tree_validate(parent, child_ptr, child) == 6
+
+
+def test_validate_rejects_a_duplicate_child():
+    # a leaf listed twice in place of another leaf: the count of entries still
+    # matches n - 1 and every parent[] agrees, so only the duplicate gives it away
+    t = synth.star_tree(6)
+    parent, child_ptr, child = _arrays(t)
+    child[1] = child[0]
+    assert oracle.tree_validate(parent, child_ptr, child) == 7
+
+
+def test_validate_rejects_an_unreachable_node():
+    # node 5 has parent 4 and is listed under 4, but 4 and 5 hang off each other
+    parent = np.array([-1, 0, 0, 0, 5, 4], np.int32)
+    child_ptr = np.array([0, 3, 3, 3, 3, 4, 5], np.int32)
+    child = np.array([1, 2, 3, 5, 4], np.int32)
+    assert oracle.tree_validate(parent, child_ptr, child) == 8
+
+
+def test_validate_rejects_bad_offsets_and_entries():
+    t = synth.kary_tree(2, 3)
+    parent, child_ptr, child = _arrays(t)
+    bad = child_ptr.copy()
+    bad[-1] = t.n  # child_ptr[n] must be n - 1
+    assert oracle.tree_validate(parent, bad, np.concatenate([child, [1]]).astype(np.int32)) == 3
+    bad = child_ptr.copy()
+    bad[1], bad[2] = bad[2], bad[1]  # decreasing offsets
+    if bad[1] != bad[2]:
+        assert oracle.tree_validate(parent, bad, child) == 4
+    bad = child.copy()
+    bad[0] = t.n  # entry out of range
+    assert oracle.tree_validate(parent, child_ptr, bad) == 5
+    bad = child.copy()
+    bad[0] = 0  # the root listed as a child
+    assert oracle.tree_validate(parent, child_ptr, bad) == 5
+    p2 = parent.copy()
+    p2[0] = 0
+    assert oracle.tree_validate(p2, child_ptr, child) == 2
+    assert oracle.tree_validate(parent, child_ptr, child) == 0
