@@ -67,25 +67,27 @@ def parse():
 def algorithmic_bytes(kernel: str, info: dict, launches: int) -> tuple[float, str] | None:
     """Algorithmic bytes per launch of `kernel` (each datum read or written once),
     from the per-unit figures: SpMV 12 B per nonzero (col, val, x gather) + 8 B
-    per row (row_ptr, y); SSSP 12 B per edge relaxation (col, w, dist read) + 8 B
-    per update (dist write, frontier stamp).  For kernels launched once per round
-    the units are the per-call totals spread over that call's launches (empty
-    trailing rounds included)."""
+    per row (row_ptr, y); SSSP 16 B per reachable edge (col 4, w 4, dist[v] read
+    and write 8) + 20 B per reached vertex (row_ptr 8, dist[u] 4, frontier in and
+    out 8), each edge and vertex counted once however often the schedule relaxes
+    it (re-relaxations are overhead, not useful bytes).  The SSSP drain handles
+    the reached vertices above the grid threshold, the parent the others.  For
+    kernels launched once per round the units are the per-call totals spread over
+    that call's launches (empty trailing rounds included)."""
     if kernel == "spmv_drain":
         return 12.0 * info["nnz_heavy"] + 4.0 * info["rows_heavy"], "12 B x nonzeros of buffered rows + 4 B x rows"
     if kernel == "spmv_parent_grid":
         return (12.0 * info["nnz_light"] + 8.0 * info["n"],
                 "12 B x nonzeros of inline rows + 8 B x rows (row_ptr, y)")
     if kernel == "sssp_drain":
-        per_call = 12.0 * info["sssp_edges_buffered"] + 8.0 * info["sssp_updates_buffered"]
+        per_call = 16.0 * info["reached_edges_heavy"] + 20.0 * info["reached_heavy"]
         return (per_call * info["sssp_calls"] / launches,
-                "12 B x edges relaxed by the drain (col, w, dist read) + 8 B x its updates (dist write, frontier mark)")
+                "16 B x reachable edges of reached vertices above the threshold (col, w, dist read + write) "
+                "+ 20 B x those vertices (row_ptr, dist, frontier in + out)")
     if kernel.startswith("sssp_round"):
-        inline = info["sssp_edges"] - info["sssp_edges_buffered"]
-        upd_inline = info["sssp_updates"] - info["sssp_updates_buffered"]
-        per_call = 12.0 * inline + 8.0 * upd_inline + 4.0 * info["n"] * info["sssp_rounds"]
+        per_call = 16.0 * info["reached_edges_light"] + 20.0 * info["reached_light"]
         return (per_call * info["sssp_calls"] / launches,
-                "12 B x inline edges + 8 B x inline updates + 4 B x vertices scanned per round")
+                "16 B x reachable edges of reached vertices up to the threshold + 20 B x those vertices")
     return None
 
 
@@ -751,10 +753,16 @@ def main():
     lens = np.diff(g.row_ptr).astype(np.int64)
     thr = wc.default_tune("spmv", args.mode, 1)["threshold"]
     heavy = lens > thr
+    sssp_thr = wc.default_tune("sssp", args.mode, 1)["threshold"]
+    reached_np = reached_mask.cpu().numpy()
+    sheavy = reached_np & (lens > sssp_thr)
+    slight = reached_np & ~(lens > sssp_thr)
     info = dict(n=g.n, nnz_heavy=int(lens[heavy].sum()), rows_heavy=int(heavy.sum()),
                 nnz_light=int(lens[~heavy].sum()), sssp_edges=sst["edges_processed"],
                 sssp_edges_buffered=sst["edges_buffered"], sssp_updates=sst["updates"],
-                sssp_updates_buffered=sst["updates_buffered"], sssp_rounds=sst["rounds"], sssp_calls=args.steps)
+                sssp_updates_buffered=sst["updates_buffered"], sssp_rounds=sst["rounds"], sssp_calls=args.steps,
+                reached_edges_heavy=int(lens[sheavy].sum()), reached_heavy=int(sheavy.sum()),
+                reached_edges_light=int(lens[slight].sum()), reached_light=int(slight.sum()))
     workload_tag = f"rmat{scale}"
     dominant = max(ktimes.items(), key=lambda kv: kv[1][1])
     kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_ms": round(v[1] / v[0], 5)}
@@ -947,6 +955,7 @@ def main():
         "gather_ceiling": gather_ceiling,
         "cold_caches": cold,
         "sssp_work": {"edges_relaxed": sst["edges_processed"], "edges_by_consolidated_child": sst["edges_buffered"],
+                      "relaxations_per_reachable_edge": round(sst["edges_processed"] / max(m_reached, 1), 4),
                       "updates": sst["updates"], "updates_by_consolidated_child": sst["updates_buffered"],
                       "rounds": sst["rounds"], "items_buffered": sst["items_buffered"]},
         "kernels": kernels,

@@ -16,8 +16,7 @@
  *              the inserts from the drain (Sec. IV.B).
  *   WC_GRID  - one global buffer per grid, filled with wave-aggregated atomic
  *              appends; the whole grid drains it after a grid-wide barrier
- *              (a kernel boundary, or the counter barrier of Sec. IV.E inside a
- *              persistent co-resident grid).
+ *              (a kernel boundary: the host relaunches one round at a time).
  *   WC_FLAT  - no consolidation: each parent thread does all of its item's
  *              work itself (the paper's flat "no-dp" baseline, Sec. V).
  * All modes compute the same result; the consolidated child processes each
@@ -26,13 +25,17 @@
  * Conventions shared by every entry point:
  *  - Array arguments are DEVICE pointers owned by the caller; the library never
  *    frees or retains them beyond the call's stream work.
- *  - Work is enqueued on `stream`.  SSSP and the trees decide at run time how
- *    many rounds/levels to run; with the relaunch driver (tune->driver = 0) the
- *    host waits on device-published round counts, so the call returns once the
- *    last round has been enqueued.  With the persistent driver (driver = 1) the
- *    call only enqueues.  Either way the caller synchronizes before reading
+ *  - Work is enqueued on `stream`.  SSSP, BFS, coloring and the trees decide at
+ *    run time how many rounds/levels to run: the host waits on device-published
+ *    round counts (each tagged with the call's epoch, so a value left by an
+ *    earlier call is never taken for this one), and the call returns once the
+ *    last round has been enqueued.  The caller synchronizes before reading
  *    outputs, unless `stats` is non-NULL, in which case the call synchronizes
  *    the stream itself to fill it in.
+ *  - Device-side waits (the packet queues of the wave and block modes of the
+ *    trees) are bounded in time (2 s by default, wc_ctx_set_wait_limit); a call
+ *    containing such waits returns only after its kernels are done and reports
+ *    WC_ETIMEOUT if a wait gave up, with or without `stats`.
  *  - A context owns one pre-allocated device pool (the custom allocator of
  *    Sec. IV.E) from which every call carves its buffers.  Calls that share a
  *    context must be issued on one stream (or be externally serialized).
@@ -100,8 +103,9 @@ typedef struct {
                                items per drain lane; grid-level chunks hold
                                64 * items_per_lane elements; <= 0: 4 */
     int32_t driver;         /* 0: one launch per round/level (host relaunch);
-                               1: one persistent co-resident launch with a grid barrier
-                                  (refused: WC_EINVAL);
+                               1: reserved for a persistent co-resident launch: not
+                                  available, every entry point refuses it with
+                                  WC_EINVAL before enqueueing anything;
                                2: grid mode of SSSP, SpMV and the trees only, for
                                   comparison: basic dynamic parallelism emulated, one
                                   host-launched child per buffered vertex (SSSP), heavy
@@ -245,6 +249,14 @@ wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *graphs, const 
  * afterwards.  Enabling or disabling waits for the device and discards earlier
  * records. */
 wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable);
+
+/* Bound of every device-side wait of later calls on this context (the packet
+ * queues of the trees' wave and block modes), in microseconds; <= 0 restores
+ * the default of 2 s.  A wait that passes its bound gives up and the call
+ * returns WC_ETIMEOUT (its outputs are then incomplete); every kernel still
+ * exits normally.  Meant for tests of the timeout path and for callers that
+ * want a tighter bound.  WC_EINVAL for a NULL context. */
+wc_status wc_ctx_set_wait_limit(wc_ctx *ctx, int64_t microseconds);
 
 /* Aggregate of the recorded launches of the index-th distinct kernel name (in
  * first-launch order): its name (a static string), launch count, total and

@@ -14,6 +14,7 @@
 #include <thread>
 
 #include "wc_internal.h"
+#include "wc_stats.h"
 
 namespace wc {
 
@@ -162,8 +163,10 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
     if (t.items_per_lane > 64) return fail(WC_EINVAL, "items_per_lane must be at most 64");
     if (t.driver < 0 || t.driver > 3)
         return fail(WC_EINVAL,
-                    "driver must be 0 (relaunch), 1 (persistent), 2 (basic; grid mode of SSSP, SpMV and trees) or "
+                    "driver must be 0 (relaunch), 2 (basic; grid mode of SSSP, SpMV and trees) or "
                     "3 (1-1 mapping; SSSP grid only)");
+    if (t.driver == 1)
+        return fail(WC_EINVAL, "the persistent driver (driver = 1) is not available: use the relaunch driver");
     if (t.driver >= 2 && strcmp(problem, "sssp") &&
         !(t.driver == 2 && (!strcmp(problem, "spmv") || !strcmp(problem, "tree"))))
         return fail(WC_EINVAL, "driver 2 exists for SSSP, SpMV and trees, driver 3 for SSSP only");
@@ -178,18 +181,28 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
 }
 
 // Clears the per-call device counters with a kernel rather than a memset node,
-// so that a captured graph replays it correctly.
-__global__ void zero_stats(DevStats *s)
+// so that a captured graph replays it correctly, and stores the call's epoch,
+// which every later kernel of the call tags its host-ring values with.
+__global__ void zero_stats(DevStats *s, unsigned int epoch)
 {
     unsigned int *w = reinterpret_cast<unsigned int *>(s);
     for (unsigned i = threadIdx.x; i < sizeof(DevStats) / 4; i += blockDim.x) w[i] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) s->epoch = epoch;
+}
+
+// Publishes the timeout and overflow flags of the call to the host ring.
+__global__ void publish_flags(DevStats *s, unsigned long long *ring)
+{
+    if (threadIdx.x == 0) publish_host(ring, kHostSlotFlags, s, (s->timed_out ? 1 : 0) | (s->overflowed ? 2 : 0));
 }
 
 wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats)
 {
     if (stats) memset(stats, 0, sizeof(*stats));
     chain_break(ctx);  // other work may have been queued since the last call
-    void *args[] = {&ctx->dstats};
+    if (++ctx->epoch == 0) ctx->epoch = 1;
+    void *args[] = {&ctx->dstats, &ctx->epoch};
     wc_status st = launch(ctx, "zero_stats", reinterpret_cast<const void *>(&zero_stats), dim3(1), dim3(64), args,
                           stream);
     if (st != WC_OK) return st;
@@ -200,10 +213,27 @@ wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats)
     return WC_OK;
 }
 
-wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow)
+wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow,
+                   bool bounded_waits)
 {
     DevStats ds;
     chain_break(ctx);
+    if (!stats && bounded_waits) {
+        // the flags come back through the host ring once the call's kernels are done
+        void *args[] = {&ctx->dstats, &ctx->host_ring_dev};
+        clear_host_slot(ctx, kHostSlotFlags);
+        wc_status st = launch(ctx, "publish_flags", reinterpret_cast<const void *>(&publish_flags), dim3(1),
+                              dim3(64), args, stream);
+        if (st != WC_OK) return st;
+        int flags = 0;
+        st = wait_host_slot(ctx, kHostSlotFlags, &flags);
+        if (st != WC_OK) return st;
+        chain_break(ctx);
+        if (flags & 1) return fail(WC_ETIMEOUT, "a device-side wait exceeded its time limit");
+        if (fail_on_overflow && (flags & 2))
+            return fail(WC_EOVERFLOW, "a consolidation buffer overflowed (buf_capacity too small)");
+        return WC_OK;
+    }
     if (stats) {
         WC_HIP(hipEventRecord(ctx->ev_stop, stream));
         WC_HIP(hipMemcpyAsync(&ds, ctx->dstats, sizeof(ds), hipMemcpyDeviceToHost, stream));
@@ -229,7 +259,7 @@ wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds,
         return WC_OK;
     }
     WC_HIP(hipGetLastError());
-    if (ds.timed_out) return fail(WC_ETIMEOUT, "a device-side wait exceeded its spin limit");
+    if (ds.timed_out) return fail(WC_ETIMEOUT, "a device-side wait exceeded its time limit");
     if (fail_on_overflow && ds.overflowed)
         return fail(WC_EOVERFLOW, "a consolidation buffer overflowed (buf_capacity too small)");
     return WC_OK;
@@ -259,7 +289,7 @@ wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes,
 
 void clear_host_slot(wc_ctx *ctx, int index)
 {
-    reinterpret_cast<volatile int *>(ctx->host_ring)[index] = -1;
+    reinterpret_cast<volatile unsigned long long *>(ctx->host_ring)[index] = 0ull;  // epoch 0 is never used
 }
 
 void clear_round_slot(wc_ctx *ctx, int r)
@@ -274,13 +304,13 @@ wc_status wait_round_count(wc_ctx *ctx, int r, int *count)
 
 wc_status wait_host_slot(wc_ctx *ctx, int index, int *count)
 {
-    volatile int *slot = reinterpret_cast<volatile int *>(ctx->host_ring) + index;
+    volatile unsigned long long *slot = reinterpret_cast<volatile unsigned long long *>(ctx->host_ring) + index;
     auto t0 = std::chrono::steady_clock::now();
     long spins = 0;
     for (;;) {
-        int v = *slot;
-        if (v != -1) {
-            *count = v;
+        const unsigned long long v = *slot;  // one aligned 8-byte load: tag and value together
+        if ((unsigned int)(v >> 32) == ctx->epoch) {
+            *count = (int)(unsigned int)(v & 0xffffffffull);
             return WC_OK;
         }
         if (++spins > 2000) {
@@ -374,7 +404,8 @@ wc_status wc_ctx_create(int device, size_t pool_bytes, wc_ctx **out)
     ctx->lds_per_block = prop.sharedMemPerBlock;
     wc_status st = pool_alloc(ctx, pool_bytes ? pool_bytes : (size_t(512) << 20));
     if (st == WC_OK) {
-        e = hipHostMalloc(&ctx->host_ring, sizeof(int) * (kHostSlotGraph + 1), hipHostMallocMapped | hipHostMallocCoherent);
+        e = hipHostMalloc(&ctx->host_ring, sizeof(unsigned long long) * kHostSlots,
+                          hipHostMallocMapped | hipHostMallocCoherent);
         if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&ctx->host_ring_dev, ctx->host_ring, 0);
         if (e == hipSuccess) e = hipMalloc(&ctx->dstats, sizeof(DevStats));
         if (e == hipSuccess) e = hipEventCreate(&ctx->ev_start);
@@ -389,7 +420,8 @@ wc_status wc_ctx_create(int device, size_t pool_bytes, wc_ctx **out)
         wc_ctx_destroy(ctx);
         return st;
     }
-    for (int i = 0; i <= kHostSlotGraph; ++i) ctx->host_ring[i] = -1;
+    for (int i = 0; i < kHostSlots; ++i) ctx->host_ring[i] = 0ull;
+    ctx->wait_ticks = kWaitTicks;
     *out = ctx;
     return WC_OK;
 }
@@ -401,6 +433,14 @@ wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable)
     WC_HIP(hipDeviceSynchronize());
     recycle_records(ctx);
     ctx->timing = enable ? 1 : 0;
+    return WC_OK;
+}
+
+wc_status wc_ctx_set_wait_limit(wc_ctx *ctx, int64_t microseconds)
+{
+    if (!ctx) return fail(WC_EINVAL, "NULL context");
+    // the device clock of the bounded waits counts at 100 MHz
+    ctx->wait_ticks = microseconds > 0 ? (unsigned long long)microseconds * 100ull : kWaitTicks;
     return WC_OK;
 }
 

@@ -52,7 +52,7 @@ struct BatchArgs {
     int *chunk_tail;   // ring of 3 (stride kPad)
     int4 *chunks;      // (global u, begin, end, instance)
     long long chunk_cap;
-    int *host_ring;
+    unsigned long long *host_ring;
     DevStats *stats;
     int want_stats;
     int has_wave, has_block, has_grid;  // which consolidation levels occur in this batch
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(BLOCK) void batch_round(BatchArgs a, int r)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.active[((r + 2) % 3) * kPad] = 0;
         a.chunk_tail[((r + 1) % 3) * kPad] = 0;
-        store_system(&a.host_ring[r % kHostRing], act);
+        publish_host(a.host_ring, r % kHostRing, a.stats, act);
     }
     if (!act) return;
     const int next = r + 1;
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(BLOCK) void batch_drain(BatchArgs a, int r)
 // Publishes whether round r has a frontier (after the graph's last round).
 __global__ void batch_publish(BatchArgs a, int r)
 {
-    if (threadIdx.x == 0) store_system(&a.host_ring[r % kHostRing], a.active[(r % 3) * kPad]);
+    if (threadIdx.x == 0) publish_host(a.host_ring, r % kHostRing, a.stats, a.active[(r % 3) * kPad]);
 }
 
 struct BatchKernels {

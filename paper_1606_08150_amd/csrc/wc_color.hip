@@ -61,7 +61,7 @@ struct ColorArgs {
     int n;
     int threshold;
     int chunk;
-    int *host_ring;
+    unsigned long long *host_ring;
     DevStats *stats;
     int want_stats;
 };
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
     const int size = a.qtail[(r % 3) * kPad];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.qtail[((r + 2) % 3) * kPad] = 0;
-        store_system(&a.host_ring[r % kHostRing], size);
+        publish_host(a.host_ring, r % kHostRing, a.stats, size);
     }
     if (size == 0) return;
     const int *q = (r & 1) ? a.queue1 : a.queue0;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(BLOCK) void color_round_grid(ColorArgs a, int r)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.chunk_tail[((r + 2) % 3) * kPad] = 0;
         a.qtail[((r + 2) % 3) * kPad] = 0;
-        store_system(&a.host_ring[r % kHostRing], (nchunks != 0 || ndefer != 0) ? 1 : 0);
+        publish_host(a.host_ring, r % kHostRing, a.stats, (nchunks != 0 || ndefer != 0) ? 1 : 0);
     }
     if (nchunks == 0 && ndefer == 0) return;
     const int total = (long long)nchunks < a.chunk_cap ? nchunks : (int)a.chunk_cap;
@@ -301,7 +301,7 @@ __global__ void color_reset(ColorArgs a)
 // Grid mode: hands the number of colored vertices to the host.
 __global__ void color_publish(ColorArgs a)
 {
-    if (threadIdx.x == 0) store_system(&a.host_ring[kHostSlotGraph], *a.colored);
+    if (threadIdx.x == 0) publish_host(a.host_ring, kHostSlotGraph, a.stats, *a.colored);
 }
 
 // Edge e of v's row toward u: does u outrank v?  Flags the edge in rcol when

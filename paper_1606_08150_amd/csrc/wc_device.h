@@ -4,8 +4,7 @@
 //    slots of every lane that inserts (the buffer insertion of Fig. 4(b)).
 //  - wave reductions in a fixed butterfly order (deterministic results).
 //  - device-scope atomics with explicit memory scope.
-//  - grid_barrier: the counter barrier of Sec. IV.E, made reusable with a
-//    generation word so one persistent grid can cross it once per round.
+//  - wall-clock deadlines for the bounded device-side waits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,11 +73,6 @@ __device__ __forceinline__ int atomic_load_dev(const int *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void store_system(int *p, int v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 // ---- wave-aggregated append ---------------------------------------------------------------------
 // Every active lane must call this (it issues a ballot).  Lanes with pred
 // receive distinct consecutive slots starting at the value *tail had; the
@@ -133,53 +127,54 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
-// ---- bounded waits --------------------------------------------------------------------------------
-// Every device-side wait is bounded in wall-clock time (the 100 MHz constant
-// clock read by wall_clock64), so a wait that can never end reports a timeout
-// instead of holding the GPU.
-constexpr unsigned long long kWaitTicks = 200000000ull;  // 2 s at 100 MHz
+// ---- summation with a bounded rounding depth -------------------------------------------------------
+// A running fp32 sum of N terms rounds the first term N times, so its error
+// bound grows with N (N * 2^-24 of the magnitude sum).  Cascade keeps four
+// partial sums: terms go into s0; after every 32 terms s0 is added into s1 and
+// restarted, after every 32 * 32 terms s1 into s2, after every 32^3 terms s2
+// into s3; the total is s3 + (s2 + (s1 + s0)).  A term is then rounded at most
+// 32 times in each of the first three levels, ceil(N / 32768) times in s3 and
+// 3 times in the final combination: at most 99 + ceil(N / 32768) roundings
+// (131 for N <= 2^20) instead of N.  The order is fixed, so sums are bitwise
+// reproducible.  Callers either add one term at a time (add) or fuse U terms
+// into s0 themselves and then call step<U>() (U divides 32).
+struct Cascade {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    unsigned int steps = 0;
 
-__device__ __forceinline__ unsigned long long wait_deadline() { return wall_clock64() + kWaitTicks; }
-__device__ __forceinline__ bool past(unsigned long long deadline) { return wall_clock64() > deadline; }
-
-// ---- grid barrier ---------------------------------------------------------------------------------
-// Counter barrier of Sec. IV.E: the counter starts at the number of blocks and
-// each block's first thread decrements it once; the block that takes it to zero
-// is the last arrival.  To reuse it across rounds the last arrival resets the
-// counter and bumps a generation word that the other blocks wait on.  Requires
-// every block of the grid to be co-resident (cooperative launch).
-struct GridBarrier {
-    int count;
-    int generation;
-};
-
-// Returns false if the wait passed its deadline (the grid then has to stop; the
-// caller reports WC_ETIMEOUT).
-__device__ __forceinline__ bool grid_barrier(GridBarrier *b, int nblocks)
-{
-    __syncthreads();
-    bool ok = true;
-    if (threadIdx.x == 0) {
-        int gen = __hip_atomic_load(&b->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // release this block's writes, then arrive
-        int left = __hip_atomic_fetch_add(&b->count, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) - 1;
-        if (left == 0) {
-            __hip_atomic_store(&b->count, nblocks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&b->generation, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const unsigned long long deadline = wait_deadline();
-            while (__hip_atomic_load(&b->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (past(deadline)) {
-                    ok = false;
-                    break;
+    template <int U>
+    __device__ __forceinline__ void step()
+    {
+        static_assert(U >= 1 && 32 % U == 0, "U must divide 32");
+        ++steps;
+        if ((steps & (32u / U - 1u)) == 0u) {
+            s1 += s0;
+            s0 = 0.f;
+            if ((steps & (1024u / U - 1u)) == 0u) {
+                s2 += s1;
+                s1 = 0.f;
+                if ((steps & (32768u / U - 1u)) == 0u) {
+                    s3 += s2;
+                    s2 = 0.f;
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __syncthreads();
-    return ok;
-}
+    __device__ __forceinline__ void add(float x)
+    {
+        s0 += x;
+        step<1>();
+    }
+    __device__ __forceinline__ float total() const { return s3 + (s2 + (s1 + s0)); }
+};
+
+// ---- bounded waits --------------------------------------------------------------------------------
+// Every device-side wait is bounded in wall-clock time (the 100 MHz constant
+// clock read by wall_clock64), so a wait that can never end reports a timeout
+// instead of holding the GPU.  The bound is the context's (default 2 s).
+constexpr unsigned long long kWaitTicks = 200000000ull;  // 2 s at 100 MHz
+
+__device__ __forceinline__ unsigned long long wait_deadline(unsigned long long ticks) { return wall_clock64() + ticks; }
+__device__ __forceinline__ bool past(unsigned long long deadline) { return wall_clock64() > deadline; }
 
 }  // namespace wc

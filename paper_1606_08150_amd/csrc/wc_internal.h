@@ -32,14 +32,22 @@ struct DevStats {
     int overflowed;
     int timed_out;
     int rounds;
-    int pad;
+    unsigned int epoch;  // the call's epoch, written by its first kernel (zero_stats)
 };
 
-// Ring of round counts published by kernels to pinned host memory, so the host
-// can stop relaunching rounds without a blocking copy per round.
+// Ring of values (round counts, flags) published by kernels to pinned host
+// memory, so the host can stop relaunching rounds without a blocking copy per
+// round.  Each entry is 64-bit: the call's epoch in the high half, the value in
+// the low half.  A call waits only for entries carrying its own epoch, so a
+// value left behind by an earlier call's trailing kernels (rounds enqueued past
+// the last one with work) is never taken for one of this call.
 constexpr int kHostRing = 256;
 // host-ring entry after the round slots, written only by a graph's last kernel
 constexpr int kHostSlotGraph = kHostRing;
+// entry written by the last kernel of a call that has bounded device-side
+// waits: bit 0 = a wait timed out, bit 1 = a buffer overflowed
+constexpr int kHostSlotFlags = kHostRing + 1;
+constexpr int kHostSlots = kHostRing + 2;
 
 }  // namespace wc
 
@@ -57,8 +65,10 @@ struct wc_ctx {
     char *pool = nullptr;      // device pool (the pre-allocated allocator of Sec. IV.E)
     size_t pool_bytes = 0;
     size_t pool_off = 0;
-    int *host_ring = nullptr;  // pinned, device-visible
-    int *host_ring_dev = nullptr;
+    unsigned long long *host_ring = nullptr;  // pinned, device-visible; see kHostRing
+    unsigned long long *host_ring_dev = nullptr;
+    unsigned int epoch = 0;  // of the current call (begin_call advances it; never 0)
+    unsigned long long wait_ticks = 0;  // bound of every device-side wait, in 100 MHz ticks
     wc::DevStats *dstats = nullptr;  // device
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     // optional per-kernel timing: events recorded around every launch
@@ -133,21 +143,29 @@ wc_status launch(wc_ctx *ctx, const char *name, const void *kernel, dim3 grid, d
                  hipStream_t stream);
 wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_tune *tune, int resident, Config *out);
 
-// Call bracket: validates the mode, clears stats, records the start event.
+// Call bracket: advances the call epoch, clears the device counters (and sets
+// the epoch there for the kernels), records the start event.
 wc_status begin_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats);
 // Records the stop event; fills `stats` (synchronizing) when non-NULL; reports
-// overflow / timeout flags.
-wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow);
+// overflow / timeout flags.  A call whose kernels contain bounded waits passes
+// bounded_waits = true: without `stats` the host then waits for a last kernel
+// that publishes the flags, so a wait that gave up is reported as WC_ETIMEOUT
+// whether or not stats were requested.
+wc_status end_call(wc_ctx *ctx, hipStream_t stream, wc_stats *stats, int rounds, bool fail_on_overflow,
+                   bool bounded_waits = false);
 
 // Copies `bytes` from host memory to device memory `dst` on `stream` through
 // the context's pinned staging buffer (waits for the previous staged copy).
 wc_status stage_to_device(wc_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t stream);
 
-// Waits (bounded) until a kernel published the count of round `r` to the host ring.
+// Waits (bounded) until a kernel of the current call published the count of
+// round `r` to the host ring.
 inline void chain_break(wc_ctx *ctx) { ctx->chain_event = nullptr; }
 wc_status wait_round_count(wc_ctx *ctx, int r, int *count);
+// Clears the entry of round r before that round is launched: within one call
+// the ring is reused every kHostRing rounds.
 void clear_round_slot(wc_ctx *ctx, int r);
-// the same for one host-ring entry by index (0 <= index <= kHostSlotGraph)
+// the same for one host-ring entry by index (0 <= index < kHostSlots)
 wc_status wait_host_slot(wc_ctx *ctx, int index, int *value);
 void clear_host_slot(wc_ctx *ctx, int index);
 

@@ -54,7 +54,7 @@ struct SsspArgs {
     int n;
     int threshold;
     int chunk;
-    int *host_ring;
+    unsigned long long *host_ring;
     DevStats *stats;
     int want_stats;
 };
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
     const int act = a.active[(r % 3) * kPad];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.active[((r + 2) % 3) * kPad] = 0;
-        store_system(&a.host_ring[r % kHostRing], act);
+        publish_host(a.host_ring, r % kHostRing, a.stats, act);
     }
     if (!act) return;
     const int next = r + 1;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.active[((r + 2) % 3) * kPad] = 0;
         a.chunk_tail[((r + 1) % 3) * kPad] = 0;
-        store_system(&a.host_ring[r % kHostRing], act);
+        publish_host(a.host_ring, r % kHostRing, a.stats, act);
     }
     if (!act) return;
     const int next = r + 1;
@@ -560,8 +560,6 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     int resident = resident_blocks(ctx, ks.round, block);
     wc_status st = resolve_tune(ctx, "sssp", mode, tune, resident, &cfg);
     if (st != WC_OK) return st;
-    if (cfg.driver == 1)
-        return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
     if ((cfg.driver == 2 || cfg.driver == 3) && mode != WC_GRID)
         return fail(WC_EINVAL, "drivers 2 and 3 are comparison variants of grid mode only");
     if (cfg.block != block) {

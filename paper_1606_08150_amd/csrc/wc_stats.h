@@ -46,4 +46,13 @@ __device__ __forceinline__ void stat_flush(DevStats *s, const StatAcc &acc)
     }
 }
 
+// Publishes `value` to entry `index` of the context's host ring, tagged with
+// the current call's epoch (set in the counters by the call's first kernel).
+// One 64-bit system-scope store, so the host sees tag and value together.
+__device__ __forceinline__ void publish_host(unsigned long long *ring, int index, const DevStats *s, int value)
+{
+    const unsigned long long word = ((unsigned long long)s->epoch << 32) | (unsigned long long)(unsigned int)value;
+    __hip_atomic_store(&ring[index], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 }  // namespace wc

@@ -10,8 +10,7 @@
 //
 //   grid  - level-synchronous: the global buffer of level l holds chunks of
 //           the children ranges of every node found in level l-1; a grid-wide
-//           barrier (kernel boundary or the persistent grid's counter barrier)
-//           separates levels.  The post-work is consolidated too (Sec. IV.C,
+//           barrier (the kernel boundary) separates levels.  The post-work is consolidated too (Sec. IV.C,
 //           grid-level post-work): after the last level, one pass per level from
 //           the deepest up folds every chunk into its node with one atomic.
 //   flat  - the same level structure without consolidation: one thread per
@@ -63,11 +62,10 @@ struct TreeArgs {
     int *outstanding;
     int *pending;        // per-node children not yet finished
     int work_cap;        // flush a buffer once its nodes carry this many children
-    int *host_ring;
+    unsigned long long wait_ticks;  // bound of the packet queue's waits (100 MHz ticks)
+    unsigned long long *host_ring;
     DevStats *stats;
     int want_stats;
-    GridBarrier *bar;
-    int bar_blocks;
 };
 
 __device__ __forceinline__ int fanout(const TreeArgs &a, int v) { return a.child_ptr[v + 1] - a.child_ptr[v]; }
@@ -105,8 +103,6 @@ __global__ void tree_init_levels(TreeArgs a)
             }
             a.lvl_count[0] = nch;
         }
-        a.bar->count = a.bar_blocks;
-        a.bar->generation = 0;
     }
 }
 
@@ -118,8 +114,6 @@ __global__ void tree_init_levels_flat(TreeArgs a)
         a.lvl_count[0] = fanout(a, 0) > 0 ? 1 : 0;
         a.lvl_count[1] = 0;
         a.items[0] = make_int4(0, 0, 0, 0);
-        a.bar->count = a.bar_blocks;
-        a.bar->generation = 0;
     }
 }
 
@@ -271,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void tree_down(TreeArgs a, int l)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.lvl_start[l + 1] = start + count;
         a.lvl_count[l + 2] = 0;
-        store_system(&a.host_ring[l % kHostRing], count);
+        publish_host(a.host_ring, l % kHostRing, a.stats, count);
         if (a.want_stats && MODE == WC_GRID && count > 0) atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
     }
     if (count == 0) return;
@@ -298,42 +292,8 @@ __global__ void tree_publish_depth(TreeArgs a, int L)
                 d = l;
                 break;
             }
-        store_system(&a.host_ring[kHostSlotGraph], d);
+        publish_host(a.host_ring, kHostSlotGraph, a.stats, d);
     }
-}
-
-// Persistent driver of the level-synchronous modes: all levels, both
-// directions, one co-resident launch, grid barrier between levels.
-template <int MODE, int OP, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void tree_levels_persistent(TreeArgs a, int max_levels)
-{
-    const int nb = gridDim.x;
-    StatAcc acc;
-    int l = 0;
-    for (; l < max_levels; ++l) {
-        const int start = atomic_load_dev(&a.lvl_start[l]), count = atomic_load_dev(&a.lvl_count[l]);
-        if (count == 0) break;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.lvl_start[l + 1] = start + count;
-            a.lvl_count[l + 2] = 0;
-            if (a.want_stats && MODE == WC_GRID) atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
-        }
-        level_down<MODE, BLOCK>(a, l, start, count, acc);
-        if (!grid_barrier(a.bar, nb)) {
-            a.stats->timed_out = 1;
-            return;
-        }
-    }
-    const int levels = l;
-    for (l = levels - 1; l >= 0; --l) {
-        level_up<MODE, OP, BLOCK>(a, atomic_load_dev(&a.lvl_start[l]), atomic_load_dev(&a.lvl_count[l]));
-        if (!grid_barrier(a.bar, nb)) {
-            a.stats->timed_out = 1;
-            return;
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.stats->rounds = levels;
-    if (a.want_stats) stat_flush(a.stats, acc);
 }
 
 // ---------------------------------------------------------------- packet queue (wave, block)
@@ -482,7 +442,7 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
         // its packet is published later or, once no packet is outstanding, never
         if (t == 0) {
             const int h = atomic_add_dev(a.pq_head, 1);
-            const unsigned long long deadline = wait_deadline();
+            const unsigned long long deadline = wait_deadline(a.wait_ticks);
             long long pk = -1;
             int got = -1;
             // polls are relaxed loads (an acquire load invalidates the L2 each
@@ -630,21 +590,19 @@ __global__ void tree_zero_out(TreeArgs a)
 
 template <int OP, int BLOCK>
 struct TreeKernels {
-    const void *down, *up, *persistent, *queue;
+    const void *down, *up, *queue;
 };
 
 template <int OP, int BLOCK>
 TreeKernels<OP, BLOCK> kernels_for(wc_mode mode)
 {
-    TreeKernels<OP, BLOCK> k{nullptr, nullptr, nullptr, nullptr};
+    TreeKernels<OP, BLOCK> k{nullptr, nullptr, nullptr};
     if (mode == WC_GRID) {
         k.down = reinterpret_cast<const void *>(&tree_down<WC_GRID, BLOCK>);
         k.up = reinterpret_cast<const void *>(&tree_up<WC_GRID, OP, BLOCK>);
-        k.persistent = reinterpret_cast<const void *>(&tree_levels_persistent<WC_GRID, OP, BLOCK>);
     } else if (mode == WC_FLAT) {
         k.down = reinterpret_cast<const void *>(&tree_down<WC_FLAT, BLOCK>);
         k.up = reinterpret_cast<const void *>(&tree_up<WC_FLAT, OP, BLOCK>);
-        k.persistent = reinterpret_cast<const void *>(&tree_levels_persistent<WC_FLAT, OP, BLOCK>);
     } else if (mode == WC_WAVE) {
         k.queue = reinterpret_cast<const void *>(&tree_queue<OP, kWave, BLOCK>);
     } else {
@@ -659,7 +617,7 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
 {
     TreeKernels<OP, BLOCK> ks = kernels_for<OP, BLOCK>(mode);
     // the grid is sized to the residency of the kernel that runs: the queue kernel, or the level kernels
-    const void *main_kernel = ks.queue ? ks.queue : (cfg.driver == 1 ? ks.persistent : ks.down);
+    const void *main_kernel = ks.queue ? ks.queue : ks.down;
     const int resident = resident_blocks(ctx, main_kernel, BLOCK);
     const int grid = std::max(1, std::min(cfg.grid, resident));
     const long long n = t->n;
@@ -675,10 +633,9 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
     a.host_ring = ctx->host_ring_dev;
     a.stats = ctx->dstats;
     a.want_stats = stats != nullptr;
-    a.bar_blocks = grid;
+    a.wait_ticks = ctx->wait_ticks;
     a.work_cap = BLOCK * cfg.items_per_lane;
     if (cfg.driver == 2) {
-        if (mode != WC_GRID) return fail(WC_EINVAL, "tree: driver 2 needs grid mode");
         // Basic dynamic parallelism, emulated: the host walks the tree (read back
         // once) and launches one child kernel per internal node, deepest first.
         std::vector<int> cp((size_t)n + 1), ch((size_t)std::max<long long>(n - 1, 1));
@@ -723,7 +680,7 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
     if (queue_mode) {
         a.work_cap = (mode == WC_WAVE ? kWave : BLOCK) * cfg.items_per_lane;
         long long pq_cap = n;
-        size_t need = padded(n * 4) * 2 + padded(pq_cap * 8) + 4 * padded(4) + padded(sizeof(GridBarrier));
+        size_t need = padded(n * 4) * 2 + padded(pq_cap * 8) + 4 * padded(4);
         wc_status st = pool_reserve(ctx, need, stream);
         if (st != WC_OK) return st;
         a.nl = pool_take<int>(ctx, n);
@@ -734,7 +691,6 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
         a.pq_head = pool_take<int>(ctx, 1);
         a.pq_tail = pool_take<int>(ctx, 1);
         a.outstanding = pool_take<int>(ctx, 1);
-        a.bar = pool_take<GridBarrier>(ctx, 1);
         st = begin_call(ctx, stream, stats);
         if (st != WC_OK) return st;
         int ig = (int)std::min<long long>((pq_cap + 255) / 256, 4096);
@@ -749,21 +705,21 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
             st = launch(ctx, mode == WC_WAVE ? "tree_queue_wave" : "tree_queue_block", ks.queue, dim3(grid),
                         dim3(BLOCK), args, stream);
         if (st != WC_OK) return st;
-        return end_call(ctx, stream, stats, 0, cfg.fail_on_overflow);
+        // the queue's waits are bounded: a wave that gave up is reported
+        return end_call(ctx, stream, stats, 0, cfg.fail_on_overflow, true);
     }
     // level-synchronous: levels <= n; chunks over all levels <= n + (n-1)/chunk + 1
     // (the relaunch driver may run up to `window` empty levels past the last one)
     const long long max_levels = n + 1;
     const long long lvl_len = max_levels + 16;
     long long cap = mode == WC_GRID ? n + n / chunk + 2 : n + 1;
-    size_t need = 2 * padded(lvl_len * 4) + padded(cap * 16) + padded(sizeof(GridBarrier));
+    size_t need = 2 * padded(lvl_len * 4) + padded(cap * 16);
     wc_status st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     a.lvl_start = pool_take<int>(ctx, lvl_len);
     a.lvl_count = pool_take<int>(ctx, lvl_len);
     a.items = pool_take<int4>(ctx, cap);
     a.item_cap = cap;
-    a.bar = pool_take<GridBarrier>(ctx, 1);
     st = begin_call(ctx, stream, stats);
     if (st != WC_OK) return st;
     {
@@ -774,8 +730,6 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
                     dim3(1), dim3(64), args, stream);
         if (st != WC_OK) return st;
     }
-    if (cfg.driver == 1)
-        return fail(WC_EINVAL, "the persistent driver (driver = 1) is disabled: use the relaunch driver");
     // A call repeated on the same tree replays a captured graph of all levels
     // (down to the recorded depth plus one empty level, then up); the empty
     // level publishes its count, and a non-zero count (a deeper tree at the same
@@ -907,6 +861,8 @@ wc_status tree_entry(int op, wc_ctx *ctx, const wc_tree *t, int32_t *out, wc_mod
     Config cfg;
     wc_status st = resolve_tune(ctx, "tree", mode, tune, ctx->num_cus * 8, &cfg);
     if (st != WC_OK) return st;
+    // refusals come before anything is enqueued
+    if (cfg.driver == 2 && mode != WC_GRID) return fail(WC_EINVAL, "tree: driver 2 needs grid mode");
     if (tune && tune->grid_blocks > 0) cfg.grid = tune->grid_blocks;
     else cfg.grid = 1 << 30;  // clamp to the resident count of the chosen kernel
     return op == OP_DESC ? run_tree_block<OP_DESC>(ctx, t, out, mode, cfg, stream, stats)

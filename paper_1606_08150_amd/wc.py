@@ -24,7 +24,7 @@ STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: 
 EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_pagerank", "wc_color", "wc_tree_descendants",
            "wc_tree_height",
            "wc_sssp_batch",
-           "wc_ctx_set_timing", "wc_ctx_kernel_stats", "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size",
+           "wc_ctx_set_timing", "wc_ctx_set_wait_limit", "wc_ctx_kernel_stats", "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size",
            "wc_kc_config", "wc_default_tune")
 
 
@@ -100,6 +100,8 @@ def load_library():
                                   c.POINTER(c.c_int), c.POINTER(Tune), c.c_int32, vp, c.POINTER(Stats)]
     lib.wc_ctx_set_timing.restype = c.c_int
     lib.wc_ctx_set_timing.argtypes = [vp, c.c_int]
+    lib.wc_ctx_set_wait_limit.restype = c.c_int
+    lib.wc_ctx_set_wait_limit.argtypes = [vp, c.c_int64]
     lib.wc_ctx_kernel_stats.restype = c.c_int
     lib.wc_ctx_kernel_stats.argtypes = [vp, c.c_int32, c.POINTER(c.c_char_p), c.POINTER(c.c_int64),
                                         c.POINTER(c.c_double), c.POINTER(c.c_double)]
@@ -227,6 +229,10 @@ class Context:
     # -- per-kernel timing --
     def set_timing(self, enable: bool):
         _check(load_library().wc_ctx_set_timing(self._ptr, 1 if enable else 0))
+
+    def set_wait_limit(self, microseconds: int):
+        """Bound of the device-side waits of later calls (<= 0: the default 2 s)."""
+        _check(load_library().wc_ctx_set_wait_limit(self._ptr, int(microseconds)))
 
     def kernel_times(self) -> dict:
         """{kernel name: (launches, total_ms, max_ms)} for the launches recorded

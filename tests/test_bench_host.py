@@ -22,11 +22,14 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 def test_algorithmic_bytes_models():
     info = {"sssp_edges_buffered": 1000, "sssp_updates_buffered": 10, "sssp_calls": 3, "sssp_edges": 1200,
-            "sssp_updates": 15, "n": 50, "sssp_rounds": 4, "nnz_heavy": 700, "rows_heavy": 7, "nnz_light": 300}
+            "sssp_updates": 15, "n": 50, "sssp_rounds": 4, "nnz_heavy": 700, "rows_heavy": 7, "nnz_light": 300,
+            "reached_edges_heavy": 900, "reached_heavy": 20, "reached_edges_light": 150, "reached_light": 30}
     b, _ = bench.algorithmic_bytes("sssp_drain", info, 6)
-    assert b == (12 * 1000 + 8 * 10) * 3 / 6
+    assert b == (16 * 900 + 20 * 20) * 3 / 6  # each reachable edge once, however often it is relaxed
     b, _ = bench.algorithmic_bytes("sssp_round_grid", info, 12)
-    assert b == (12 * 200 + 8 * 5 + 4 * 50 * 4) * 3 / 12
+    assert b == (16 * 150 + 20 * 30) * 3 / 12
+    more = dict(info, sssp_edges_buffered=5000)  # redundant relaxations add no useful bytes
+    assert bench.algorithmic_bytes("sssp_drain", more, 6)[0] == (16 * 900 + 20 * 20) * 3 / 6
     assert bench.algorithmic_bytes("spmv_drain", info, 1)[0] == 12 * 700 + 4 * 7
     assert bench.algorithmic_bytes("spmv_parent_grid", info, 1)[0] == 12 * 300 + 8 * 50
     assert bench.algorithmic_bytes("something_else", info, 1) is None

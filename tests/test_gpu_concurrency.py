@@ -12,6 +12,7 @@ import oracle
 import synth
 from gpu_util import dev_to_u32, say, u32_to_dev
 from paper_1606_08150_amd import wc
+from tolerance import pagerank_rtol
 
 pytestmark = pytest.mark.gpu
 
@@ -69,8 +70,9 @@ def test_coloring_and_pagerank_concurrently(c1_graph):
     torch.cuda.synchronize()
     for c in out["color"]:
         assert np.array_equal(c, ref_c)
+    rtol = max(pagerank_rtol(20, np.diff(tg.row_ptr), mode, tg.n) for mode in ("grid", "flat"))
     for r in out["rank"]:
-        assert oracle.pagerank_check(ref_r, r) == (0, -1)
+        assert oracle.pagerank_check(ref_r, r, rtol) == (0, -1)
     ctx_a.close()
     ctx_b.close()
 

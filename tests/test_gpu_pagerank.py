@@ -1,6 +1,7 @@
-"""GPU parity of wc_pagerank against the binary64 oracle (relative bound
-oracle.PAGERANK_RTOL per vertex), every mode and tune, bit-identical repeats,
-special graphs, argument errors, and the scale-22 graph."""
+"""GPU parity of wc_pagerank against the binary64 oracle, every mode and tune,
+bit-identical repeats, special graphs, argument errors, and the scale-22 graph.
+The relative bound per vertex is derived for each mode, tune and number of
+sweeps from the rounding depth of the kernels' sums (tests/tolerance.py)."""
 import numpy as np
 import pytest
 import torch
@@ -9,6 +10,7 @@ import oracle
 import synth
 from gpu_util import say
 from paper_1606_08150_amd import wc
+from tolerance import pagerank_rtol
 
 pytestmark = pytest.mark.gpu
 MODES = ["flat", "wave", "block", "grid"]
@@ -21,6 +23,11 @@ def upload(g):
 
 def reference(g, t, iters, d=0.85):
     return oracle.pagerank_f64(t.row_ptr, t.col, synth.out_degree(g), iters, d)
+
+
+def bound(t, iters, mode, **tune):
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return pagerank_rtol(iters, np.diff(t.row_ptr), mode, t.n, num_cus=cus, **tune)
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +45,7 @@ def test_scale12_all_modes(ctx, c1_pr, mode):
         r = ctx.pagerank(dg, od, k, mode=mode)
         torch.cuda.synchronize()
         got = r.cpu().numpy()
-        assert oracle.pagerank_check(ref, got) == (0, -1), k
+        assert oracle.pagerank_check(ref, got, bound(t, k, mode)) == (0, -1), k
         assert abs(float(got.astype(np.float64).sum()) - 1.0) < 1e-4
 
 
@@ -50,7 +57,7 @@ def test_tune_sweep_and_repeats(ctx, c1_pr, mode, tune):
     g, dg, od, t, refs = c1_pr
     tt = wc.make_tune(**tune)
     first = ctx.pagerank(dg, od, 10, mode=mode, tune=tt).cpu().numpy()
-    assert oracle.pagerank_check(refs[10], first) == (0, -1)
+    assert oracle.pagerank_check(refs[10], first, bound(t, 10, mode, **tune)) == (0, -1)
     for _ in range(3):
         again = ctx.pagerank(dg, od, 10, mode=mode, tune=tt).cpu().numpy()
         assert np.array_equal(again.view(np.uint32), first.view(np.uint32))
@@ -74,7 +81,7 @@ def test_special_graphs(ctx, mode):
         for k in (0, 3, 20):
             ref = reference(g, t, k)
             got = ctx.pagerank(dg, od, k, mode=mode).cpu().numpy()
-            assert oracle.pagerank_check(ref, got) == (0, -1), (name, k)
+            assert oracle.pagerank_check(ref, got, bound(t, k, mode)) == (0, -1), (name, k)
 
 
 def test_invalid_arguments(ctx, c1_pr):
@@ -103,13 +110,19 @@ def c2_pr():
     say("generating scale-22 graph for PageRank")
     g = synth.rmat_csr(22, 1 << 26)
     dg, od, t = upload(g)
-    say("oracle PageRank at scale 22 (10 sweeps)")
-    return g, dg, od, reference(g, t, 10)
+    say("oracle PageRank at scale 22 (1 and 10 sweeps)")
+    return g, dg, od, t, {k: reference(g, t, k) for k in (1, 10)}
 
 
 @pytest.mark.parametrize("mode", MODES)
-def test_scale22(ctx, c2_pr, mode):
-    g, dg, od, ref = c2_pr
-    say(f"pagerank scale 22 mode={mode}")
-    got = ctx.pagerank(dg, od, 10, mode=mode).cpu().numpy()
-    assert oracle.pagerank_check(ref, got) == (0, -1)
+@pytest.mark.parametrize("iters", [1, 10])
+def test_scale22(ctx, c2_pr, mode, iters):
+    """One sweep shows the first sums' rounding undamped (the hub's 159,737
+    in-edges); ten sweeps the accumulated error.  Both against the bound derived
+    for the mode."""
+    g, dg, od, t, refs = c2_pr
+    say(f"pagerank scale 22 mode={mode} iterations={iters}")
+    got = ctx.pagerank(dg, od, iters, mode=mode).cpu().numpy()
+    rtol = bound(t, iters, mode)
+    assert rtol < (1e-5 if iters == 1 else 1e-4)
+    assert oracle.pagerank_check(refs[iters], got, rtol) == (0, -1)
