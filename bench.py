@@ -48,8 +48,9 @@ def parse():
     p.add_argument("--batch-reps", type=int, default=10)
     p.add_argument("--no-trees", action="store_true", help="skip the tree descendants / heights section")
     p.add_argument("--no-serve", action="store_true", help="skip the continuous-batching serving section")
-    p.add_argument("--serve-requests", type=int, default=4000, help="requests per arrival rate")
+    p.add_argument("--serve-requests", type=int, default=10000, help="requests per arrival rate")
     p.add_argument("--no-gather-ceiling", action="store_true", help="skip the bare-gather reference timing")
+    p.add_argument("--no-spmv-hot", action="store_true", help="skip the hot-column SpMV layout timings")
     p.add_argument("--no-cold", action="store_true", help="skip the cold-cache (L2 and MALL flushed) timings")
     p.add_argument("--no-pagerank", action="store_true", help="skip the PageRank section")
     p.add_argument("--no-coloring", action="store_true", help="skip the graph coloring section")
@@ -58,6 +59,9 @@ def parse():
                    help="skip the comparison of the default configuration with exhaustive search")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
+    p.add_argument("--counter-run", default=None, choices=["flat", "wave", "block", "grid"],
+                   help="only run SSSP, SpMV and tree descendants in this mode, 3 calls each (for rocprofv3 "
+                        "counter passes per mode), then exit")
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
                    help="first run a plain device-to-device copy of this many MiB three times (a known-size "
                         "kernel for scaling hardware byte counters)")
@@ -255,6 +259,66 @@ def summarize_counters(sq_dir, tcc_dir, workload, command, out_name,
     return tot
 
 
+MODE_PROBLEMS = (("sssp", "sssp_"), ("spmv", "spmv_"), ("tree", "tree_"))
+
+
+def summarize_mode_counters(runs, workload, command, out_name, fetch_scale=2.0):
+    """profiles/<out_name>.md: the per-mode comparison of Figs. 8-10 (Sec. V.D)
+    from rocprofv3 --pmc passes of `bench.py --counter-run MODE`, one process
+    per mode and pass: `runs` maps mode -> output directories.  Per mode and
+    problem, over that problem's kernels: VALU lane utilization (the analogue of
+    warp execution efficiency: active lanes per VALU instruction / 64), mean
+    waves per CU weighted by dispatch length (the occupancy analogue), and
+    HBM-side bytes (FETCH_SIZE scaled by the copy calibration, plus WRITE_SIZE)
+    per call."""
+    import csv
+    disp = {}
+    for mode, dirs in runs.items():
+        for d in dirs:
+            with open(os.path.join(d, "run_counter_collection.csv")) as f:
+                for r in csv.DictReader(f):
+                    k = _short_kernel(r["Kernel_Name"])
+                    prob = next((p for p, prefix in MODE_PROBLEMS if k.startswith(prefix)), None)
+                    if prob is None:
+                        continue
+                    e = disp.setdefault((mode, prob, d, r["Dispatch_Id"]), {})
+                    c = r["Counter_Name"]
+                    e[c] = e.get(c, 0.0) + float(r["Counter_Value"])
+    rows = {}
+    for (mode, prob, _, _), e in disp.items():
+        t = rows.setdefault((mode, prob), {"occ_w": 0.0, "gui": 0.0})
+        for c, v in e.items():
+            t[c] = t.get(c, 0.0) + v
+        if "MeanOccupancyPerCU" in e and "GRBM_GUI_ACTIVE" in e:
+            t["occ_w"] += e["MeanOccupancyPerCU"] * e["GRBM_GUI_ACTIVE"]
+            t["gui"] += e["GRBM_GUI_ACTIVE"]
+    lines = [f"# Counters per consolidation mode: {workload}", "",
+             "Commands (one process per mode and counter pass):", "", "```", command, "```", "",
+             "Over every kernel of the problem in the run (3 calls each). VALU lane utilization = "
+             "SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU), the analogue of warp execution efficiency "
+             "(Fig. 8); waves per CU = MeanOccupancyPerCU weighted by each dispatch's GRBM_GUI_ACTIVE cycles, "
+             "the occupancy analogue (Fig. 9); HBM-side bytes = "
+             f"{fetch_scale:g} x FETCH_SIZE + WRITE_SIZE (KiB counters, copy-calibrated) per call, the analogue "
+             "of DRAM transactions (Fig. 10).", "",
+             "| problem | mode | VALU insts per call | VALU lane utilization | waves per CU | HBM-side MB per call |",
+             "|---|---|---|---|---|---|"]
+    for prob, _ in MODE_PROBLEMS:
+        for mode in ("flat", "wave", "block", "grid"):
+            t = rows.get((mode, prob))
+            if not t:
+                continue
+            act = t.get("SQ_ACTIVE_INST_VALU", 0.0)
+            util = t.get("SQ_THREAD_CYCLES_VALU", 0.0) / (64.0 * act) if act else float("nan")
+            occ = t["occ_w"] / t["gui"] if t["gui"] else float("nan")
+            mb = (fetch_scale * t.get("FETCH_SIZE", 0.0) + t.get("WRITE_SIZE", 0.0)) * 1024 / 3 / 1e6
+            lines.append(f"| {prob} | {mode} | {t.get('SQ_INSTS_VALU', 0.0) / 3:.3g} | {util:.3f} | {occ:.1f} | "
+                         f"{mb:.1f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return rows
+
+
 def summarize_profiles(fetch_dir, write_dir, copy_mb, workload, command):
     """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; csv output) of
     `command` into profiles/<kernel>_<workload>_pmc.json files: KiB per dispatch
@@ -361,7 +425,8 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
     vertex, SpMV with one per heavy row and tree descendants with one per
     internal node (tune driver 2, no consolidation) beside flat and the three
     consolidation levels, on smaller inputs (the per-item launches make the
-    basic variant slow)."""
+    basic variant slow); and the allocator comparison (Fig. 5): SSSP's wave and
+    block buffers in registers / LDS, in pool slices or from device malloc."""
     out = {}
     for scale in scales:
         g = synth.rmat_csr(scale, 16 << scale)
@@ -386,6 +451,26 @@ def run_ablation(ctx, torch, synth, wc, stream, scales=(12, 16), reps=3):
             row[name]["speedup_vs_basic_dp"] = round(row["basic_dp"]["ms"] / row[name]["ms"], 1)
         out[f"rmat{scale}"] = row
         print(f"[bench] ablation scale {scale}: {row}", file=sys.stderr, flush=True)
+        # allocator comparison (Sec. V.A, Fig. 5): the wave's / block's buffer in
+        # registers / LDS, in a pool slice, or from device-side malloc per dispatch
+        arow = {}
+        for mode in ("wave", "block"):
+            arow[mode] = {}
+            for name, alloc in (("registers_lds", 0), ("pool", 1), ("device_malloc", 2)):
+                tune = wc.make_tune(buffer_alloc=alloc)
+                _, st = ctx.sssp(dg, dw, 0, mode=mode, tune=tune, out=dist, stats=True)
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(reps):
+                    ctx.sssp(dg, dw, 0, mode=mode, tune=tune, out=dist)
+                b.record(stream)
+                torch.cuda.synchronize()
+                arow[mode][name] = {"ms": round(a.elapsed_time(b) / reps, 3), "fallback": bool(st["overflowed"])}
+            arow[mode]["malloc_over_pool"] = round(arow[mode]["device_malloc"]["ms"] / arow[mode]["pool"]["ms"], 2)
+            arow[mode]["basic_dp_over_pool"] = round(row["basic_dp"]["ms"] / arow[mode]["pool"]["ms"], 1)
+        out[f"alloc_rmat{scale}"] = arow
+        print(f"[bench] allocator comparison scale {scale}: {arow}", file=sys.stderr, flush=True)
         # SpMV on the same matrix: one child launch per heavy row (driver 2)
         val = torch.from_numpy(synth.values(g.m)).cuda()
         x = torch.from_numpy(synth.vector_x(g.n)).cuda()
@@ -528,7 +613,41 @@ def run_trees(ctx, torch, synth, wc, stream, n=1 << 22, reps=5):
         for mode, row in res.items():
             print(f"[bench] tree {name} {mode}: {row}", file=sys.stderr, flush=True)
         del t
+    out["batch"] = run_tree_batch(ctx, torch, synth, wc, stream, reps)
     return out
+
+
+def run_tree_batch(ctx, torch, synth, wc, stream, reps=5, count=64):
+    """Batched trees: 64 random trees of 2^10..2^18 nodes in one call
+    (wc_tree_descendants_batch / wc_tree_height_batch, grid and flat modes)
+    against the same trees one call each."""
+    trees = synth.batch_trees(count, 10.0, 18.0, seed=17)
+    dts = [wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child) for t in trees]
+    outs = [torch.empty(t.n, dtype=torch.int32, device="cuda") for t in trees]
+    nodes = sum(t.n for t in trees)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {}
+    for mode in ("flat", "grid"):
+        for what, bfn, sfn in (("desc", ctx.tree_descendants_batch, ctx.tree_descendants),
+                               ("height", ctx.tree_height_batch, ctx.tree_height)):
+            one = timed(lambda: bfn(dts, mode=mode, outs=outs))
+            each = timed(lambda: [sfn(d, mode=mode, out=o) for d, o in zip(dts, outs)])
+            res[f"{mode}_{what}"] = {"batch_ms": round(one, 4), "one_call_per_tree_ms": round(each, 4),
+                                     "speedup": round(each / one, 2),
+                                     "batch_gnodes_s": round(nodes / (one * 1e-3) / 1e9, 3)}
+            print(f"[bench] tree batch {mode} {what}: {res[f'{mode}_{what}']}", file=sys.stderr, flush=True)
+    return {"workload": f"{count} random trees of 2^10..2^18 nodes ({nodes} nodes in total)", "modes": res}
 
 
 def run_batch(args, ctx, torch, synth, wc):
@@ -617,7 +736,9 @@ def run_serving(args, torch, synth, wc):
             reqs = serve.poisson_requests(args.serve_requests, rate, srcs, n_x=4, seed=int(rate))
             out = srv.run(reqs, time_limit=300)
             edges = sum(reached(r.graph, r.arg) for r in out if r.kind == serve.SSSP)
-            row = {"rate_rps": rate, **serve.summarize(out, edges)}
+            row = {"rate_rps": rate, **serve.summarize(out, edges), "pool_growths": srv.grows,
+                   "pool_growth_bytes": srv.admission.pool_growth, "peak_used_bytes": srv.admission.peak_used,
+                   "budget_bytes": srv.admission.budget}
             rows.append(row)
             print(f"[bench] serving {row}", file=sys.stderr, flush=True)
     finally:
@@ -625,7 +746,11 @@ def run_serving(args, torch, synth, wc):
         ctx.close()
     return {"workload": "Poisson arrivals, 50% SSSP (random source with out-edges) / 50% SpMV (4 resident x "
                         "per graph), 64 resident R-MAT graphs of 2^14..2^20 vertices, degree 16",
-            "workers": args.serve_workers, "graphs_vertices": sum(sizes), "rates": rows}
+            "workers": args.serve_workers, "graphs_vertices": sum(sizes), "requests_per_rate": args.serve_requests,
+            "admission": "outputs by exact tensor bytes; batch workspace from the library's plan-only mode "
+                         "against each worker's pool; pool growth charged to the budget (half the free memory "
+                         "measured after the workers' contexts exist)",
+            "rates": rows}
 
 
 def main():
@@ -642,6 +767,20 @@ def main():
         a = sp.parse_args()
         summarize_counters(a.sq_dir, a.tcc_dir, a.workload, a.command, a.out_name, cyc_dir=a.cyc_dir,
                            cyc_command=a.cyc_command)
+        return
+    if "--summarize-mode-counters" in sys.argv:
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--summarize-mode-counters", action="store_true")
+        sp.add_argument("--run", action="append", required=True, help="MODE=DIR (repeatable)")
+        sp.add_argument("--workload", default="rmat22")
+        sp.add_argument("--command", required=True)
+        sp.add_argument("--out-name", required=True)
+        a = sp.parse_args()
+        runs = {}
+        for item in a.run:
+            mode, d = item.split("=", 1)
+            runs.setdefault(mode, []).append(d)
+        summarize_mode_counters(runs, a.workload, a.command, a.out_name)
         return
     if "--summarize-profiles" in sys.argv:
         sp = argparse.ArgumentParser()
@@ -697,6 +836,26 @@ def main():
     dw = torch.from_numpy(w.view(np.int32)).cuda()
     dval, dx = torch.from_numpy(val).cuda(), torch.from_numpy(x).cuda()
     dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    if args.counter_run:
+        # counter passes per mode: SSSP, SpMV and tree descendants, 3 calls each
+        t = synth.random_tree(1 << 22)
+        dt = wc.DeviceTree.from_host(t.parent, t.child_ptr, t.child)
+        out_t = torch.empty(t.n, dtype=torch.int32, device="cuda")
+        y = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        mode = args.counter_run
+        times = {}
+        for name, fn in (("sssp", lambda: ctx.sssp(dg, dw, 0, mode=mode, out=dist)),
+                         ("spmv", lambda: ctx.spmv(dg, dval, dx, mode=mode, out=y)),
+                         ("tree", lambda: ctx.tree_descendants(dt, mode=mode, out=out_t))):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            times[name] = round((time.perf_counter() - t1) / 3 * 1e3, 3)
+        print(json.dumps({"counter_run": mode, "ms_per_call": times}), flush=True)
+        ctx.close()
+        return
     y = torch.empty(g.n, dtype=torch.float32, device="cuda")
     deg = torch.from_numpy(np.diff(g.row_ptr).astype(np.int64)).cuda()
     stream = torch.cuda.current_stream()
@@ -850,6 +1009,37 @@ def main():
         del col64, gout
         print(f"[bench] gather ceiling: {gather_ceiling}", file=sys.stderr, flush=True)
 
+    # ---- the hot-column layout (wc_spmv_prepare once, then wc_spmv_hot per
+    # product, its gather of the hot x values included): grid mode, bit-identical
+    # to wc_spmv; untimed for `value`
+    spmv_hot = None
+    if not args.no_spmv_hot:
+        y_hot = torch.empty(g.n, dtype=torch.float32, device="cuda")
+        spmv_hot = {"what": "wc_spmv_hot in grid mode after wc_spmv_prepare (columns ranked by use; the hot "
+                            "x values gathered per product, the most used staged in LDS by the drain)",
+                    "by_hot": {}}
+        for hot in (16384, 65536, 262144):
+            t1 = time.perf_counter()
+            a_hot, ids = ctx.spmv_prepare(dg, hot)
+            prep_s = time.perf_counter() - t1
+            ctx.spmv_hot(a_hot, ids, dval, dx, mode="grid", out=y_hot)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(10):
+                ctx.spmv_hot(a_hot, ids, dval, dx, mode="grid", out=y_hot)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / 10
+            spmv_hot["by_hot"][str(hot)] = {"ms": round(ms, 4), "alg_gbs": round(spmv_bytes / (ms * 1e-3) / 1e9, 1),
+                                            "frac_hbm": round(spmv_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                            "prepare_s": round(prep_s, 3)}
+            del a_hot, ids
+        best = min(spmv_hot["by_hot"].items(), key=lambda kv: kv[1]["ms"])
+        spmv_hot["best_hot"] = int(best[0])
+        spmv_hot["speedup_vs_wc_spmv"] = round(spmv_avg / best[1]["ms"], 3)
+        print(f"[bench] spmv hot-column layout: {spmv_hot}", file=sys.stderr, flush=True)
+
     # ---- flat / wave / block / grid side by side (mean of 3 calls after 1 warm-up)
     modes = {}
     if not args.no_modes:
@@ -923,10 +1113,18 @@ def main():
                "cores": 1, "kind": "oracle",
                "sample": f"binary-heap Dijkstra from vertex 0 on the full scale-{scale} graph, {reps} runs "
                          f"(mean {dt:.2f} s each)"}
-        # context: the oracle's fp64 SpMV on the same matrix (one core) and the host
+        # context: the oracle's fp64 SpMV on the same matrix, one core and all
+        # host threads (row blocks side by side), and the host
         t1 = time.perf_counter()
         oracle.spmv_f64(g.row_ptr, g.col, val, x)
         cpu["spmv_f64_s"] = round(time.perf_counter() - t1, 3)
+        threads = min(os.cpu_count() or 1, 16)
+        oracle.spmv_f64_threads(g.row_ptr, g.col, val, x, threads)
+        t1 = time.perf_counter()
+        for _ in range(3):
+            oracle.spmv_f64_threads(g.row_ptr, g.col, val, x, threads)
+        cpu["spmv_f64_all_threads_s"] = round((time.perf_counter() - t1) / 3, 4)
+        cpu["spmv_f64_threads"] = threads
         cpu["host_cpu"] = host_cpu_model()
         cpu["host_threads"] = os.cpu_count()
 
@@ -953,6 +1151,7 @@ def main():
         "roofline": roofline,
         "spmv_roofline": spmv_roofline,
         "gather_ceiling": gather_ceiling,
+        "spmv_hot": spmv_hot,
         "cold_caches": cold,
         "sssp_work": {"edges_relaxed": sst["edges_processed"], "edges_by_consolidated_child": sst["edges_buffered"],
                       "relaxations_per_reachable_edge": round(sst["edges_processed"] / max(m_reached, 1), 4),

@@ -69,7 +69,9 @@ typedef enum {
     WC_ENOMEM = -2,    /* device pool could not be (re)allocated */
     WC_EOVERFLOW = -3, /* a consolidation buffer overflowed and tune->allow_fallback < 0 */
     WC_ETIMEOUT = -4,  /* a bounded device-side or host-side wait expired */
-    WC_EHIP = -5       /* a HIP runtime call failed */
+    WC_EHIP = -5,      /* a HIP runtime call failed */
+    WC_PLANNED = 1     /* plan-only context (wc_ctx_set_plan_only): the arguments were
+                          checked and the call's workspace recorded; nothing was enqueued */
 } wc_status;
 
 /* Directed graph / sparse matrix, CSR with row = source vertex.
@@ -122,6 +124,16 @@ typedef struct {
                                < 0 the call returns WC_EOVERFLOW after its work ends */
     int64_t buf_capacity;   /* grid/queue buffer capacity in entries; <= 0: large enough
                                that no overflow can occur */
+    int32_t buffer_alloc;   /* SSSP (and BFS) wave and block modes only, for the allocator
+                               comparison of Sec. V.A: where a group's consolidation buffer
+                               lives.  0 (default): registers / LDS (the child runs inside the
+                               group); 1: a global-memory slice of the context pool per
+                               workgroup (the paper's pre-allocated allocator, Sec. IV.E);
+                               2: a global-memory buffer from device-side malloc per
+                               dispatch, freed after the child (the default allocator).  A
+                               failed malloc keeps the items in registers / LDS and sets
+                               stats->overflowed.  Any other problem or mode: 0 only. */
+    int32_t reserved;       /* 0 */
 } wc_tune;
 
 /* Device-side counters of one call (filled when `stats` is non-NULL). */
@@ -161,9 +173,22 @@ wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, 
 /* Breadth-first levels (recursive BFS, the BFS-Rec benchmark of Sec. V): level[v]
  * = number of edges on a shortest path src -> v, UINT32_MAX if v is unreachable.
  * A visit of v is a recursive call whose children are the neighbours it brings
- * to a lower level; consolidation groups the calls of one depth (the frontier)
- * per `mode`, so this is wc_sssp with every edge weighing 1, on the same
- * kernels.  level[n] is written entirely. */
+ * to a lower level (parallel recursion, Sec. II.B).
+ *   WC_WAVE, WC_BLOCK: the recursion path.  The recursive calls a wave
+ *     (workgroup) makes go into its buffer; a full buffer is one consolidated
+ *     dispatch, a packet of a device-wide queue that any group of a persistent
+ *     grid processes (no grid-wide barrier).  The call of a vertex with more
+ *     than 64 * items_per_lane out-edges is split into packets of its own, so
+ *     a hub is spread over many groups.  Waits for packets are bounded
+ *     (WC_ETIMEOUT).  A call list too small (tune->buf_capacity entries; by
+ *     default twice the vertices plus edge chunks) raises stats->overflowed
+ *     and the levels are recomputed with the frontier rounds below
+ *     (WC_EOVERFLOW instead when tune->allow_fallback < 0).
+ *   WC_FLAT, WC_GRID: the calls of one depth (the frontier) are consolidated by
+ *     the frontier rounds of wc_sssp with every edge weighing 1, on the same
+ *     kernels.
+ * level[n] is written entirely.  tune->driver must be 0 in wave and block
+ * modes, and tune->buffer_alloc 0. */
 wc_status wc_bfs(wc_ctx *ctx, const wc_csr *g, int32_t src, uint32_t *level, wc_mode mode, const wc_tune *tune,
                  hipStream_t stream, wc_stats *stats);
 
@@ -173,6 +198,30 @@ wc_status wc_bfs(wc_ctx *ctx, const wc_csr *g, int32_t src, uint32_t *level, wc_
  * lane.  y[n] is written entirely; empty rows give +0. */
 wc_status wc_spmv(wc_ctx *ctx, const wc_csr *a, const float *val, const float *x, float *y, wc_mode mode,
                   const wc_tune *tune, hipStream_t stream, wc_stats *stats);
+
+/* Hot-column layout for repeated products with one matrix (a layout choice
+ * around the method, not part of it): the x gathers of SpMV go to random
+ * columns, and a power-law matrix's most used columns are spread over the
+ * whole of x.  wc_spmv_prepare ranks the columns by their number of entries
+ * (ties by column id), writes the `hot` most used column ids to hot_ids[hot]
+ * (device, most used first) and col_hot[m] (device): col_hot[e] = the rank of
+ * col[e] if it is one of the hot columns, else hot + col[e].  Rows, the order
+ * of entries and the values are unchanged.  Synchronous (the ranking runs on
+ * the host from device-computed counts).  WC_EINVAL for hot outside [0, n],
+ * n + hot >= 2^31 or NULL arrays. */
+wc_status wc_spmv_prepare(wc_ctx *ctx, const wc_csr *a, int32_t hot, int32_t *col_hot, int32_t *hot_ids,
+                          hipStream_t stream);
+
+/* y = A x with A in the hot-column layout (a_hot: the matrix's row_ptr with
+ * col_hot as col; hot and hot_ids from wc_spmv_prepare; val and x as for
+ * wc_spmv).  The product first gathers the hot columns' x values into a dense
+ * array; in grid mode each drain workgroup stages the most used of them in LDS
+ * (32 per thread, up to 16384).  Same kernels, mode semantics, tune and
+ * summation order as wc_spmv on the original matrix, so results are
+ * bit-identical to it. */
+wc_status wc_spmv_hot(wc_ctx *ctx, const wc_csr *a_hot, int32_t hot, const int32_t *hot_ids, const float *val,
+                      const float *x, float *y, wc_mode mode, const wc_tune *tune, hipStream_t stream,
+                      wc_stats *stats);
 
 /* PageRank (the PR benchmark of Sec. V, an irregular loop like SpMV): from
  * rank = 1/n, `iterations` synchronous sweeps of
@@ -221,6 +270,24 @@ wc_status wc_tree_descendants(wc_ctx *ctx, const wc_tree *t, int32_t *desc, wc_m
 wc_status wc_tree_height(wc_ctx *ctx, const wc_tree *t, int32_t *height, wc_mode mode, const wc_tune *tune,
                          hipStream_t stream, wc_stats *stats);
 
+/* Batched tree descendants / heights: `count` trees of any sizes in one
+ * sequence of level launches (a systems pattern around the method; each tree is
+ * the problem of wc_tree_descendants / wc_tree_height).  trees and desc /
+ * height are HOST arrays of `count` entries whose pointers are device arrays
+ * (desc[i] has trees[i].n entries and is written entirely; trees[i].parent is
+ * not read).  Flat or grid mode for the whole batch: every level kernel takes
+ * the items of that depth in all trees, so grid mode consolidates the recursive
+ * calls of all trees into one buffer per level (one child per level for the
+ * whole batch) and its post-work likewise.  A call repeated with the same
+ * trees, outputs, mode and tune replays a HIP graph of all its levels.
+ * Results equal the single-tree calls.  WC_EINVAL for wave or block mode, a
+ * tree without root, NULL arrays, more than 2^31 nodes in total, or
+ * tune->driver != 0. */
+wc_status wc_tree_descendants_batch(wc_ctx *ctx, int32_t count, const wc_tree *trees, int32_t *const *desc,
+                                    wc_mode mode, const wc_tune *tune, hipStream_t stream, wc_stats *stats);
+wc_status wc_tree_height_batch(wc_ctx *ctx, int32_t count, const wc_tree *trees, int32_t *const *height,
+                               wc_mode mode, const wc_tune *tune, hipStream_t stream, wc_stats *stats);
+
 /* Batched SSSP: `count` independent instances in one launch sequence
  * (a systems pattern around the method; each instance is the problem of wc_sssp).
  * graphs, w, src, dist are HOST arrays of `count` entries whose pointers are
@@ -257,6 +324,28 @@ wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable);
  * exits normally.  Meant for tests of the timeout path and for callers that
  * want a tighter bound.  WC_EINVAL for a NULL context. */
 wc_status wc_ctx_set_wait_limit(wc_ctx *ctx, int64_t microseconds);
+
+/* Plan-only mode, for callers that budget device memory before running (a
+ * serving loop admitting work by free memory): while enabled, every call on
+ * this context checks its arguments, records the pool bytes it would carve
+ * (its workspace: consolidation buffers, frontier and level arrays) and
+ * returns WC_PLANNED without enqueueing anything or touching the pool.
+ * Enabling or disabling resets the recorded maximum.  Calls that return
+ * WC_OK at once (empty inputs) need no workspace. */
+wc_status wc_ctx_set_plan_only(wc_ctx *ctx, int enable);
+
+/* Largest workspace (bytes) recorded by calls made in plan-only mode since it
+ * was last switched. */
+wc_status wc_ctx_planned_bytes(wc_ctx *ctx, size_t *bytes);
+
+/* Current pool size in bytes and the number of times the pool has grown
+ * (a call that needs more than the pool drains the device and regrows it). */
+wc_status wc_ctx_pool_info(wc_ctx *ctx, size_t *pool_bytes, int64_t *grows);
+
+/* Grows the pool to at least `bytes` now (waits for the device first; captured
+ * graphs of the context are dropped), so that later calls up to that size
+ * never grow it while other work runs.  No-op when the pool is large enough. */
+wc_status wc_ctx_reserve(wc_ctx *ctx, size_t bytes);
 
 /* Aggregate of the recorded launches of the index-th distinct kernel name (in
  * first-launch order): its name (a static string), launch count, total and

@@ -149,6 +149,31 @@ def spmv_f64(row_ptr, col, val, x):
     return y[:n], b[:n]
 
 
+def spmv_f64_threads(row_ptr, col, val, x, threads: int):
+    """spmv_f64 with the rows split into `threads` blocks of about equal nonzero
+    counts, each block computed by orc_spmv_f64 on its own host thread (the
+    arithmetic of every row is that of spmv_f64; only the rows run side by
+    side).  For timing the oracle on all host cores."""
+    import concurrent.futures as cf
+    n = len(row_ptr) - 1
+    rp = _i32(row_ptr)
+    c, v, xx = _nonempty(col, np.int32), _nonempty(val, np.float32), _nonempty(x, np.float32)
+    y = np.empty(max(n, 1), dtype=np.float64)
+    b = np.empty(max(n, 1), dtype=np.float64)
+    m = int(rp[n]) if n > 0 else 0
+    cuts = [0] + [int(np.searchsorted(rp, m * k // threads, side="left")) for k in range(1, threads)] + [n]
+    cuts = sorted(set(min(max(q, 0), n) for q in cuts))
+    lib = _load()
+
+    def block(lo, hi):
+        if hi > lo:
+            lib.orc_spmv_f64(hi - lo, rp[lo:hi + 1], c, v, xx, y[lo:hi], b[lo:hi])
+
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda p: block(*p), zip(cuts[:-1], cuts[1:])))
+    return y[:n], b[:n]
+
+
 SPMV_RTOL = 1e-5
 
 

@@ -15,10 +15,10 @@ import math
 
 # vertex-count buckets by floor(log2 n): [10,12), [12,14), [14,16), [16,19)
 BUCKET_EDGES = (12, 14, 16)
-MODES = ("wave", "block", "grid")
-THRESHOLDS = (8, 32)
-ITEMS_PER_LANE = (4, 8)
-BLOCKS = (256, 512)
+MODES = ("flat", "wave", "block", "grid")
+THRESHOLDS = (2, 4, 8, 16, 32, 64, 128)
+ITEMS_PER_LANE = (1, 2, 4, 8, 16)       # grid level: chunk sizes (64 x items per lane)
+BLOCKS = (128, 256, 512, 1024)
 
 
 def bucket_of(n: int) -> int:
@@ -31,12 +31,14 @@ def bucket_of(n: int) -> int:
 
 
 def candidates():
-    out = []
-    for mode in MODES:
+    """Every (mode, threshold, items per lane) of the search: flat once (no
+    threshold), wave and block per threshold, grid per threshold and chunk size
+    (the batch's wave and block levels keep every buffered item in the group,
+    so items per lane shapes only grid-level chunks)."""
+    out = [{"mode": "flat", "threshold": 0, "items_per_lane": 0}]
+    for mode in MODES[1:]:
         for thr in THRESHOLDS:
-            for ipl in ITEMS_PER_LANE:
-                if mode != "grid" and ipl != ITEMS_PER_LANE[0]:
-                    continue  # items_per_lane only shapes grid-level chunks
+            for ipl in (ITEMS_PER_LANE if mode == "grid" else (0,)):
                 out.append({"mode": mode, "threshold": thr, "items_per_lane": ipl})
     return out
 

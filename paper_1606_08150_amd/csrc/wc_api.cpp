@@ -54,8 +54,13 @@ static wc_status pool_alloc(wc_ctx *ctx, size_t bytes)
 
 wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream)
 {
+    if (ctx->plan_only) {
+        ctx->planned = std::max(ctx->planned, bytes);
+        return WC_PLANNED;
+    }
     ctx->pool_off = 0;
     if (bytes <= ctx->pool_bytes) return WC_OK;
+    ++ctx->pool_grows;
     // earlier calls may still be using the pool: drain before replacing it
     WC_HIP(hipStreamSynchronize(stream));
     WC_HIP(hipDeviceSynchronize());
@@ -74,15 +79,17 @@ wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream)
 
 void pool_reset(wc_ctx *ctx) { ctx->pool_off = 0; }
 
-int resident_blocks(wc_ctx *ctx, const void *kernel, int block)
+int resident_blocks_on(int num_cus, const void *kernel, int block)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1) {
         (void)hipGetLastError();
         per_cu = 1;
     }
-    return per_cu * ctx->num_cus;
+    return per_cu * num_cus;
 }
+
+int resident_blocks(wc_ctx *ctx, const void *kernel, int block) { return resident_blocks_on(ctx->num_cus, kernel, block); }
 
 static hipEvent_t take_event(wc_ctx *ctx)
 {
@@ -109,7 +116,7 @@ static void recycle_records(wc_ctx *ctx)
 wc_status launch(wc_ctx *ctx, const char *name, const void *kernel, dim3 grid, dim3 block, void **args,
                  hipStream_t stream)
 {
-    if (!ctx->timing) {
+    if (!ctx || !ctx->timing) {
         WC_HIP(hipLaunchKernel(kernel, grid, block, args, 0, stream));
         return WC_OK;
     }
@@ -156,6 +163,7 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
         if (tune->driver > 0) t.driver = tune->driver;
         t.allow_fallback = tune->allow_fallback;
         if (tune->buf_capacity > 0) t.buf_capacity = tune->buf_capacity;
+        t.buffer_alloc = tune->buffer_alloc;
     }
     int b = t.block_threads;
     if (b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
@@ -176,7 +184,12 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
     out->items_per_lane = t.items_per_lane;
     out->driver = t.driver;
     out->fail_on_overflow = t.allow_fallback < 0;
+    if (t.buffer_alloc < 0 || t.buffer_alloc > 2)
+        return fail(WC_EINVAL, "buffer_alloc must be 0 (registers / LDS), 1 (pool) or 2 (device malloc)");
+    if (t.buffer_alloc != 0 && strcmp(problem, "sssp"))
+        return fail(WC_EINVAL, "buffer_alloc exists for SSSP only");
     out->buf_capacity = t.buf_capacity;
+    out->buffer_alloc = t.buffer_alloc;
     return WC_OK;
 }
 
@@ -377,6 +390,8 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     out->driver = 0;
     out->allow_fallback = 0;
     out->buf_capacity = 0;
+    out->buffer_alloc = 0;
+    out->reserved = 0;
     return WC_OK;
 }
 
@@ -434,6 +449,48 @@ wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable)
     recycle_records(ctx);
     ctx->timing = enable ? 1 : 0;
     return WC_OK;
+}
+
+wc_status wc_ctx_set_plan_only(wc_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(WC_EINVAL, "NULL context");
+    ctx->plan_only = enable ? 1 : 0;
+    ctx->planned = 0;
+    return WC_OK;
+}
+
+wc_status wc_ctx_planned_bytes(wc_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(WC_EINVAL, "NULL argument");
+    *bytes = ctx->planned;
+    return WC_OK;
+}
+
+wc_status wc_ctx_pool_info(wc_ctx *ctx, size_t *pool_bytes, int64_t *grows)
+{
+    if (!ctx || !pool_bytes || !grows) return fail(WC_EINVAL, "NULL argument");
+    *pool_bytes = ctx->pool_bytes;
+    *grows = ctx->pool_grows;
+    return WC_OK;
+}
+
+wc_status wc_ctx_reserve(wc_ctx *ctx, size_t bytes)
+{
+    if (!ctx) return fail(WC_EINVAL, "NULL context");
+    if (bytes <= ctx->pool_bytes) return WC_OK;
+    WC_HIP(hipSetDevice(ctx->device));
+    WC_HIP(hipDeviceSynchronize());
+    ++ctx->pool_grows;
+    if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+        ctx->graph_key = 0;
+    }
+    for (auto &tg : ctx->tree_graphs) {
+        if (tg.exec) (void)hipGraphExecDestroy(tg.exec);
+        tg = wc_ctx::TreeGraph{};
+    }
+    return pool_alloc(ctx, bytes);
 }
 
 wc_status wc_ctx_set_wait_limit(wc_ctx *ctx, int64_t microseconds)

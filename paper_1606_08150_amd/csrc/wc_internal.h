@@ -68,6 +68,11 @@ struct wc_ctx {
     unsigned long long *host_ring = nullptr;  // pinned, device-visible; see kHostRing
     unsigned long long *host_ring_dev = nullptr;
     unsigned int epoch = 0;  // of the current call (begin_call advances it; never 0)
+    // plan-only mode (wc_ctx_set_plan_only): calls record their workspace and
+    // return WC_PLANNED before enqueueing anything
+    int plan_only = 0;
+    size_t planned = 0;
+    long long pool_grows = 0;
     unsigned long long wait_ticks = 0;  // bound of every device-side wait, in 100 MHz ticks
     wc::DevStats *dstats = nullptr;  // device
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -112,6 +117,8 @@ wc_status hip_fail(hipError_t e, const char *what);
 
 // Pool carving: reset at the start of each call, then take aligned slices.
 // Grows the pool (after draining the device) if a call needs more than it has.
+// In plan-only mode it records `bytes` and returns WC_PLANNED instead, which
+// every caller passes straight up (nothing has been enqueued at that point).
 wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream);
 void pool_reset(wc_ctx *ctx);
 template <typename T>
@@ -133,12 +140,16 @@ struct Config {
     int driver;
     bool fail_on_overflow;
     long long buf_capacity;
+    int buffer_alloc;
 };
 
 int resident_blocks(wc_ctx *ctx, const void *kernel, int block);
+// the same for a device with num_cus compute units (no context needed)
+int resident_blocks_on(int num_cus, const void *kernel, int block);
 
 // Every kernel launch of the library goes through here so that per-kernel
-// timing (wc_ctx_set_timing) can bracket it with events on its stream.
+// timing (wc_ctx_set_timing) can bracket it with events on its stream.  A
+// NULL context launches without timing (the entry points that take none).
 wc_status launch(wc_ctx *ctx, const char *name, const void *kernel, dim3 grid, dim3 block, void **args,
                  hipStream_t stream);
 wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_tune *tune, int resident, Config *out);
@@ -168,6 +179,11 @@ void clear_round_slot(wc_ctx *ctx, int r);
 // the same for one host-ring entry by index (0 <= index < kHostSlots)
 wc_status wait_host_slot(wc_ctx *ctx, int index, int *value);
 void clear_host_slot(wc_ctx *ctx, int index);
+
+// Recursive BFS in the wave and block modes (the recursion path); sets
+// *overflowed (levels incomplete) when its call list was too small.
+wc_status run_bfs_rec(wc_ctx *ctx, const wc_csr *g, int32_t src, uint32_t *level, wc_mode mode, const Config &cfg,
+                      hipStream_t stream, wc_stats *stats, int *overflowed);
 
 
 }  // namespace wc

@@ -5,9 +5,14 @@
 // its mode, a lighter row is summed inline by its lane ("work").
 //   wave  - ballot-mask buffer; the wave sums each buffered row, lane l taking
 //           elements l, l+64, ..., then a fixed butterfly reduction.
-//   block - thread-ordered LDS buffer, then the workgroup barrier.  Rows longer
-//           than BLOCK * items_per_lane are summed by the whole block (fixed
-//           block reduction); the others are shared out to the block's waves.
+//   block - thread-ordered LDS buffer, then the workgroup barrier; the buffered
+//           rows are shared out to the block's waves, one wave per row.
+//   In both, a buffered row too long for one group's child (more than
+//   4 * 64 * items_per_lane nonzeros for a wave, BLOCK * items_per_lane for a
+//   block) is handed on as chunks to a global buffer that the grid-mode drain
+//   spreads over the whole grid after the parent (the KC_X rule of Sec. IV.E
+//   gives a warp's or block's child many blocks); its chunk partials are
+//   combined in chunk order.
 //   grid  - global buffers and a grid-wide barrier (kernel boundary).  The
 //           child-work thread-count heuristic sizes the group of lanes that
 //           sums one buffered row: g = the power of two >= len / items_per_lane,
@@ -47,11 +52,17 @@ struct SpmvArgs {
     const float *val;  // nullptr: every stored entry is 1 (the in-edge sums of PageRank)
     const float *x;
     float *y;
+    // hot-column layout (wc_spmv_hot): column c < hot is the c-th most used
+    // column, whose x value is x_hot[c]; column hot + j is column j of x
+    const float *x_hot;
+    const int *hot_ids;
+    int hot;
     int n;
     int threshold;
     int ipl;           // items per lane
     int chunk;         // 64 * ipl
-    int big;           // block mode: rows longer than this use the whole block
+    int spill;         // wave and block modes: buffered rows longer than this go to the global chunks
+    int count_drain;   // grid mode: the drain counts as the consolidated dispatch
     // grid mode
     int *blk_count;    // [grid * kCols]: per parent block, rows per bin 0..6, chunks, split rows
     int *blk_off;      // [grid * kCols]: exclusive offsets of each block within its column
@@ -67,11 +78,21 @@ struct SpmvArgs {
     int want_stats;
 };
 
+// x value of stored column c.  Plain layout (hot = 0): x[c].  Hot-column
+// layout: the first nlds hot values staged in LDS (xs), the other hot ones in
+// x_hot, the rest in x.
+__device__ __forceinline__ float load_x(const SpmvArgs &a, const float *xs, int nlds, int c)
+{
+    if (c < a.hot) return c < nlds ? xs[c] : a.x_hot[c];
+    return a.x[c - a.hot];
+}
+
 // Sum of val[e] * x[col[e]] over e = first + k * stride (k >= 0, e < end), in
 // order of k, U loads in flight; the U products of a step are fused into the
 // cascade's first partial sum one after another.
 template <int U>
-__device__ __forceinline__ float dot_strided_u(const SpmvArgs &a, int first, int stride, int end)
+__device__ __forceinline__ float dot_strided_u(const SpmvArgs &a, int first, int stride, int end,
+                                               const float *xs = nullptr, int nlds = 0)
 {
     Cascade cs;
     for (int e0 = first; e0 < end; e0 += U * stride) {
@@ -85,7 +106,7 @@ __device__ __forceinline__ float dot_strided_u(const SpmvArgs &a, int first, int
             v[k] = ok ? (a.val ? a.val[e] : 1.f) : 0.f;
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) xv[k] = c[k] >= 0 ? a.x[c[k]] : 0.f;
+        for (int k = 0; k < U; ++k) xv[k] = c[k] >= 0 ? load_x(a, xs, nlds, c[k]) : 0.f;
 #pragma unroll
         for (int k = 0; k < U; ++k)
             if (c[k] >= 0) cs.s0 = fmaf(v[k], xv[k], cs.s0);
@@ -126,7 +147,6 @@ struct SpmvBlockBuf {
     int beg[BLOCK];
     int end[BLOCK];
     int scan_tmp[2 * (BLOCK / kWave)];
-    float red[BLOCK / kWave];
 };
 
 __device__ __forceinline__ void count_stats(StatAcc &acc, int len, bool heavy, bool wave_dispatch)
@@ -135,6 +155,43 @@ __device__ __forceinline__ void count_stats(StatAcc &acc, int len, bool heavy, b
     acc.buffered += heavy ? len : 0;
     acc.items += heavy ? 1 : 0;
     if (wave_dispatch && __ballot(heavy) && lane_id() == 0) acc.dispatches += 1;
+}
+
+// Hands the rows of the lanes with nch > 0 on as chunks of the global buffer
+// (wave and block modes): one reservation per wave for the chunks and one for
+// the split-row records; the wave writes each row's chunks together.  A row
+// whose chunks do not all fit is summed by its own lane instead (the overflow
+// fallback) and its reserved entries are marked empty.  Every lane calls this.
+__device__ __forceinline__ void spill_rows(const SpmvArgs &a, int r, int beg, int end, int nch)
+{
+    const int slot = wave_reserve_n(nch, &a.bin_total[kChunkBin]);
+    const int mslot = wave_reserve(nch > 0, &a.bin_total[kMultiCol]);
+    const bool fits = nch > 0 && (long long)slot + nch <= a.chunk_cap && mslot < a.multi_cap;
+    uint64_t m = __ballot(fits);
+    while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1;
+        const int s0 = readlane(slot, b), n0 = readlane(nch, b), rb = readlane(beg, b), re = readlane(end, b);
+        const int rr = readlane(r, b);
+        for (int c = lane_id(); c < n0; c += kWave) {
+            const int cb = rb + c * a.chunk;
+            a.chunks[s0 + c] = make_int4(rr, cb, min(re, cb + a.chunk), 0);
+        }
+    }
+    if (fits) a.multi[mslot] = make_int4(r, slot, nch, 0);
+    if (nch > 0 && !fits) {
+        for (int c = 0; c < nch; ++c)
+            if ((long long)slot + c < a.chunk_cap) a.chunks[slot + c] = make_int4(-1, 0, 0, 0);
+        if (mslot < a.multi_cap) a.multi[mslot] = make_int4(-1, 0, 0, 0);
+        a.stats->overflowed = 1;
+        a.y[r] = dot_strided(a, beg, 1, end);
+    }
+}
+
+// Zeroes the bin totals before a wave- or block-mode parent reserves chunks.
+__global__ void spmv_reset(SpmvArgs a)
+{
+    if (threadIdx.x < kCols) a.bin_total[threadIdx.x] = 0;
 }
 
 // Parent kernel of the flat, wave and block modes.
@@ -155,9 +212,15 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent(SpmvArgs a)
         const bool heavy = MODE != WC_FLAT && len > a.threshold;
         if (a.want_stats) count_stats(acc, len, heavy, MODE == WC_WAVE);
         if (valid && !heavy) a.y[r] = dot_strided(a, beg, 1, end);
+        // buffered rows too long for the group's own child go to the global chunks
+        const bool spill = heavy && len > a.spill;
+        if constexpr (MODE != WC_FLAT) {
+            if (__ballot(spill)) spill_rows(a, r, beg, end, spill ? (len + a.chunk - 1) / a.chunk : 0);
+        }
+        const bool mine = heavy && !spill;
 
         if constexpr (MODE == WC_WAVE) {
-            uint64_t mask = __ballot(heavy);
+            uint64_t mask = __ballot(mine);
             while (mask) {
                 int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
@@ -167,28 +230,19 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent(SpmvArgs a)
         } else if constexpr (MODE == WC_BLOCK) {
             __shared__ SpmvBlockBuf<BLOCK> sb;
             constexpr int NW = BLOCK / kWave;
-            int k, dummy, nb, dummy_total;
-            block_scan2<BLOCK>(heavy ? 1 : 0, 0, sb.scan_tmp, k, dummy, nb, dummy_total);
-            if (heavy) {
+            int k, dummy, nb, nh;
+            block_scan2<BLOCK>(mine ? 1 : 0, heavy ? 1 : 0, sb.scan_tmp, k, dummy, nb, nh);
+            if (mine) {
                 sb.row[k] = r;
                 sb.beg[k] = beg;
                 sb.end[k] = end;
             }
-            if (threadIdx.x == 0 && a.want_stats && nb) acc.dispatches += 1;
+            if (threadIdx.x == 0 && a.want_stats && nh) acc.dispatches += 1;
             __syncthreads();  // the "synchronize" between inserts and the child
-            // rows too long for one wave: the whole block, one row at a time
-            for (int it = 0; it < nb; ++it) {
-                const int rb = sb.beg[it], re = sb.end[it];
-                if (re - rb <= a.big) continue;
-                float s = dot_strided(a, rb + (int)threadIdx.x, BLOCK, re);
-                s = block_sum<BLOCK>(s, sb.red);
-                if (threadIdx.x == 0) a.y[sb.row[it]] = s;
-            }
-            // the rest: one wave per row, rows dealt round-robin to the waves
+            // one wave per row, rows dealt round-robin to the waves
             const int wid = threadIdx.x / kWave;
             for (int it = wid; it < nb; it += NW) {
                 const int rb = sb.beg[it], re = sb.end[it];
-                if (re - rb > a.big) continue;
                 float s = dot_wave(a, rb, re);
                 if (lane == 0) a.y[sb.row[it]] = s;
             }
@@ -355,10 +409,24 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
 
 // Consolidated child of grid mode.  Wave tasks: for bin b (g = 2^b lanes per
 // row) a task is 64 / g consecutive rows of the bin; then one task per chunk.
+// Hot x values staged in LDS by the drain of the hot-column layout: 32 per
+// thread, at most 16384 (64 KiB), so that four waves per SIMD stay resident.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void spmv_drain(SpmvArgs a)
+constexpr int lds_hot_for() { return 32 * BLOCK < 16384 ? 32 * BLOCK : 16384; }
+
+template <int BLOCK, bool HOT>
+struct DrainLds {
+    float x[HOT ? lds_hot_for<BLOCK>() : 1];
+};
+
+template <int BLOCK, bool HOT>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HOT ? 4 : 8))) void spmv_drain(SpmvArgs a)
 {
     __shared__ int s_cnt[8], s_off[8], s_task[9];
+    __shared__ DrainLds<BLOCK, HOT> s_x;
+    const int nlds = HOT ? min(a.hot, lds_hot_for<BLOCK>()) : 0;
+    if (HOT)
+        for (int i = threadIdx.x; i < nlds; i += BLOCK) s_x.x[i] = a.x_hot[i];
     if (threadIdx.x == 0) {
         int o = 0, t = 0;
         for (int b = 0; b < 8; ++b) {
@@ -371,7 +439,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
             t += b < kBins ? (c + (kWave >> b) - 1) / (kWave >> b) : c;
         }
         s_task[8] = t;
-        if (a.want_stats && blockIdx.x == 0 && t > 0) atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
+        if (a.want_stats && a.count_drain && blockIdx.x == 0 && t > 0)
+            atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
     }
     __syncthreads();
     const int total = s_task[8];
@@ -404,7 +473,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
                 dst = d.x;
             }
         }
-        float s = dot_strided_u<2 * kUnroll>(a, first, g, end);
+        float s = dot_strided_u<2 * kUnroll>(a, first, g, end, s_x.x, nlds);
         s = group_sum(s, g);
         if (dst >= 0 && sub == 0) {
             if (chunk) a.partials[dst] = s;
@@ -467,16 +536,24 @@ __global__ void spmv_basic_reset(SpmvArgs a)
     if (threadIdx.x == 0) a.bin_total[0] = 0;
 }
 
+// x_hot[k] = x[hot_ids[k]] for the hot-column layout (once per product).
+__global__ __launch_bounds__(256) void spmv_gather_hot(SpmvArgs a)
+{
+    float *xh = const_cast<float *>(a.x_hot);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < a.hot; k += gridDim.x * 256) xh[k] = a.x[a.hot_ids[k]];
+}
+
 struct SpmvKernels {
     const void *parent, *classify, *parent_grid, *drain, *combine;
 };
 
 template <int BLOCK>
-SpmvKernels pick_block(wc_mode mode)
+SpmvKernels pick_block(wc_mode mode, bool hot)
 {
     SpmvKernels k{nullptr, reinterpret_cast<const void *>(&spmv_classify<BLOCK>),
                   reinterpret_cast<const void *>(&spmv_parent_grid<BLOCK>),
-                  reinterpret_cast<const void *>(&spmv_drain<BLOCK>),
+                  hot ? reinterpret_cast<const void *>(&spmv_drain<BLOCK, true>)
+                      : reinterpret_cast<const void *>(&spmv_drain<BLOCK, false>),
                   reinterpret_cast<const void *>(&spmv_combine<BLOCK>)};
     switch (mode) {
     case WC_FLAT: k.parent = reinterpret_cast<const void *>(&spmv_parent<WC_FLAT, BLOCK>); break;
@@ -487,55 +564,63 @@ SpmvKernels pick_block(wc_mode mode)
     return k;
 }
 
-SpmvKernels pick(wc_mode mode, int block)
+SpmvKernels pick(wc_mode mode, int block, bool hot)
 {
     switch (block) {
-    case 64: return pick_block<64>(mode);
-    case 128: return pick_block<128>(mode);
-    case 512: return pick_block<512>(mode);
-    case 1024: return pick_block<1024>(mode);
-    default: return pick_block<256>(mode);
+    case 64: return pick_block<64>(mode, hot);
+    case 128: return pick_block<128>(mode, hot);
+    case 512: return pick_block<512>(mode, hot);
+    case 1024: return pick_block<1024>(mode, hot);
+    default: return pick_block<256>(mode, hot);
     }
 }
 
 
 // A planned product y = A x: the tune resolved, the kernels picked and the
-// workspace carved from the pool (plus `extra_bytes` left reserved for the
-// caller).  x and y may be set after planning.
+// workspace laid out (plus `extra_bytes` left for the caller after it).  x and
+// y may be set after planning.
 struct SpmvPlan {
     SpmvArgs a;
     SpmvKernels ks;
     Config cfg;
     wc_mode mode;
     int grid, dgrid;
+    long long rows_cap, cap, mcap;
 };
 
-wc_status spmv_plan(wc_ctx *ctx, const wc_csr *g, const float *val, wc_mode mode, const wc_tune *tune,
-                    size_t extra_bytes, hipStream_t stream, wc_stats *stats, SpmvPlan *p)
+// Resolves the tune and the launch shapes for a device with `num_cus` compute
+// units; touches no memory.
+wc_status spmv_shape(int num_cus, const wc_csr *g, const float *val, wc_mode mode, const wc_tune *tune,
+                     bool want_stats, SpmvPlan *p, bool hot = false)
 {
     int block = (tune && tune->block_threads > 0) ? tune->block_threads : 256;
     p->mode = mode;
-    p->ks = pick(mode, block);
-    int resident = resident_blocks(ctx, p->ks.parent, block);
-    wc_status st = resolve_tune(ctx, "spmv", mode, tune, resident, &p->cfg);
+    p->ks = pick(mode, block, hot);
+    int resident = resident_blocks_on(num_cus, p->ks.parent, block);
+    wc_status st = resolve_tune(nullptr, "spmv", mode, tune, resident, &p->cfg);
     if (st != WC_OK) return st;
     const Config &cfg = p->cfg;
     if (cfg.block != block) {
-        p->ks = pick(mode, cfg.block);
-        resident = resident_blocks(ctx, p->ks.parent, cfg.block);
+        p->ks = pick(mode, cfg.block, hot);
+        resident = resident_blocks_on(num_cus, p->ks.parent, cfg.block);
     }
+    // the drain of the hot-column layout holds 64 KiB of LDS: its own residency
+    if (hot) resident = std::min(resident, resident_blocks_on(num_cus, p->ks.drain, cfg.block));
     const long long n = g->n, m = g->m;
     const int chunk = kWave * cfg.items_per_lane;
-    long long cap_full = n + m / chunk + 1;
-    long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    long long rows_cap = mode == WC_GRID ? n : 1;
-    long long mcap = mode == WC_GRID ? n : 1;
+    // wave and block modes hand rows longer than `spill` on as chunks: at most
+    // m / spill such rows, each with at most one partly filled chunk
+    const int spill = mode == WC_WAVE ? 4 * chunk : cfg.block * cfg.items_per_lane;
+    long long cap_full = n + m / chunk + 1, multi_full = n;
+    if (mode == WC_WAVE || mode == WC_BLOCK) {
+        cap_full = m / chunk + m / spill + 1;
+        multi_full = m / spill + 1;
+    }
+    p->cap = mode != WC_FLAT ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
+    p->rows_cap = mode == WC_GRID ? n : 1;
+    p->mcap = mode != WC_FLAT ? multi_full : 1;
     p->grid = (int)std::max<long long>(1, std::min<long long>(cfg.grid, (n + cfg.block - 1) / cfg.block));
     p->dgrid = std::max(1, std::min(cfg.grid, resident));
-    size_t need = 2 * padded((size_t)p->grid * kCols * 4) + padded(kCols * 4) + padded(rows_cap * 16) +
-                  padded(cap * 16) + padded(cap * 4) + padded(mcap * 16) + extra_bytes;
-    st = pool_reserve(ctx, need, stream);
-    if (st != WC_OK) return st;
     SpmvArgs &a = p->a;
     std::memset(&a, 0, sizeof(a));
     a.row_ptr = g->row_ptr;
@@ -545,19 +630,53 @@ wc_status spmv_plan(wc_ctx *ctx, const wc_csr *g, const float *val, wc_mode mode
     a.threshold = cfg.threshold;
     a.ipl = cfg.items_per_lane;
     a.chunk = chunk;
-    a.big = cfg.block * cfg.items_per_lane;
-    a.blk_count = pool_take<int>(ctx, (size_t)p->grid * kCols);
-    a.blk_off = pool_take<int>(ctx, (size_t)p->grid * kCols);
-    a.bin_total = pool_take<int>(ctx, kCols);
-    a.rows_buf = pool_take<int4>(ctx, rows_cap);
-    a.rows_cap = rows_cap;
-    a.chunks = pool_take<int4>(ctx, cap);
-    a.chunk_cap = cap;
-    a.partials = pool_take<float>(ctx, cap);
-    a.multi = pool_take<int4>(ctx, mcap);
-    a.multi_cap = mcap;
-    a.stats = ctx->dstats;
-    a.want_stats = stats != nullptr;
+    a.spill = spill;
+    a.count_drain = mode == WC_GRID;
+    a.rows_cap = p->rows_cap;
+    a.chunk_cap = p->cap;
+    a.multi_cap = p->mcap;
+    a.want_stats = want_stats;
+    return WC_OK;
+}
+
+// Bytes of workspace the planned product needs (256-byte aligned pieces).
+size_t spmv_workspace_bytes(const SpmvPlan *p)
+{
+    return 2 * padded((size_t)p->grid * kCols * 4) + padded(kCols * 4) + padded(p->rows_cap * 16) +
+           padded(p->cap * 16) + padded(p->cap * 4) + padded(p->mcap * 16);
+}
+
+// Lays the workspace out from `base` (256-byte aligned, spmv_workspace_bytes
+// long); returns the first byte after it.
+char *spmv_carve(SpmvPlan *p, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *q = base + off;
+        off += padded(bytes);
+        return q;
+    };
+    SpmvArgs &a = p->a;
+    a.blk_count = reinterpret_cast<int *>(take((size_t)p->grid * kCols * 4));
+    a.blk_off = reinterpret_cast<int *>(take((size_t)p->grid * kCols * 4));
+    a.bin_total = reinterpret_cast<int *>(take(kCols * 4));
+    a.rows_buf = reinterpret_cast<int4 *>(take(p->rows_cap * 16));
+    a.chunks = reinterpret_cast<int4 *>(take(p->cap * 16));
+    a.partials = reinterpret_cast<float *>(take(p->cap * 4));
+    a.multi = reinterpret_cast<int4 *>(take(p->mcap * 16));
+    return base + off;
+}
+
+wc_status spmv_plan(wc_ctx *ctx, const wc_csr *g, const float *val, wc_mode mode, const wc_tune *tune,
+                    size_t extra_bytes, hipStream_t stream, wc_stats *stats, SpmvPlan *p, bool hot = false)
+{
+    wc_status st = spmv_shape(ctx->num_cus, g, val, mode, tune, stats != nullptr, p, hot);
+    if (st != WC_OK) return st;
+    st = pool_reserve(ctx, spmv_workspace_bytes(p) + extra_bytes, stream);
+    if (st != WC_OK) return st;
+    char *end = spmv_carve(p, ctx->pool);
+    ctx->pool_off = (size_t)(end - ctx->pool);
+    p->a.stats = ctx->dstats;
     return WC_OK;
 }
 
@@ -567,9 +686,18 @@ wc_status spmv_launch(wc_ctx *ctx, SpmvPlan *p, hipStream_t stream)
 {
     const Config &cfg = p->cfg;
     void *args[] = {&p->a};
+    if (p->mode == WC_FLAT)
+        return launch(ctx, "spmv_parent_flat", p->ks.parent, dim3(p->grid), dim3(cfg.block), args, stream);
     if (p->mode != WC_GRID) {
-        static const char *names[] = {"spmv_parent_flat", "spmv_parent_wave", "spmv_parent_block"};
-        return launch(ctx, names[p->mode], p->ks.parent, dim3(p->grid), dim3(cfg.block), args, stream);
+        // parent, then the grid-wide drain of the rows it handed on and their combination
+        const char *name = p->mode == WC_WAVE ? "spmv_parent_wave" : "spmv_parent_block";
+        wc_status st = launch(ctx, "spmv_reset", reinterpret_cast<const void *>(&spmv_reset), dim3(1), dim3(kWave),
+                              args, stream);
+        if (st == WC_OK) st = launch(ctx, name, p->ks.parent, dim3(p->grid), dim3(cfg.block), args, stream);
+        if (st == WC_OK) st = launch(ctx, "spmv_drain", p->ks.drain, dim3(p->dgrid), dim3(cfg.block), args, stream);
+        if (st == WC_OK)
+            st = launch(ctx, "spmv_combine", p->ks.combine, dim3(p->dgrid), dim3(cfg.block), args, stream);
+        return st;
     }
     int nblocks = p->grid;
     void *sargs[] = {&p->a, &nblocks};
@@ -748,4 +876,111 @@ extern "C" wc_status wc_pagerank(wc_ctx *ctx, const wc_csr *in_graph, const int3
     }
     if (st != WC_OK) return st;
     return end_call(ctx, stream, stats, iterations, p.cfg.fail_on_overflow);
+}
+
+// ---------------------------------------------------------------- hot-column layout
+
+namespace wc {
+namespace {
+
+__global__ __launch_bounds__(256) void hot_count(const int *col, long long m, int *cnt)
+{
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < m; e += (long long)gridDim.x * 256)
+        atomicAdd(&cnt[col[e]], 1);
+}
+
+__global__ __launch_bounds__(256) void hot_remap(const int *col, long long m, const int *rank, int hot, int *out)
+{
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < m; e += (long long)gridDim.x * 256) {
+        const int c = col[e];
+        const int r = rank[c];
+        out[e] = r >= 0 ? r : hot + c;
+    }
+}
+
+}  // namespace
+}  // namespace wc
+
+extern "C" wc_status wc_spmv_prepare(wc_ctx *ctx, const wc_csr *a, int32_t hot, int32_t *col_hot, int32_t *hot_ids,
+                                     hipStream_t stream)
+{
+    if (!ctx || !a) return fail(WC_EINVAL, "wc_spmv_prepare: NULL context or matrix");
+    if (a->n < 0 || a->m < 0) return fail(WC_EINVAL, "wc_spmv_prepare: negative size");
+    if (hot < 0 || hot > a->n) return fail(WC_EINVAL, "wc_spmv_prepare: hot must be in [0, n]");
+    if ((long long)a->n + hot > 0x7fffffffLL) return fail(WC_EINVAL, "wc_spmv_prepare: n + hot exceeds int32");
+    if (a->n == 0) return WC_OK;
+    if (!a->row_ptr || (a->m > 0 && (!a->col || !col_hot)) || (hot > 0 && !hot_ids))
+        return fail(WC_EINVAL, "wc_spmv_prepare: NULL array");
+    WC_HIP(hipSetDevice(ctx->device));
+    const long long n = a->n, m = a->m;
+    wc_status st = pool_reserve(ctx, 2 * padded(n * 4), stream);
+    if (st != WC_OK) return st;
+    int *cnt = pool_take<int>(ctx, n);
+    int *rank = pool_take<int>(ctx, n);
+    const int grid = (int)std::max<long long>(1, std::min<long long>((m + 255) / 256, 8LL * ctx->num_cus));
+    chain_break(ctx);
+    WC_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)n, stream));
+    if (m > 0) {
+        void *args[] = {const_cast<int **>(&a->col), const_cast<long long *>(&m), &cnt};
+        st = launch(ctx, "hot_count", reinterpret_cast<const void *>(&hot_count), dim3(grid), dim3(256), args, stream);
+        if (st != WC_OK) return st;
+    }
+    // the hot columns: most entries first, ties by column id
+    std::vector<int> counts((size_t)n), order((size_t)n), rk((size_t)n, -1);
+    WC_HIP(hipMemcpyAsync(counts.data(), cnt, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, stream));
+    WC_HIP(hipStreamSynchronize(stream));
+    for (long long v = 0; v < n; ++v) order[(size_t)v] = (int)v;
+    auto more = [&](int u, int v) { return counts[u] != counts[v] ? counts[u] > counts[v] : u < v; };
+    std::partial_sort(order.begin(), order.begin() + hot, order.end(), more);
+    for (int k = 0; k < hot; ++k) rk[(size_t)order[(size_t)k]] = k;
+    chain_break(ctx);
+    WC_HIP(hipMemcpyAsync(rank, rk.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, stream));
+    if (hot > 0) WC_HIP(hipMemcpyAsync(hot_ids, order.data(), sizeof(int) * (size_t)hot, hipMemcpyHostToDevice, stream));
+    if (m > 0) {
+        void *args[] = {const_cast<int **>(&a->col), const_cast<long long *>(&m), &rank, &hot, &col_hot};
+        st = launch(ctx, "hot_remap", reinterpret_cast<const void *>(&hot_remap), dim3(grid), dim3(256), args, stream);
+        if (st != WC_OK) return st;
+    }
+    // the host vectors above are read by the copies: wait for them
+    WC_HIP(hipStreamSynchronize(stream));
+    return WC_OK;
+}
+
+extern "C" wc_status wc_spmv_hot(wc_ctx *ctx, const wc_csr *a_hot, int32_t hot, const int32_t *hot_ids,
+                                 const float *val, const float *x, float *y, wc_mode mode, const wc_tune *tune,
+                                 hipStream_t stream, wc_stats *stats)
+{
+    if (!ctx || !a_hot) return fail(WC_EINVAL, "wc_spmv_hot: NULL context or matrix");
+    if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "wc_spmv_hot: bad mode");
+    if (a_hot->n < 0 || a_hot->m < 0) return fail(WC_EINVAL, "wc_spmv_hot: negative size");
+    if (hot < 0 || hot > a_hot->n) return fail(WC_EINVAL, "wc_spmv_hot: hot must be in [0, n]");
+    if (a_hot->n == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return WC_OK;
+    }
+    if (!a_hot->row_ptr || !x || !y || (a_hot->m > 0 && (!a_hot->col || !val)) || (hot > 0 && !hot_ids))
+        return fail(WC_EINVAL, "wc_spmv_hot: NULL array");
+    WC_HIP(hipSetDevice(ctx->device));
+    SpmvPlan p;
+    wc_status st = spmv_plan(ctx, a_hot, val, mode, tune, padded((size_t)std::max(hot, 1) * 4), stream, stats, &p,
+                             hot > 0);
+    if (st != WC_OK) return st;
+    if (p.cfg.driver != 0) return fail(WC_EINVAL, "wc_spmv_hot: only the relaunch driver (driver = 0) applies");
+    p.a.x = x;
+    p.a.y = y;
+    p.a.hot = hot;
+    p.a.hot_ids = hot_ids;
+    p.a.x_hot = pool_take<float>(ctx, (size_t)std::max(hot, 1));
+    st = begin_call(ctx, stream, stats);
+    if (st != WC_OK) return st;
+    if (hot > 0) {
+        void *args[] = {&p.a};
+        const int g = (int)std::min<long long>((hot + 255) / 256, 4LL * ctx->num_cus);
+        st = launch(ctx, "spmv_gather_hot", reinterpret_cast<const void *>(&spmv_gather_hot), dim3(g), dim3(256), args,
+                    stream);
+        if (st != WC_OK) return st;
+    }
+    st = spmv_launch(ctx, &p, stream);
+    if (st != WC_OK) return st;
+    return end_call(ctx, stream, stats, 1, p.cfg.fail_on_overflow);
 }

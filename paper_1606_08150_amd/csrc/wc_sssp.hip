@@ -54,6 +54,9 @@ struct SsspArgs {
     int n;
     int threshold;
     int chunk;
+    int spill;        // wave and block modes: buffered items with more edges go to the global buffer
+    int buffer_alloc; // wave and block buffers: 0 registers / LDS, 1 pool slices, 2 device malloc
+    int4 *group_bufs; // buffer_alloc 1: one slice of BLOCK + 1 items per workgroup (waves: 64 each)
     unsigned long long *host_ring;
     DevStats *stats;
     int want_stats;
@@ -132,6 +135,7 @@ __device__ __forceinline__ int relax_wave(const SsspArgs &a, int beg, int end, u
 // their edges are requested (they may have improved since the vertex was
 // buffered); the largest distance used per chunk is returned.  Chunk 1 may be
 // empty (cb1 == ce1, u1 unused).
+template <bool STAMP>
 __device__ __forceinline__ int relax_wave2(const SsspArgs &a, int u0, int cb0, int ce0, int u1, int cb1, int ce1,
                                             int next, uint32_t &du0_used, uint32_t &du1_used)
 {
@@ -157,7 +161,7 @@ __device__ __forceinline__ int relax_wave2(const SsspArgs &a, int u0, int cb0, i
         for (int k = 0; k < 2 * kUnroll; ++k) dv[k] = v[k] >= 0 ? a.dist[v[k]] : 0u;
 #pragma unroll
         for (int k = 0; k < 2 * kUnroll; ++k)
-            if (v[k] >= 0) upd += relax_loaded<false>(a, v[k], add_sat(k < kUnroll ? du0 : du1, wt[k]), dv[k], next);
+            if (v[k] >= 0) upd += relax_loaded<STAMP>(a, v[k], add_sat(k < kUnroll ? du0 : du1, wt[k]), dv[k], next);
     }
     return upd;
 }
@@ -167,6 +171,83 @@ __device__ __forceinline__ void mark_active(const SsspArgs &a, int r, bool any)
     if (__ballot(any) && lane_id() == 0) a.active[((r + 1) % 3) * kPad] = 1;
 }
 
+// Child thread-count heuristic of the wave and block modes (the KC_X rule of
+// Sec. IV.E: a warp's or block's consolidated child is launched with many
+// blocks, not just the parent group's threads).  An item of the wave's or
+// block's buffer with more than `spill` edges is handed on as chunks of the
+// round's global buffer, which the drain kernel after the parent spreads over
+// the whole grid, instead of occupying its own group for its whole edge list.
+// Every lane of the wave calls this (nch = 0: nothing to hand on); one atomic
+// per wave reserves the slots and the wave writes each item's chunks together.
+// A chunk beyond the buffer's capacity is relaxed by the writing lane itself
+// (the overflow fallback).  Returns the updates made by such fallbacks.
+__device__ __forceinline__ int spill_chunks(const SsspArgs &a, int r, int u, int beg, int end, uint32_t du, int nch)
+{
+    const int slot = wave_reserve_n(nch, &a.chunk_tail[(r % 3) * kPad]);
+    int upd = 0;
+    uint64_t m = __ballot(nch > 0);
+    while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1;
+        const int s0 = readlane(slot, b), n0 = readlane(nch, b), rb = readlane(beg, b), re = readlane(end, b);
+        const int ub = readlane(u, b);
+        const uint32_t dub = readlane_u(du, b);
+        for (int c = lane_id(); c < n0; c += kWave) {
+            const int cb = rb + c * a.chunk, ce = min(re, cb + a.chunk);
+            if ((long long)s0 + c < a.chunk_cap) {
+                a.chunks[s0 + c] = make_int4(ub, cb, ce, 0);
+            } else {
+                a.stats->overflowed = 1;
+                upd += relax_lane<true>(a, cb, ce, dub, r + 1);
+            }
+        }
+    }
+    return upd;
+}
+
+// Buffers in global memory, for the allocator comparison of Sec. V.A: the
+// paper's consolidation buffers live in global memory and come either from a
+// pre-allocated pool or from the device's malloc.  Here the group writes its
+// buffered items out, its child reads them back, and a malloc'ed buffer is
+// freed after the child.  A failed malloc leaves the items in registers / LDS
+// (the default path) and raises the overflow flag.
+__device__ __forceinline__ int4 *group_buffer(const SsspArgs &a, int slot, int items)
+{
+    if (a.buffer_alloc == 1) return a.group_bufs + slot;
+    return static_cast<int4 *>(malloc((size_t)items * sizeof(int4)));
+}
+
+// Wave mode: items (begin, end, du) of the lanes in `mask` through a global buffer.
+__device__ __forceinline__ int wave_child_global(const SsspArgs &a, uint64_t mask, bool mine, int beg, int end,
+                                                 uint32_t du, int next, bool &done)
+{
+    const int nb = __builtin_popcountll(mask);
+    unsigned long long p = 0;
+    if (lane_id() == 0) {
+        // pool slices: the block's slice of BLOCK + 1 items, 64 per wave
+        const int wave_slot = blockIdx.x * (blockDim.x + 1) + threadIdx.x / kWave * kWave;
+        p = reinterpret_cast<unsigned long long>(group_buffer(a, wave_slot, nb));
+    }
+    p = ((unsigned long long)readlane_u((uint32_t)(p >> 32), 0) << 32) | readlane_u((uint32_t)p, 0);
+    int4 *buf = reinterpret_cast<int4 *>(p);
+    done = buf != nullptr;
+    if (!buf) {
+        if (lane_id() == 0) a.stats->overflowed = 1;
+        return 0;
+    }
+    if (mine) buf[rank_in(mask)] = make_int4(beg, end, (int)du, 0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    int upd = 0;
+    for (int i = 0; i < nb; ++i) {
+        const int4 it = buf[i];
+        upd += relax_wave(a, __builtin_amdgcn_readfirstlane(it.x), __builtin_amdgcn_readfirstlane(it.y),
+                          (uint32_t)__builtin_amdgcn_readfirstlane(it.z), next);
+    }
+    if (a.buffer_alloc == 2 && lane_id() == 0) free(buf);
+    return upd;
+}
+
 template <int BLOCK>
 struct BlockBuf {
     int beg[BLOCK];
@@ -174,6 +255,7 @@ struct BlockBuf {
     int pre[BLOCK + 1];
     int scan_tmp[2 * (BLOCK / kWave)];
     int base;
+    int4 *gbuf;  // buffer_alloc != 0: the block's buffer in global memory (or NULL: LDS)
 };
 
 // Parent kernel of round r in flat, wave and block modes: thread i takes vertex
@@ -185,6 +267,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
     const int act = a.active[(r % 3) * kPad];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.active[((r + 2) % 3) * kPad] = 0;
+        a.chunk_tail[((r + 1) % 3) * kPad] = 0;
         publish_host(a.host_ring, r % kHostRing, a.stats, act);
     }
     if (!act) return;
@@ -213,9 +296,19 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
         const int upd_inline = relax_lane<true>(a, beg, heavy ? beg : end, du, next);
         int upd = 0;  // by the consolidated child
 
+        // buffered items too long for the group's own child go to the global buffer
+        const bool spill = MODE != WC_FLAT && heavy && deg > a.spill;
+        if constexpr (MODE != WC_FLAT) {
+            if (__ballot(spill)) upd += spill_chunks(a, r, u, beg, end, du, spill ? (deg + a.chunk - 1) / a.chunk : 0);
+        }
+        const bool mine = heavy && !spill;
+
         if constexpr (MODE == WC_WAVE) {
             // insert_buffer = ballot; the mask is the wave's buffer; no barrier needed
-            uint64_t mask = __ballot(heavy);
+            uint64_t mask = __ballot(mine);
+            bool done = false;
+            if (a.buffer_alloc && mask) upd += wave_child_global(a, mask, mine, beg, end, du, next, done);
+            if (done) mask = 0;
             while (mask) {
                 int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
@@ -224,16 +317,32 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
         } else if constexpr (MODE == WC_BLOCK) {
             __shared__ BlockBuf<BLOCK> sb;
             int k, off, nb, total;
-            block_scan2<BLOCK>(heavy ? 1 : 0, heavy ? deg : 0, sb.scan_tmp, k, off, nb, total);
-            if (heavy) {
-                sb.beg[k] = beg;
-                sb.du[k] = du;
-                sb.pre[k] = off;
+            block_scan2<BLOCK>(mine ? 1 : 0, mine ? deg : 0, sb.scan_tmp, k, off, nb, total);
+            if (a.buffer_alloc) {
+                // the buffer in global memory (allocator comparison); NULL: LDS
+                if (threadIdx.x == 0) {
+                    sb.gbuf = nb ? group_buffer(a, blockIdx.x * (BLOCK + 1), nb + 1) : nullptr;
+                    if (nb && !sb.gbuf) a.stats->overflowed = 1;
+                }
+                __syncthreads();
+            }
+            int4 *const gb = a.buffer_alloc ? sb.gbuf : nullptr;
+            if (mine) {
+                if (gb) {
+                    gb[k] = make_int4(beg, (int)du, off, 0);
+                } else {
+                    sb.beg[k] = beg;
+                    sb.du[k] = du;
+                    sb.pre[k] = off;
+                }
             }
             if (threadIdx.x == 0) {
-                sb.pre[nb] = total;
-                if (a.want_stats && nb) acc.dispatches += 1;
+                if (gb) gb[nb] = make_int4(0, 0, total, 0);
+                else sb.pre[nb] = total;
             }
+            // the block's buffer counts as one dispatch when it holds any item,
+            // also when all of them were handed on to the grid
+            if (a.want_stats && __syncthreads_or(heavy) && threadIdx.x == 0) acc.dispatches += 1;
             __syncthreads();  // the "synchronize" between inserts and the child
             // the block relaxes the concatenated edge ranges, kUnroll edges per
             // thread in flight: flattened index j -> (item, edge) by a cursor
@@ -247,10 +356,18 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
                     v[q] = -1;
                     nd[q] = 0;
                     if (j < total) {
-                        while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
-                        const int e = sb.beg[it] + (j - sb.pre[it]);
-                        v[q] = a.col[e];
-                        nd[q] = add_sat(sb.du[it], weight(a, e));
+                        if (gb) {
+                            while (it + 1 < nb && gb[it + 1].z <= j) ++it;
+                            const int4 d = gb[it];
+                            const int e = d.x + (j - d.z);
+                            v[q] = a.col[e];
+                            nd[q] = add_sat((uint32_t)d.y, weight(a, e));
+                        } else {
+                            while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
+                            const int e = sb.beg[it] + (j - sb.pre[it]);
+                            v[q] = a.col[e];
+                            nd[q] = add_sat(sb.du[it], weight(a, e));
+                        }
                     }
                 }
 #pragma unroll
@@ -260,6 +377,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
                     if (v[q] >= 0) upd += relax_loaded<true>(a, v[q], nd[q], dv[q], next);
             }
             __syncthreads();  // LDS buffer is reused by the next window
+            if (gb && a.buffer_alloc == 2 && threadIdx.x == 0) free(gb);
         }
         if (a.want_stats) {
             acc.updates += upd_inline + upd;
@@ -435,8 +553,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
 }
 
 // Consolidated child of grid-level consolidation: one wave per chunk, chunks
-// fetched grid-stride until the buffer is exhausted (moldable).
-template <int BLOCK>
+// fetched grid-stride until the buffer is exhausted (moldable).  With STAMP
+// (wave and block modes) it drains the items their groups handed on, and
+// stamps improved vertices into the next frontier instead of keeping
+// relaxed_at.
+template <int BLOCK, bool STAMP>
 __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
 {
     if (!a.active[(r % 3) * kPad]) return;
@@ -445,7 +566,9 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
     const int next = r + 1;
     const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
     const int nw = gridDim.x * (BLOCK / kWave);
-    if (a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0)
+    // in wave and block modes the drain runs the children of the groups' buffers,
+    // which those groups already counted as dispatches
+    if (!STAMP && a.want_stats && blockIdx.x == 0 && threadIdx.x == 0 && total > 0)
         atomic_add_dev(&a.stats->rep[0].dispatches, 1ull);
     int upd = 0;
     // two chunks per wave and step; the next pair's entries are fetched before
@@ -460,8 +583,8 @@ __global__ __launch_bounds__(BLOCK) void sssp_drain(SsspArgs a, int r)
         d0 = load_or_zero(a.chunks, cn, cn < total);
         d1 = load_or_zero(a.chunks, cn + nw, cn + nw < total);
         uint32_t du0, du1;
-        upd += relax_wave2(a, u0, cb0, ce0, u1, cb1, ce1, next, du0, du1);
-        if (lane_id() == 0) {
+        upd += relax_wave2<STAMP>(a, u0, cb0, ce0, u1, cb1, ce1, next, du0, du1);
+        if (!STAMP && lane_id() == 0) {
             atomic_max_dev_noret(&a.relaxed_at[u0], du0);
             if (cb1 < ce1) atomic_max_dev_noret(&a.relaxed_at[u1], du1);
         }
@@ -513,11 +636,12 @@ struct KernelSet {
 template <int BLOCK>
 KernelSet pick_block(wc_mode mode)
 {
-    const void *drain = reinterpret_cast<const void *>(&sssp_drain<BLOCK>);
+    const void *drain = reinterpret_cast<const void *>(&sssp_drain<BLOCK, false>);
+    const void *drain_stamp = reinterpret_cast<const void *>(&sssp_drain<BLOCK, true>);
     switch (mode) {
     case WC_FLAT: return {reinterpret_cast<const void *>(&sssp_round<WC_FLAT, BLOCK>), nullptr};
-    case WC_WAVE: return {reinterpret_cast<const void *>(&sssp_round<WC_WAVE, BLOCK>), nullptr};
-    case WC_BLOCK: return {reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK>), nullptr};
+    case WC_WAVE: return {reinterpret_cast<const void *>(&sssp_round<WC_WAVE, BLOCK>), drain_stamp};
+    case WC_BLOCK: return {reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK>), drain_stamp};
     default: return {reinterpret_cast<const void *>(&sssp_round_grid2<BLOCK>), drain};
     }
 }
@@ -562,6 +686,8 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     if (st != WC_OK) return st;
     if ((cfg.driver == 2 || cfg.driver == 3) && mode != WC_GRID)
         return fail(WC_EINVAL, "drivers 2 and 3 are comparison variants of grid mode only");
+    if (cfg.buffer_alloc != 0 && mode != WC_WAVE && mode != WC_BLOCK)
+        return fail(WC_EINVAL, "buffer_alloc applies to the wave and block modes only");
     if (cfg.block != block) {
         ks = pick(mode, cfg.block);
         resident = resident_blocks(ctx, ks.round, cfg.block);
@@ -571,8 +697,14 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     // Grid buffer: every frontier vertex (at most n per round) yields at most
     // ceil(deg / chunk) chunks, so n + m / chunk + 1 entries never overflow.
     long long cap_full = n + m / chunk + 1;
-    long long cap = mode == WC_GRID ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    size_t need = padded(n * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16);
+    // wave and block modes hand on only vertices above `spill` edges, each at
+    // most once per round: m / chunk + m / spill + 1 entries suffice
+    const int spill = mode == WC_WAVE ? 4 * chunk : (cfg.block / kWave) * chunk;
+    if (mode == WC_WAVE || mode == WC_BLOCK) cap_full = m / chunk + m / spill + 1;
+    long long cap = mode != WC_FLAT ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
+    const int grid_cap = std::max(1, std::min(cfg.grid, resident));
+    const long long slices = cfg.buffer_alloc == 1 ? (long long)grid_cap * (cfg.block + 1) : 0;
+    size_t need = padded(n * 4) + 2 * padded(3 * kPad * 4) + padded(cap * 16) + padded(slices * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     SsspArgs a;
@@ -587,9 +719,13 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     a.chunk_tail = pool_take<int>(ctx, 3 * kPad);
     a.chunks = pool_take<int4>(ctx, cap);
     a.chunk_cap = cap;
+    a.buffer_alloc = cfg.buffer_alloc;
+    a.group_bufs = slices ? pool_take<int4>(ctx, slices) : nullptr;
     a.n = (int)n;
     a.threshold = cfg.threshold;
     a.chunk = chunk;
+    // a wave's child keeps items of up to 4 chunks, a block's up to one chunk per wave
+    a.spill = spill;
     a.host_ring = ctx->host_ring_dev;
     a.stats = ctx->dstats;
     a.want_stats = stats != nullptr;
@@ -689,7 +825,7 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
             clear_round_slot(ctx, launched);
             void *args[] = {&a, &launched};
             st = launch(ctx, round_name(mode), ks.round, dim3(grid), dim3(cfg.block), args, stream);
-            if (st == WC_OK && mode == WC_GRID)
+            if (st == WC_OK && ks.drain)
                 st = launch(ctx, "sssp_drain", ks.drain, dim3(dgrid), dim3(cfg.block), args, stream);
             if (st != WC_OK) return st;
             ++launched;
@@ -742,5 +878,21 @@ extern "C" wc_status wc_bfs(wc_ctx *ctx, const wc_csr *g, int32_t src, uint32_t 
         if (stats) std::memset(stats, 0, sizeof(*stats));
         return WC_OK;
     }
-    return run_sssp(ctx, g, nullptr, src, level, mode, tune, stream, stats);
+    if (mode != WC_WAVE && mode != WC_BLOCK) return run_sssp(ctx, g, nullptr, src, level, mode, tune, stream, stats);
+    // wave and block modes: the recursion path (consolidated recursive calls)
+    WC_HIP(hipSetDevice(ctx->device));
+    Config cfg;
+    st = resolve_tune(ctx, "sssp", mode, tune, 1 << 20, &cfg);
+    if (st != WC_OK) return st;
+    if (cfg.driver != 0) return fail(WC_EINVAL, "wc_bfs: drivers 2 and 3 are comparison variants of grid mode only");
+    if (cfg.buffer_alloc != 0) return fail(WC_EINVAL, "wc_bfs: buffer_alloc does not apply to the recursion path");
+    int overflowed = 0;
+    st = run_bfs_rec(ctx, g, src, level, mode, cfg, stream, stats, &overflowed);
+    if (st != WC_OK || !overflowed) return st;
+    // the call list was too small: the frontier rounds recompute the levels
+    st = run_sssp(ctx, g, nullptr, src, level, mode, tune, stream, stats);
+    if (stats) stats->overflowed = 1;
+    if (st == WC_OK && cfg.fail_on_overflow)
+        return fail(WC_EOVERFLOW, "wc_bfs: the call list overflowed (buf_capacity too small)");
+    return st;
 }

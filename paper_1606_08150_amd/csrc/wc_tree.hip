@@ -21,13 +21,15 @@
 //           final) buffer becomes one consolidated dispatch: a packet in a
 //           device-wide queue that any wave (block) of the persistent grid
 //           picks up.  The post-work runs as soon as a node's last child is
-//           done: per-node pending-children counters; the thread that
+//           done: per-node words of pending children and folded value; the thread that
 //           completes a node folds it into its parent and climbs on while it
 //           keeps completing ancestors.
 // Integer folds are associative and commutative, so every mode and schedule
 // gives identical results.
 #include <algorithm>
 #include <cstring>
+#include <string>
+#include <type_traits>
 #include <vector>
 
 #include "wc_block.h"
@@ -40,6 +42,14 @@ namespace {
 
 enum { OP_DESC = 0, OP_HEIGHT = 1 };
 
+// One tree of a batch (wc_tree_batch).
+struct TreeInst {
+    const int *child_ptr;
+    const int *child;
+    int *out;
+    long long n;
+};
+
 struct TreeArgs {
     const int *parent;
     const int *child_ptr;
@@ -47,6 +57,10 @@ struct TreeArgs {
     int *out;
     int n;
     int chunk;
+    // batch of trees (level-synchronous modes): NULL for a single tree; else
+    // items carry their tree's index in .w >> 1 and every array is the tree's
+    const TreeInst *inst;
+    int count;
     // level-synchronous modes
     int *lvl_start;  // [max_levels + 2]
     int *lvl_count;  // [max_levels + 2]
@@ -60,7 +74,7 @@ struct TreeArgs {
     int *pq_head;
     int *pq_tail;
     int *outstanding;
-    int *pending;        // per-node children not yet finished
+    unsigned long long *word;  // per internal node: (children not yet finished << 32) | folded value
     int work_cap;        // flush a buffer once its nodes carry this many children
     unsigned long long wait_ticks;  // bound of the packet queue's waits (100 MHz ticks)
     unsigned long long *host_ring;
@@ -69,6 +83,20 @@ struct TreeArgs {
 };
 
 __device__ __forceinline__ int fanout(const TreeArgs &a, int v) { return a.child_ptr[v + 1] - a.child_ptr[v]; }
+
+// The arrays of the tree an item belongs to (the single tree, or tree i of a batch).
+struct TreeView {
+    const int *child_ptr;
+    const int *child;
+    int *out;
+};
+__device__ __forceinline__ TreeView view(const TreeArgs &a, int i)
+{
+    if (!a.inst) return TreeView{a.child_ptr, a.child, a.out};
+    const TreeInst &t = a.inst[i];
+    return TreeView{t.child_ptr, t.child, t.out};
+}
+__device__ __forceinline__ int fanout(const TreeView &t, int v) { return t.child_ptr[v + 1] - t.child_ptr[v]; }
 
 template <int OP>
 __device__ __forceinline__ int fold(int acc, int v)
@@ -117,6 +145,39 @@ __global__ void tree_init_levels_flat(TreeArgs a)
     }
 }
 
+// Level 0 of a batch: every tree's root is the host's launch on its children.
+// One workgroup; grid mode buffers the roots' children as chunks, flat mode the
+// roots themselves.
+__global__ __launch_bounds__(256) void tree_init_batch(TreeArgs a, int grid_mode)
+{
+    __shared__ int s_count;
+    if (threadIdx.x == 0) {
+        s_count = 0;
+        a.lvl_start[0] = 0;
+        a.lvl_count[1] = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.count; i += blockDim.x) {
+        const TreeView t = view(a, i);
+        t.out[0] = 0;
+        const int f = fanout(t, 0);
+        if (f == 0) continue;
+        if (!grid_mode) {
+            const int slot = atomicAdd(&s_count, 1);
+            a.items[slot] = make_int4(0, 0, 0, i << 1);
+            continue;
+        }
+        const int nch = (f + a.chunk - 1) / a.chunk;
+        const int slot = atomicAdd(&s_count, nch);
+        for (int c = 0; c < nch; ++c) {
+            const int cb = t.child_ptr[0] + c * a.chunk;
+            a.items[slot + c] = make_int4(0, cb, min(cb + a.chunk, t.child_ptr[1]), (i << 1) | (nch == 1));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.lvl_count[0] = s_count;
+}
+
 // Items per block tile in the grid-mode level passes: up to BLOCK, fewer when
 // the level is small, so that every block of the grid gets work.
 template <int BLOCK>
@@ -138,26 +199,29 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count, StatA
         // children as one flattened range (most items have a few children), so
         // the next level's buffer is reserved with one atomic per BLOCK
         // children instead of one per item.
-        __shared__ int s_pre[BLOCK], s_cb[BLOCK], s_tmp[2 * (BLOCK / kWave)];
+        __shared__ int s_pre[BLOCK], s_cb[BLOCK], s_inst[BLOCK], s_tmp[2 * (BLOCK / kWave)];
         __shared__ int s_base;
         const int T = tile_items<BLOCK>(count);
         for (int tile = blockIdx.x * T; tile < count; tile += gridDim.x * T) {
             const int it = tile + threadIdx.x;
-            int cb = 0, len = 0;
+            int cb = 0, len = 0, ti = 0;
             if ((int)threadIdx.x < T && it < count) {
                 const int4 d = a.items[start + it];
                 cb = d.y;
                 len = d.z - d.y;
+                ti = d.w >> 1;
             }
             if (a.want_stats) acc.edges += len;
             int excl, e0, total, e1;
             block_scan2<BLOCK>(len, 0, s_tmp, excl, e0, total, e1);
             s_pre[threadIdx.x] = excl;
             s_cb[threadIdx.x] = cb;
+            s_inst[threadIdx.x] = ti;
             __syncthreads();
             for (int j0 = 0; j0 < total; j0 += BLOCK) {
                 const int j = j0 + threadIdx.x;
-                int c = -1, f = 0;
+                int c = -1, f = 0, ci = 0;
+                TreeView t{nullptr, nullptr, nullptr};
                 if (j < total) {
                     // owner: the last item whose offset is <= j
                     int lo = 0, hi = BLOCK - 1;
@@ -166,9 +230,11 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count, StatA
                         if (s_pre[mid] <= j) lo = mid;
                         else hi = mid - 1;
                     }
-                    c = a.child[s_cb[lo] + (j - s_pre[lo])];
-                    f = fanout(a, c);
-                    a.out[c] = 0;  // leaf work, or the identity the folds start from
+                    ci = s_inst[lo];
+                    t = view(a, ci);
+                    c = t.child[s_cb[lo] + (j - s_pre[lo])];
+                    f = fanout(t, c);
+                    t.out[c] = 0;  // leaf work, or the identity the folds start from
                 }
                 const int nch = f > 0 ? (f + a.chunk - 1) / a.chunk : 0;
                 if (a.want_stats) acc.items += f > 0 ? 1 : 0;
@@ -178,10 +244,11 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count, StatA
                 __syncthreads();
                 const int slot = s_base + x0;
                 if (nch > 0) {
-                    const int c0 = a.child_ptr[c];
+                    const int c0 = t.child_ptr[c];
                     for (int k = 0; k < nch; ++k) {
                         const int kb = c0 + k * a.chunk;
-                        a.items[out_base + slot + k] = make_int4(c, kb, min(kb + a.chunk, c0 + f), nch == 1);
+                        a.items[out_base + slot + k] =
+                            make_int4(c, kb, min(kb + a.chunk, c0 + f), (ci << 1) | (nch == 1));
                     }
                 }
                 __syncthreads();  // s_base is rewritten by the next step
@@ -189,15 +256,17 @@ __device__ void level_down(const TreeArgs &a, int l, int start, int count, StatA
         }
     } else {
         for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
-            const int p = a.items[start + i].x;
-            const int cb = a.child_ptr[p], ce = a.child_ptr[p + 1];
+            const int4 d = a.items[start + i];
+            const int p = d.x;
+            const TreeView t = view(a, d.w >> 1);
+            const int cb = t.child_ptr[p], ce = t.child_ptr[p + 1];
             if (a.want_stats) acc.edges += ce - cb;
             for (int e = cb; e < ce; ++e) {
-                const int c = a.child[e];
-                const bool internal = fanout(a, c) > 0;
-                a.out[c] = 0;
+                const int c = t.child[e];
+                const bool internal = fanout(t, c) > 0;
+                t.out[c] = 0;
                 const int slot = wave_reserve(internal, cnt_next);
-                if (internal) a.items[out_base + slot] = make_int4(c, 0, 0, 0);
+                if (internal) a.items[out_base + slot] = make_int4(c, 0, 0, d.w & ~1);
             }
         }
     }
@@ -210,23 +279,25 @@ __device__ void level_up(const TreeArgs &a, int start, int count)
     if constexpr (MODE == WC_GRID) {
         // tiles of items as in the top-down pass: the children's values are
         // folded per item in LDS, then one atomic per item folds into its node
-        __shared__ int s_pre[BLOCK], s_cb[BLOCK], s_acc[BLOCK], s_tmp[2 * (BLOCK / kWave)];
+        __shared__ int s_pre[BLOCK], s_cb[BLOCK], s_acc[BLOCK], s_inst[BLOCK], s_tmp[2 * (BLOCK / kWave)];
         const int T = tile_items<BLOCK>(count);
         for (int tile = blockIdx.x * T; tile < count; tile += gridDim.x * T) {
             const int it = tile + threadIdx.x;
-            int p = -1, cb = 0, len = 0, whole = 0;
+            int p = -1, cb = 0, len = 0, whole = 0, ti = 0;
             if ((int)threadIdx.x < T && it < count) {
                 const int4 d = a.items[start + it];
                 p = d.x;
                 cb = d.y;
                 len = d.z - d.y;
-                whole = d.w;
+                whole = d.w & 1;
+                ti = d.w >> 1;
             }
             int excl, e0, total, e1;
             block_scan2<BLOCK>(len, 0, s_tmp, excl, e0, total, e1);
             s_pre[threadIdx.x] = excl;
             s_cb[threadIdx.x] = cb;
             s_acc[threadIdx.x] = 0;
+            s_inst[threadIdx.x] = ti;
             __syncthreads();
             for (int j = threadIdx.x; j < total; j += BLOCK) {
                 int lo = 0, hi = BLOCK - 1;
@@ -235,7 +306,8 @@ __device__ void level_up(const TreeArgs &a, int start, int count)
                     if (s_pre[mid] <= j) lo = mid;
                     else hi = mid - 1;
                 }
-                const int v = 1 + a.out[a.child[s_cb[lo] + (j - s_pre[lo])]];
+                const TreeView t = view(a, s_inst[lo]);
+                const int v = 1 + t.out[t.child[s_cb[lo] + (j - s_pre[lo])]];
                 if (OP == OP_DESC) atomicAdd(&s_acc[lo], v);
                 else atomicMax(&s_acc[lo], v);
             }
@@ -243,17 +315,20 @@ __device__ void level_up(const TreeArgs &a, int start, int count)
             // an item holding all of its node's children is the node's only
             // contribution: a plain store; split nodes fold atomically
             if (p >= 0) {
-                if (whole) a.out[p] = s_acc[threadIdx.x];
-                else atomic_fold<OP>(&a.out[p], s_acc[threadIdx.x]);
+                int *o = view(a, ti).out;
+                if (whole) o[p] = s_acc[threadIdx.x];
+                else atomic_fold<OP>(&o[p], s_acc[threadIdx.x]);
             }
             __syncthreads();  // the LDS arrays are rewritten by the next tile
         }
     } else {
         for (int i = blockIdx.x * BLOCK + threadIdx.x; i < count; i += gridDim.x * BLOCK) {
-            const int p = a.items[start + i].x;
+            const int4 d = a.items[start + i];
+            const int p = d.x;
+            const TreeView t = view(a, d.w >> 1);
             int acc = 0;
-            for (int e = a.child_ptr[p]; e < a.child_ptr[p + 1]; ++e) acc = fold<OP>(acc, a.out[a.child[e]]);
-            a.out[p] = acc;
+            for (int e = t.child_ptr[p]; e < t.child_ptr[p + 1]; ++e) acc = fold<OP>(acc, t.out[t.child[e]]);
+            t.out[p] = acc;
         }
     }
 }
@@ -298,19 +373,45 @@ __global__ void tree_publish_depth(TreeArgs a, int L)
 
 // ---------------------------------------------------------------- packet queue (wave, block)
 
-// Post-work of a finished node v: fold it into its parent; whoever finishes the
-// parent's last child carries on upward.
+// Post-work state of an internal node is ONE 64-bit word: the number of its
+// children not yet finished in the high half and the fold of the finished
+// ones in the low half.  A finishing child updates both with a single atomic
+// read-modify-write (descendants: one 64-bit add; heights: a compare-and-swap
+// loop), so the count can never be seen before the value it guards and no
+// memory fence is needed on this path.  The child whose update takes the count
+// to zero gets the node's final value back from its own atomic.
+template <int OP>
+__device__ __forceinline__ unsigned long long fold_finished(unsigned long long *w, int contrib, int count)
+{
+    if (OP == OP_DESC) {
+        // the low half never carries: a node's descendants stay below 2^31
+        const unsigned long long add =
+            (unsigned long long)(unsigned int)contrib - ((unsigned long long)(unsigned int)count << 32);
+        return __hip_atomic_fetch_add(w, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
+    }
+    unsigned long long old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), nw;
+    do {
+        const unsigned int lo = (unsigned int)old, hi = (unsigned int)(old >> 32);
+        nw = ((unsigned long long)(hi - (unsigned int)count) << 32) | (unsigned int)max((int)lo, contrib);
+    } while (!__hip_atomic_compare_exchange_weak(w, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT));
+    return nw;
+}
+
+// Post-work of a finished node v with value val: fold it into its parent;
+// whoever finishes the parent's last child stores the parent's value and
+// carries on upward.
 template <int OP>
 __device__ void complete_upward(const TreeArgs &a, int v, int val)
 {
     for (;;) {
         const int p = a.parent[v];
         if (p < 0) return;
-        atomic_fold<OP>(&a.out[p], 1 + val);
-        int left = __hip_atomic_fetch_add(&a.pending[p], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) - 1;
-        if (left != 0) return;
+        const unsigned long long nw = fold_finished<OP>(&a.word[p], 1 + val, 1);
+        if ((nw >> 32) != 0) return;
+        val = (int)(unsigned int)nw;
+        a.out[p] = val;
         v = p;
-        val = __hip_atomic_load(&a.out[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -319,11 +420,11 @@ __device__ void complete_upward(const TreeArgs &a, int v, int val)
 template <int OP>
 __device__ void complete_leaves(const TreeArgs &a, int p, int nleaf)
 {
-    atomic_fold<OP>(&a.out[p], OP == OP_DESC ? nleaf : 1);
-    const int left =
-        __hip_atomic_fetch_add(&a.pending[p], -nleaf, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) - nleaf;
-    if (left != 0) return;
-    complete_upward<OP>(a, p, __hip_atomic_load(&a.out[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long nw = fold_finished<OP>(&a.word[p], OP == OP_DESC ? nleaf : 1, nleaf);
+    if ((nw >> 32) != 0) return;
+    const int val = (int)(unsigned int)nw;
+    a.out[p] = val;
+    complete_upward<OP>(a, p, val);
 }
 
 __global__ void tree_init_queue(TreeArgs a, long long pq_cap)
@@ -340,7 +441,7 @@ __global__ void tree_init_queue(TreeArgs a, long long pq_cap)
             *a.pq_tail = 0;
             *a.outstanding = 0;
         } else {
-            a.pending[0] = f;
+            a.word[0] = (unsigned long long)(unsigned int)f << 32;
             a.nl[0] = 0;
             *a.nl_tail = 1;
             *a.pq_tail = 1;
@@ -405,8 +506,8 @@ __device__ void flush_buffer(const TreeArgs &a, QueueLds<G> &s, StatAcc &acc)
         if (t < k) a.nl[base + t] = s.buf[off + t];
         gsync<G>();
         if (t == 0) {
-            // the nodes (and their pending counts / initial outputs) become
-            // visible before the packet does
+            // the nodes (and their post-work words) become visible before the
+            // packet does
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             atomic_add_dev(a.outstanding, 1);
             const int slot = atomic_add_dev(a.pq_tail, 1);
@@ -507,8 +608,8 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
                 p = s.pk_node[k];
                 c = a.child[s.pk_beg[k] + (j - s.pk_pre[k])];
                 cf = fanout(a, c);
-                a.out[c] = 0;  // leaf work, or the identity the folds start from
-                if (cf > 0) a.pending[c] = cf;
+                if (cf > 0) a.word[c] = (unsigned long long)(unsigned int)cf << 32;  // nothing folded yet
+                else a.out[c] = 0;  // leaf work
             }
             // insert the recursive calls into the group's buffer
             if constexpr (G > kWave) {
@@ -611,125 +712,55 @@ TreeKernels<OP, BLOCK> kernels_for(wc_mode mode)
     return k;
 }
 
+// The level-synchronous modes (flat, grid) over one tree or a batch of trees
+// (all trees' items of one depth in the same level buffer).  n: total nodes,
+// max_n: nodes of the largest tree (bounds the depth).
 template <int OP, int BLOCK>
-wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const Config &cfg, hipStream_t stream,
-                   wc_stats *stats)
+wc_status run_levels(wc_ctx *ctx, TreeArgs a, wc_mode mode, const Config &cfg, int grid, long long n, long long max_n,
+                     const std::vector<TreeInst> *batch, hipStream_t stream, wc_stats *stats)
 {
+    // level-synchronous: levels <= max_n; chunks over all levels <= n + (n-1)/chunk + 1
+    // per tree (the relaunch driver may run up to `window` empty levels past the last one)
     TreeKernels<OP, BLOCK> ks = kernels_for<OP, BLOCK>(mode);
-    // the grid is sized to the residency of the kernel that runs: the queue kernel, or the level kernels
-    const void *main_kernel = ks.queue ? ks.queue : ks.down;
-    const int resident = resident_blocks(ctx, main_kernel, BLOCK);
-    const int grid = std::max(1, std::min(cfg.grid, resident));
-    const long long n = t->n;
-    const int chunk = kWave * cfg.items_per_lane;
-    TreeArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.parent = t->parent;
-    a.child_ptr = t->child_ptr;
-    a.child = t->child;
-    a.out = out;
-    a.n = (int)n;
-    a.chunk = chunk;
-    a.host_ring = ctx->host_ring_dev;
-    a.stats = ctx->dstats;
-    a.want_stats = stats != nullptr;
-    a.wait_ticks = ctx->wait_ticks;
-    a.work_cap = BLOCK * cfg.items_per_lane;
-    if (cfg.driver == 2) {
-        // Basic dynamic parallelism, emulated: the host walks the tree (read back
-        // once) and launches one child kernel per internal node, deepest first.
-        std::vector<int> cp((size_t)n + 1), ch((size_t)std::max<long long>(n - 1, 1));
-        WC_HIP(hipMemcpy(cp.data(), t->child_ptr, sizeof(int) * (size_t)(n + 1), hipMemcpyDeviceToHost));
-        if (n > 1) WC_HIP(hipMemcpy(ch.data(), t->child, sizeof(int) * (size_t)(n - 1), hipMemcpyDeviceToHost));
-        std::vector<int> order;
-        order.reserve((size_t)n);
-        order.push_back(0);
-        for (size_t i = 0; i < order.size(); ++i) {
-            const int v = order[i];
-            if (cp[v] < 0 || cp[v + 1] > n - 1 || cp[v] > cp[v + 1])
-                return fail(WC_EINVAL, "tree: child_ptr out of range");
-            for (int k = cp[v]; k < cp[v + 1]; ++k) {
-                if (ch[k] <= 0 || ch[k] >= n || (long long)order.size() >= n)
-                    return fail(WC_EINVAL, "tree: child list is not a tree rooted at 0");
-                order.push_back(ch[k]);
-            }
-        }
-        wc_status st = begin_call(ctx, stream, stats);
-        if (st != WC_OK) return st;
-        void *zargs[] = {&a};
-        st = launch(ctx, "tree_zero_out", reinterpret_cast<const void *>(&tree_zero_out),
-                    dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)), dim3(256), zargs, stream);
-        long long launches = 0;
-        for (size_t i = order.size(); i-- > 0 && st == WC_OK;) {
-            int v = order[i];
-            if (cp[v + 1] == cp[v]) continue;
-            void *cargs[] = {&a, &v};
-            st = launch(ctx, "tree_child_basic", reinterpret_cast<const void *>(&tree_child_basic<OP>), dim3(1),
-                        dim3(kBasicBlock), cargs, stream);
-            ++launches;
-        }
-        if (st != WC_OK) return st;
-        st = end_call(ctx, stream, stats, 0, cfg.fail_on_overflow);
-        if (stats) {
-            stats->dispatches = launches;
-            stats->items_buffered = launches;
-        }
-        return st;
-    }
-    const bool queue_mode = mode == WC_WAVE || mode == WC_BLOCK;
-    if (queue_mode) {
-        a.work_cap = (mode == WC_WAVE ? kWave : BLOCK) * cfg.items_per_lane;
-        long long pq_cap = n;
-        size_t need = padded(n * 4) * 2 + padded(pq_cap * 8) + 4 * padded(4);
-        wc_status st = pool_reserve(ctx, need, stream);
-        if (st != WC_OK) return st;
-        a.nl = pool_take<int>(ctx, n);
-        a.pending = pool_take<int>(ctx, n);
-        a.pq = pool_take<long long>(ctx, pq_cap);
-        a.pq_cap = pq_cap;
-        a.nl_tail = pool_take<int>(ctx, 1);
-        a.pq_head = pool_take<int>(ctx, 1);
-        a.pq_tail = pool_take<int>(ctx, 1);
-        a.outstanding = pool_take<int>(ctx, 1);
-        st = begin_call(ctx, stream, stats);
-        if (st != WC_OK) return st;
-        int ig = (int)std::min<long long>((pq_cap + 255) / 256, 4096);
-        void *iargs[] = {&a, &pq_cap};
-        st = launch(ctx, "tree_init_queue", reinterpret_cast<const void *>(&tree_init_queue), dim3(ig), dim3(256),
-                    iargs, stream);
-        void *args[] = {&a};
-        if (st == WC_OK)
-            st = launch(ctx, "tree_publish_root", reinterpret_cast<const void *>(&tree_publish_root), dim3(1),
-                        dim3(64), args, stream);
-        if (st == WC_OK)
-            st = launch(ctx, mode == WC_WAVE ? "tree_queue_wave" : "tree_queue_block", ks.queue, dim3(grid),
-                        dim3(BLOCK), args, stream);
-        if (st != WC_OK) return st;
-        // the queue's waits are bounded: a wave that gave up is reported
-        return end_call(ctx, stream, stats, 0, cfg.fail_on_overflow, true);
-    }
-    // level-synchronous: levels <= n; chunks over all levels <= n + (n-1)/chunk + 1
-    // (the relaunch driver may run up to `window` empty levels past the last one)
-    const long long max_levels = n + 1;
+    const int count = batch ? (int)batch->size() : 1;
+    const long long max_levels = max_n + 1;
     const long long lvl_len = max_levels + 16;
-    long long cap = mode == WC_GRID ? n + n / chunk + 2 : n + 1;
-    size_t need = 2 * padded(lvl_len * 4) + padded(cap * 16);
+    const int chunk = a.chunk;
+    long long cap = mode == WC_GRID ? n + n / chunk + 2LL * count : n + count;
+    const size_t inst_bytes = batch ? sizeof(TreeInst) * batch->size() : 0;
+    size_t need = 2 * padded(lvl_len * 4) + padded(cap * 16) + padded(inst_bytes);
     wc_status st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     a.lvl_start = pool_take<int>(ctx, lvl_len);
     a.lvl_count = pool_take<int>(ctx, lvl_len);
     a.items = pool_take<int4>(ctx, cap);
     a.item_cap = cap;
+    if (batch) {
+        a.inst = reinterpret_cast<const TreeInst *>(pool_take<char>(ctx, inst_bytes));
+        a.count = count;
+    }
     st = begin_call(ctx, stream, stats);
     if (st != WC_OK) return st;
-    {
-        void *args[] = {&a};
-        st = launch(ctx, "tree_init_levels",
-                    mode == WC_GRID ? reinterpret_cast<const void *>(&tree_init_levels)
-                                    : reinterpret_cast<const void *>(&tree_init_levels_flat),
-                    dim3(1), dim3(64), args, stream);
+    if (batch) {
+        st = stage_to_device(ctx, const_cast<TreeInst *>(a.inst), batch->data(), inst_bytes, stream);
         if (st != WC_OK) return st;
     }
+    // level 0: the root(s)
+    auto init_levels = [&]() -> wc_status {
+        void *args[] = {&a};
+        if (batch) {
+            int grid_mode = mode == WC_GRID;
+            void *bargs[] = {&a, &grid_mode};
+            return launch(ctx, "tree_init_levels", reinterpret_cast<const void *>(&tree_init_batch), dim3(1),
+                          dim3(256), bargs, stream);
+        }
+        return launch(ctx, "tree_init_levels",
+                      mode == WC_GRID ? reinterpret_cast<const void *>(&tree_init_levels)
+                                      : reinterpret_cast<const void *>(&tree_init_levels_flat),
+                      dim3(1), dim3(64), args, stream);
+    };
+    st = init_levels();
+    if (st != WC_OK) return st;
     // A call repeated on the same tree replays a captured graph of all levels
     // (down to the recorded depth plus one empty level, then up); the empty
     // level publishes its count, and a non-zero count (a deeper tree at the same
@@ -743,6 +774,9 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
         const long long extra[4] = {(long long)mode, (long long)OP, (long long)grid, (long long)BLOCK};
         b = reinterpret_cast<const unsigned char *>(extra);
         for (size_t k = 0; k < sizeof(extra); ++k) key = (key ^ b[k]) * 1099511628211ull;
+        // a batch is the same call only with the same trees and outputs
+        b = reinterpret_cast<const unsigned char *>(batch ? batch->data() : nullptr);
+        for (size_t k = 0; k < inst_bytes; ++k) key = (key ^ b[k]) * 1099511628211ull;
     }
     wc_ctx::TreeGraph *tg = nullptr;
     if (!ctx->timing)
@@ -765,11 +799,11 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
         *tg = wc_ctx::TreeGraph{};
         st = begin_call(ctx, stream, stats);
         if (st != WC_OK) return st;
-        void *args[] = {&a};
-        st = launch(ctx, "tree_init_levels",
-                    mode == WC_GRID ? reinterpret_cast<const void *>(&tree_init_levels)
-                                    : reinterpret_cast<const void *>(&tree_init_levels_flat),
-                    dim3(1), dim3(64), args, stream);
+        if (batch) {
+            st = stage_to_device(ctx, const_cast<TreeInst *>(a.inst), batch->data(), inst_bytes, stream);
+            if (st != WC_OK) return st;
+        }
+        st = init_levels();
         if (st != WC_OK) return st;
     }
     const int window = 4;
@@ -837,6 +871,108 @@ wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const 
     return end_call(ctx, stream, stats, levels, cfg.fail_on_overflow);
 }
 
+template <int OP, int BLOCK>
+wc_status run_tree(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const Config &cfg, hipStream_t stream,
+                   wc_stats *stats)
+{
+    TreeKernels<OP, BLOCK> ks = kernels_for<OP, BLOCK>(mode);
+    // the grid is sized to the residency of the kernel that runs: the queue kernel, or the level kernels
+    const void *main_kernel = ks.queue ? ks.queue : ks.down;
+    const int resident = resident_blocks(ctx, main_kernel, BLOCK);
+    const int grid = std::max(1, std::min(cfg.grid, resident));
+    const long long n = t->n;
+    const int chunk = kWave * cfg.items_per_lane;
+    TreeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.parent = t->parent;
+    a.child_ptr = t->child_ptr;
+    a.child = t->child;
+    a.out = out;
+    a.n = (int)n;
+    a.chunk = chunk;
+    a.host_ring = ctx->host_ring_dev;
+    a.stats = ctx->dstats;
+    a.want_stats = stats != nullptr;
+    a.wait_ticks = ctx->wait_ticks;
+    a.work_cap = BLOCK * cfg.items_per_lane;
+    if (cfg.driver == 2) {
+        // no pool workspace (plan-only mode: nothing to record, nothing enqueued)
+        if (ctx->plan_only) return pool_reserve(ctx, 0, stream);
+        // Basic dynamic parallelism, emulated: the host walks the tree (read back
+        // once) and launches one child kernel per internal node, deepest first.
+        std::vector<int> cp((size_t)n + 1), ch((size_t)std::max<long long>(n - 1, 1));
+        WC_HIP(hipMemcpy(cp.data(), t->child_ptr, sizeof(int) * (size_t)(n + 1), hipMemcpyDeviceToHost));
+        if (n > 1) WC_HIP(hipMemcpy(ch.data(), t->child, sizeof(int) * (size_t)(n - 1), hipMemcpyDeviceToHost));
+        std::vector<int> order;
+        order.reserve((size_t)n);
+        order.push_back(0);
+        for (size_t i = 0; i < order.size(); ++i) {
+            const int v = order[i];
+            if (cp[v] < 0 || cp[v + 1] > n - 1 || cp[v] > cp[v + 1])
+                return fail(WC_EINVAL, "tree: child_ptr out of range");
+            for (int k = cp[v]; k < cp[v + 1]; ++k) {
+                if (ch[k] <= 0 || ch[k] >= n || (long long)order.size() >= n)
+                    return fail(WC_EINVAL, "tree: child list is not a tree rooted at 0");
+                order.push_back(ch[k]);
+            }
+        }
+        wc_status st = begin_call(ctx, stream, stats);
+        if (st != WC_OK) return st;
+        void *zargs[] = {&a};
+        st = launch(ctx, "tree_zero_out", reinterpret_cast<const void *>(&tree_zero_out),
+                    dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)), dim3(256), zargs, stream);
+        long long launches = 0;
+        for (size_t i = order.size(); i-- > 0 && st == WC_OK;) {
+            int v = order[i];
+            if (cp[v + 1] == cp[v]) continue;
+            void *cargs[] = {&a, &v};
+            st = launch(ctx, "tree_child_basic", reinterpret_cast<const void *>(&tree_child_basic<OP>), dim3(1),
+                        dim3(kBasicBlock), cargs, stream);
+            ++launches;
+        }
+        if (st != WC_OK) return st;
+        st = end_call(ctx, stream, stats, 0, cfg.fail_on_overflow);
+        if (stats) {
+            stats->dispatches = launches;
+            stats->items_buffered = launches;
+        }
+        return st;
+    }
+    const bool queue_mode = mode == WC_WAVE || mode == WC_BLOCK;
+    if (queue_mode) {
+        a.work_cap = (mode == WC_WAVE ? kWave : BLOCK) * cfg.items_per_lane;
+        long long pq_cap = n;
+        size_t need = padded(n * 4) + padded(n * 8) + padded(pq_cap * 8) + 4 * padded(4);
+        wc_status st = pool_reserve(ctx, need, stream);
+        if (st != WC_OK) return st;
+        a.nl = pool_take<int>(ctx, n);
+        a.word = pool_take<unsigned long long>(ctx, n);
+        a.pq = pool_take<long long>(ctx, pq_cap);
+        a.pq_cap = pq_cap;
+        a.nl_tail = pool_take<int>(ctx, 1);
+        a.pq_head = pool_take<int>(ctx, 1);
+        a.pq_tail = pool_take<int>(ctx, 1);
+        a.outstanding = pool_take<int>(ctx, 1);
+        st = begin_call(ctx, stream, stats);
+        if (st != WC_OK) return st;
+        int ig = (int)std::min<long long>((pq_cap + 255) / 256, 4096);
+        void *iargs[] = {&a, &pq_cap};
+        st = launch(ctx, "tree_init_queue", reinterpret_cast<const void *>(&tree_init_queue), dim3(ig), dim3(256),
+                    iargs, stream);
+        void *args[] = {&a};
+        if (st == WC_OK)
+            st = launch(ctx, "tree_publish_root", reinterpret_cast<const void *>(&tree_publish_root), dim3(1),
+                        dim3(64), args, stream);
+        if (st == WC_OK)
+            st = launch(ctx, mode == WC_WAVE ? "tree_queue_wave" : "tree_queue_block", ks.queue, dim3(grid),
+                        dim3(BLOCK), args, stream);
+        if (st != WC_OK) return st;
+        // the queue's waits are bounded: a wave that gave up is reported
+        return end_call(ctx, stream, stats, 0, cfg.fail_on_overflow, true);
+    }
+    return run_levels<OP, BLOCK>(ctx, a, mode, cfg, grid, n, n, nullptr, stream, stats);
+}
+
 template <int OP>
 wc_status run_tree_block(wc_ctx *ctx, const wc_tree *t, int *out, wc_mode mode, const Config &cfg,
                          hipStream_t stream, wc_stats *stats)
@@ -869,10 +1005,88 @@ wc_status tree_entry(int op, wc_ctx *ctx, const wc_tree *t, int32_t *out, wc_mod
                          : run_tree_block<OP_HEIGHT>(ctx, t, out, mode, cfg, stream, stats);
 }
 
+// Many trees in one sequence of level launches (flat or grid mode): every
+// level kernel takes the items of that depth of all trees, so grid mode
+// consolidates the recursive calls of every tree into one buffer per level.
+template <int OP, int BLOCK>
+wc_status run_tree_batch(wc_ctx *ctx, int32_t count, const wc_tree *trees, int32_t *const *out, wc_mode mode,
+                         const Config &cfg, hipStream_t stream, wc_stats *stats)
+{
+    TreeKernels<OP, BLOCK> ks = kernels_for<OP, BLOCK>(mode);
+    const int resident = resident_blocks(ctx, ks.down, BLOCK);
+    const int grid = std::max(1, std::min(cfg.grid, resident));
+    std::vector<TreeInst> inst((size_t)count);
+    long long total = 0, max_n = 1;
+    for (int i = 0; i < count; ++i) {
+        inst[i] = TreeInst{trees[i].child_ptr, trees[i].child, out[i], trees[i].n};
+        total += trees[i].n;
+        max_n = std::max<long long>(max_n, trees[i].n);
+    }
+    if (total > 0x7fffffffLL) return fail(WC_EINVAL, "tree batch: more than 2^31 nodes in one batch");
+    TreeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = (int)total;
+    a.chunk = kWave * cfg.items_per_lane;
+    a.host_ring = ctx->host_ring_dev;
+    a.stats = ctx->dstats;
+    a.want_stats = stats != nullptr;
+    a.wait_ticks = ctx->wait_ticks;
+    return run_levels<OP, BLOCK>(ctx, a, mode, cfg, grid, total, max_n, &inst, stream, stats);
+}
+
+wc_status tree_batch_entry(int op, wc_ctx *ctx, int32_t count, const wc_tree *trees, int32_t *const *out,
+                           wc_mode mode, const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+{
+    if (!ctx || count < 0 || (count > 0 && (!trees || !out))) return fail(WC_EINVAL, "tree batch: NULL argument");
+    if (mode != WC_FLAT && mode != WC_GRID)
+        return fail(WC_EINVAL, "tree batch: flat and grid modes only (the queue modes run one tree per call)");
+    if (count > (1 << 30)) return fail(WC_EINVAL, "tree batch: too many trees");
+    for (int i = 0; i < count; ++i) {
+        const wc_tree &t = trees[i];
+        if (t.n < 1) return fail(WC_EINVAL, "tree batch: tree " + std::to_string(i) + " has no root");
+        if (!t.child_ptr || !out[i] || (t.n > 1 && !t.child))
+            return fail(WC_EINVAL, "tree batch: NULL array in tree " + std::to_string(i));
+    }
+    if (count == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return WC_OK;
+    }
+    WC_HIP(hipSetDevice(ctx->device));
+    Config cfg;
+    wc_status st = resolve_tune(ctx, "tree", mode, tune, ctx->num_cus * 8, &cfg);
+    if (st != WC_OK) return st;
+    if (cfg.driver != 0) return fail(WC_EINVAL, "tree batch: only the relaunch driver (driver = 0) applies");
+    if (tune && tune->grid_blocks > 0) cfg.grid = tune->grid_blocks;
+    else cfg.grid = 1 << 30;
+    auto run = [&](auto opc) -> wc_status {
+        constexpr int OPV = decltype(opc)::value;
+        switch (cfg.block) {
+        case 64: return run_tree_batch<OPV, 64>(ctx, count, trees, out, mode, cfg, stream, stats);
+        case 128: return run_tree_batch<OPV, 128>(ctx, count, trees, out, mode, cfg, stream, stats);
+        case 512: return run_tree_batch<OPV, 512>(ctx, count, trees, out, mode, cfg, stream, stats);
+        case 1024: return run_tree_batch<OPV, 1024>(ctx, count, trees, out, mode, cfg, stream, stats);
+        default: return run_tree_batch<OPV, 256>(ctx, count, trees, out, mode, cfg, stream, stats);
+        }
+    };
+    return op == OP_DESC ? run(std::integral_constant<int, OP_DESC>{}) : run(std::integral_constant<int, OP_HEIGHT>{});
+}
+
 }  // namespace
 }  // namespace wc
 
 using namespace wc;
+
+extern "C" wc_status wc_tree_descendants_batch(wc_ctx *ctx, int32_t count, const wc_tree *trees, int32_t *const *desc,
+                                               wc_mode mode, const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+{
+    return tree_batch_entry(OP_DESC, ctx, count, trees, desc, mode, tune, stream, stats);
+}
+
+extern "C" wc_status wc_tree_height_batch(wc_ctx *ctx, int32_t count, const wc_tree *trees, int32_t *const *height,
+                                          wc_mode mode, const wc_tune *tune, hipStream_t stream, wc_stats *stats)
+{
+    return tree_batch_entry(OP_HEIGHT, ctx, count, trees, height, mode, tune, stream, stats);
+}
 
 extern "C" wc_status wc_tree_descendants(wc_ctx *ctx, const wc_tree *t, int32_t *desc, wc_mode mode,
                                          const wc_tune *tune, hipStream_t stream, wc_stats *stats)

@@ -11,6 +11,15 @@ tree requests through wc_tree_descendants / wc_tree_height.
 Each result is the same as the request run alone (bit-identical distances;
 SpMV results bit-identical for a fixed mode and tune).
 
+Device memory is budgeted exactly.  A request holds its output from admission
+to completion; a batch also needs its worker's consolidation workspace (the
+context pool), which the backend computes with the library's plan-only mode (the
+bytes the calls would carve, nothing enqueued).  A batch whose workspace exceeds
+its worker's pool is cut down; a single request that still needs a larger pool
+is dispatched only when the growth fits the remaining budget (pools never
+shrink, so growth is charged for good), otherwise it waits for memory to free.
+The budget is measured after the workers' contexts (and their pools) exist.
+
 Only the scheduling lives here; every request's arithmetic runs in libwc.  The
 device side is a backend object, so the scheduling can be exercised on the
 CPU with a stand-in backend.
@@ -59,6 +68,7 @@ class Admission:
         self.slots = 0
         self.peak_used = 0
         self.peak_slots = 0
+        self.pool_growth = 0  # bytes of pool growth charged so far (never released)
 
     def fits_ever(self, nbytes: int) -> bool:
         return nbytes <= self.budget
@@ -77,17 +87,21 @@ class Admission:
         self.slots -= 1
         assert self.used >= 0 and self.slots >= 0
 
+    def try_grow(self, nbytes: int) -> bool:
+        """Charges a pool growth for good (pools never shrink), if it fits."""
+        if self.used + nbytes > self.budget:
+            return False
+        self.used += nbytes
+        self.pool_growth += nbytes
+        self.peak_used = max(self.peak_used, self.used)
+        return True
+
 
 def request_bytes(kind: int, n: int, m: int) -> int:
-    """Device bytes a request holds while admitted: its output plus its share
-    of the consolidation workspace (SSSP: distances, frontier array, grid chunk
-    buffer; SpMV: y plus row bins, chunks, partials and split-row entries;
-    trees (m unused): the output plus the level buffers)."""
-    if kind == SSSP:
-        return 4 * n + 4 * n + 16 * (n + m // 256 + 1)
-    if kind in TREE_KINDS:
-        return 4 * n + 8 * (n + 17) + 16 * (n + n // 128 + 2)
-    return 4 * n + 16 * n + 20 * (n + m // 256 + 1) + 16 * n
+    """Device bytes a request holds from admission to completion: its output
+    (n 32-bit distances, values or tree results; m unused).  The consolidation
+    workspace lives in the worker's pool and is budgeted per batch."""
+    return 4 * n
 
 
 def poisson_requests(count: int, rate: float, sources_per_graph, n_x: int, seed: int, sssp_fraction: float = 0.5,
@@ -141,13 +155,17 @@ class ResidentGraph:
 
 
 class GpuBackend:
-    """libwc on one device: one context and one stream per worker."""
+    """libwc on one device: one context and one stream per worker, and one
+    plan-only context that computes the workspace of a batch."""
 
-    def __init__(self, graphs, device: int = 0, sssp_mode="grid", spmv_mode="grid", trees=(), tree_mode="grid"):
+    def __init__(self, graphs, device: int = 0, sssp_mode="grid", spmv_mode="grid", trees=(), tree_mode="grid",
+                 pool_bytes: int = 256 << 20):
         self.graphs = graphs
         self.trees = list(trees)  # wc.DeviceTree
         self.device = device
         self.sssp_mode, self.spmv_mode, self.tree_mode = sssp_mode, spmv_mode, tree_mode
+        self.pool_bytes0 = pool_bytes
+        self._planner = None
 
     def free_bytes(self) -> int:
         import torch
@@ -156,10 +174,35 @@ class GpuBackend:
     def worker_state(self):
         import torch
         from . import wc
-        return wc.Context(self.device), torch.cuda.Stream(device=self.device)
+        return wc.Context(self.device, pool_bytes=self.pool_bytes0), torch.cuda.Stream(device=self.device)
 
     def close_state(self, state):
         state[0].close()
+
+    def close(self):
+        if self._planner is not None:
+            self._planner.close()
+            self._planner = None
+
+    def pool_bytes(self, state) -> int:
+        return state[0].pool_info()[0]
+
+    def pool_grows(self, state) -> int:
+        return state[0].pool_info()[1]
+
+    def grow(self, state, nbytes: int):
+        state[0].reserve(nbytes)
+
+    def workspace(self, batch) -> int:
+        """Pool bytes the batch's calls carve on a worker (the library's own
+        plan; the calls run one after another, so the largest one counts)."""
+        from . import wc
+        import torch
+        if self._planner is None:
+            self._planner = wc.Context(self.device, pool_bytes=1 << 20)
+            # stands in for outputs not allocated yet: a plan-only call writes nothing
+            self._placeholder = torch.empty(1, dtype=torch.int32, device=f"cuda:{self.device}")
+        return self._planner.workspace_bytes(lambda c: self._issue(c, batch, None, plan=True))
 
     def allocate(self, r):
         import torch
@@ -170,23 +213,28 @@ class GpuBackend:
         dt = torch.int32 if r.kind == SSSP else torch.float32
         r.out = torch.empty(g.n, dtype=dt, device=f"cuda:{self.device}")
 
+    def _issue(self, ctx, batch, stream, plan=False):
+        def out(r):
+            return r.out if not plan or r.out is not None else self._placeholder
+        sssp = [r for r in batch if r.kind == SSSP]
+        if sssp:
+            gs = [self.graphs[r.graph] for r in sssp]
+            ctx.sssp_batch([g.csr for g in gs], [g.w for g in gs], [r.arg for r in sssp],
+                           modes=[self.sssp_mode] * len(sssp), outs=[out(r) for r in sssp], stream=stream)
+        for r in batch:
+            if r.kind == SPMV:
+                g = self.graphs[r.graph]
+                ctx.spmv(g.csr, g.val, g.xs[r.arg], mode=self.spmv_mode, out=out(r), stream=stream)
+            elif r.kind in TREE_KINDS:
+                fn = ctx.tree_descendants if r.kind == TREE_DESC else ctx.tree_height
+                fn(self.trees[r.graph], mode=self.tree_mode, out=out(r), stream=stream)
+
     def execute(self, state, batch):
         """Runs one batch on the worker's stream and waits for it."""
         import torch
         ctx, stream = state
         with torch.cuda.stream(stream):
-            sssp = [r for r in batch if r.kind == SSSP]
-            if sssp:
-                gs = [self.graphs[r.graph] for r in sssp]
-                ctx.sssp_batch([g.csr for g in gs], [g.w for g in gs], [r.arg for r in sssp],
-                               modes=[self.sssp_mode] * len(sssp), outs=[r.out for r in sssp], stream=stream)
-            for r in batch:
-                if r.kind == SPMV:
-                    g = self.graphs[r.graph]
-                    ctx.spmv(g.csr, g.val, g.xs[r.arg], mode=self.spmv_mode, out=r.out, stream=stream)
-                elif r.kind in TREE_KINDS:
-                    fn = ctx.tree_descendants if r.kind == TREE_DESC else ctx.tree_height
-                    fn(self.trees[r.graph], mode=self.tree_mode, out=r.out, stream=stream)
+            self._issue(ctx, batch, stream)
         stream.synchronize()
 
 
@@ -201,13 +249,16 @@ class _Worker(threading.Thread):
     def run(self):
         be = self.server.backend
         while True:
-            batch = self.inbox.get()
-            if batch is None:
+            item = self.inbox.get()
+            if item is None:
                 break
+            batch, grow_to = item
             now = self.server.clock()
             for r in batch:
                 r.t_start = now
             try:
+                if grow_to:
+                    be.grow(self.state, grow_to)  # charged to the budget by the scheduler
                 be.execute(self.state, batch)
             except Exception as e:  # a failed batch must not poison the others
                 for r in batch:
@@ -229,12 +280,16 @@ class Server:
         self.backend = backend
         self.max_batch = max_batch
         self.keep_outputs = keep_outputs
+        self._done: queue.Queue = queue.Queue()
+        self._t0 = time.perf_counter()
+        # the workers' contexts (and their pools) exist before the budget is measured
+        self.workers = [_Worker(self, i) for i in range(workers)]
+        self.pool = [int(backend.pool_bytes(w.state)) for w in self.workers]
         if budget_bytes is None:
             budget_bytes = backend.free_bytes() // 2
         self.admission = Admission(budget_bytes, max_slots)
-        self._done: queue.Queue = queue.Queue()
-        self._t0 = time.perf_counter()
-        self.workers = [_Worker(self, i) for i in range(workers)]
+        self.grows = 0
+        self._ws_cache = {}
         for w in self.workers:
             w.start()
 
@@ -244,6 +299,32 @@ class Server:
     def close(self):
         for w in self.workers:
             w.close()
+        if hasattr(self.backend, "close"):
+            self.backend.close()
+
+    def _single_workspace(self, r) -> int:
+        key = (r.kind, r.graph)
+        if key not in self._ws_cache:
+            self._ws_cache[key] = int(self.backend.workspace([r]))
+        return self._ws_cache[key]
+
+    def _fit_batch(self, wi, batch, ready):
+        """Cuts `batch` until its workspace fits worker wi's pool (the cut
+        requests go back to the front of `ready`).  Returns the pool size the
+        worker must grow to first (0: none), or -1 when even the first request
+        needs a growth the budget cannot take now (everything goes back)."""
+        need = int(self.backend.workspace(batch))
+        while need > self.pool[wi] and len(batch) > 1:
+            ready.appendleft(batch.pop())
+            need = int(self.backend.workspace(batch))
+        if need <= self.pool[wi]:
+            return 0
+        if not self.admission.try_grow(need - self.pool[wi]):
+            ready.appendleft(batch.pop())
+            return -1
+        self.pool[wi] = need
+        self.grows += 1
+        return need
 
     def _complete(self, wi, batch, idle):
         idle.add(wi)
@@ -256,14 +337,16 @@ class Server:
     def run(self, requests, time_limit: float = 120.0):
         """Serves `requests` (sorted by t_arrive) in real time and returns them with
         admission, start and completion times filled in."""
+        largest_pool = max(self.pool)
         for r in requests:
             if r.kind in TREE_KINDS:
                 r.nbytes = request_bytes(r.kind, self.backend.trees[r.graph].n, 0)
             else:
                 g = self.backend.graphs[r.graph]
                 r.nbytes = request_bytes(r.kind, g.n, g.m)
-            if not self.admission.fits_ever(r.nbytes):
-                raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, more than the whole budget")
+            growth = max(0, self._single_workspace(r) - largest_pool)
+            if not self.admission.fits_ever(r.nbytes + growth):
+                raise ValueError(f"request {r.rid} needs {r.nbytes + growth} bytes, more than the whole budget")
         self._t0 = time.perf_counter()
         waiting: collections.deque = collections.deque()
         ready: collections.deque = collections.deque()
@@ -282,11 +365,16 @@ class Server:
                 r.t_admit = now
                 self.backend.allocate(r)
                 ready.append(r)
-            # batched on arrival: every idle worker takes what is ready now
+            # batched on arrival: every idle worker takes what is ready now, as
+            # much as its pool holds (a growth only when the budget takes it)
             while ready and idle:
-                wi = idle.pop()
+                wi = max(idle, key=lambda i: self.pool[i])
                 batch = [ready.popleft() for _ in range(min(self.max_batch, len(ready)))]
-                self.workers[wi].inbox.put(batch)
+                grow_to = self._fit_batch(wi, batch, ready)
+                if grow_to < 0:
+                    break  # waits for completions to free memory
+                idle.discard(wi)
+                self.workers[wi].inbox.put((batch, grow_to))
             # completions free memory and slots for the next admissions
             progressed = False
             while True:

@@ -18,14 +18,17 @@ LIB_PATH = os.path.join(_HERE, "libwc.so")
 
 FLAT, WAVE, BLOCK, GRID = 0, 1, 2, 3
 MODES = {"flat": FLAT, "wave": WAVE, "block": BLOCK, "grid": GRID}
-STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: "WC_ETIMEOUT", -5: "WC_EHIP"}
+STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: "WC_ETIMEOUT", -5: "WC_EHIP",
+          1: "WC_PLANNED"}
 
 # C-ABI symbols declared in include/wc.h
-EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_pagerank", "wc_color", "wc_tree_descendants",
-           "wc_tree_height",
-           "wc_sssp_batch",
-           "wc_ctx_set_timing", "wc_ctx_set_wait_limit", "wc_ctx_kernel_stats", "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size",
-           "wc_kc_config", "wc_default_tune")
+EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_spmv_prepare",
+           "wc_spmv_hot", "wc_pagerank",
+           "wc_color", "wc_tree_descendants", "wc_tree_height", "wc_tree_descendants_batch", "wc_tree_height_batch",
+           "wc_sssp_batch", "wc_ctx_set_timing", "wc_ctx_set_wait_limit", "wc_ctx_set_plan_only",
+           "wc_ctx_planned_bytes", "wc_ctx_pool_info", "wc_ctx_reserve", "wc_ctx_kernel_stats",
+           "wc_ctx_kernel_record", "wc_last_error", "wc_version", "wc_per_buffer_size", "wc_kc_config",
+           "wc_default_tune")
 
 
 class WcError(RuntimeError):
@@ -47,7 +50,7 @@ class CTree(ctypes.Structure):
 class Tune(ctypes.Structure):
     _fields_ = [("threshold", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("items_per_lane", ctypes.c_int32), ("driver", ctypes.c_int32), ("allow_fallback", ctypes.c_int32),
-                ("buf_capacity", ctypes.c_int64)]
+                ("buf_capacity", ctypes.c_int64), ("buffer_alloc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,6 +89,11 @@ def load_library():
     lib.wc_bfs.argtypes = [vp, c.POINTER(CCsr), c.c_int32, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_spmv.restype = c.c_int
     lib.wc_spmv.argtypes = [vp, c.POINTER(CCsr), vp, vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_spmv_prepare.restype = c.c_int
+    lib.wc_spmv_prepare.argtypes = [vp, c.POINTER(CCsr), c.c_int32, vp, vp, vp]
+    lib.wc_spmv_hot.restype = c.c_int
+    lib.wc_spmv_hot.argtypes = [vp, c.POINTER(CCsr), c.c_int32, vp, vp, vp, vp, c.c_int, c.POINTER(Tune), vp,
+                                c.POINTER(Stats)]
     lib.wc_color.restype = c.c_int
     lib.wc_color.argtypes = [vp, c.POINTER(CCsr), vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_pagerank.restype = c.c_int
@@ -95,11 +103,24 @@ def load_library():
         fn = getattr(lib, name)
         fn.restype = c.c_int
         fn.argtypes = [vp, c.POINTER(CTree), vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    for name in ("wc_tree_descendants_batch", "wc_tree_height_batch"):
+        fn = getattr(lib, name)
+        fn.restype = c.c_int
+        fn.argtypes = [vp, c.c_int32, c.POINTER(CTree), c.POINTER(vp), c.c_int, c.POINTER(Tune), vp,
+                       c.POINTER(Stats)]
     lib.wc_sssp_batch.restype = c.c_int
     lib.wc_sssp_batch.argtypes = [vp, c.c_int32, c.POINTER(CCsr), c.POINTER(vp), c.POINTER(c.c_int32), c.POINTER(vp),
                                   c.POINTER(c.c_int), c.POINTER(Tune), c.c_int32, vp, c.POINTER(Stats)]
     lib.wc_ctx_set_timing.restype = c.c_int
     lib.wc_ctx_set_timing.argtypes = [vp, c.c_int]
+    lib.wc_ctx_set_plan_only.restype = c.c_int
+    lib.wc_ctx_set_plan_only.argtypes = [vp, c.c_int]
+    lib.wc_ctx_planned_bytes.restype = c.c_int
+    lib.wc_ctx_planned_bytes.argtypes = [vp, c.POINTER(c.c_size_t)]
+    lib.wc_ctx_pool_info.restype = c.c_int
+    lib.wc_ctx_pool_info.argtypes = [vp, c.POINTER(c.c_size_t), c.POINTER(c.c_int64)]
+    lib.wc_ctx_reserve.restype = c.c_int
+    lib.wc_ctx_reserve.argtypes = [vp, c.c_size_t]
     lib.wc_ctx_set_wait_limit.restype = c.c_int
     lib.wc_ctx_set_wait_limit.argtypes = [vp, c.c_int64]
     lib.wc_ctx_kernel_stats.restype = c.c_int
@@ -121,7 +142,8 @@ def load_library():
 
 
 def _check(status: int):
-    if status != 0:
+    # WC_PLANNED (1): a plan-only context recorded the call's workspace
+    if status != 0 and status != 1:
         raise WcError(status, load_library().wc_last_error().decode())
 
 
@@ -230,6 +252,29 @@ class Context:
     def set_timing(self, enable: bool):
         _check(load_library().wc_ctx_set_timing(self._ptr, 1 if enable else 0))
 
+    def workspace_bytes(self, fn) -> int:
+        """Pool bytes the calls made by fn(self) would carve (plan-only mode:
+        nothing is enqueued; results of those calls are not computed)."""
+        lib = load_library()
+        _check(lib.wc_ctx_set_plan_only(self._ptr, 1))
+        try:
+            fn(self)
+            b = ctypes.c_size_t()
+            _check(lib.wc_ctx_planned_bytes(self._ptr, ctypes.byref(b)))
+            return int(b.value)
+        finally:
+            lib.wc_ctx_set_plan_only(self._ptr, 0)
+
+    def pool_info(self):
+        """(pool bytes, number of times the pool has grown)."""
+        b, g = ctypes.c_size_t(), ctypes.c_int64()
+        _check(load_library().wc_ctx_pool_info(self._ptr, ctypes.byref(b), ctypes.byref(g)))
+        return int(b.value), int(g.value)
+
+    def reserve(self, nbytes: int):
+        """Grow the pool to at least nbytes now (waits for the device)."""
+        _check(load_library().wc_ctx_reserve(self._ptr, int(nbytes)))
+
     def set_wait_limit(self, microseconds: int):
         """Bound of the device-side waits of later calls (<= 0: the default 2 s)."""
         _check(load_library().wc_ctx_set_wait_limit(self._ptr, int(microseconds)))
@@ -315,6 +360,28 @@ class Context:
                                       _stream_ptr(stream), ctypes.byref(st) if st else None))
         return (y, st.as_dict()) if stats else y
 
+    def spmv_prepare(self, a: DeviceCSR, hot: int, stream=None):
+        """Hot-column layout of a: (DeviceCSR with the remapped columns, hot_ids tensor)."""
+        col_hot = torch.empty(max(a.m, 1), dtype=torch.int32, device=a.row_ptr.device)
+        hot_ids = torch.empty(max(hot, 1), dtype=torch.int32, device=a.row_ptr.device)
+        ca = a.c()
+        _check(load_library().wc_spmv_prepare(self._ptr, ctypes.byref(ca), int(hot), col_hot.data_ptr(),
+                                              hot_ids.data_ptr(), _stream_ptr(stream)))
+        return DeviceCSR(a.n, a.row_ptr, col_hot[:a.m]), hot_ids[:hot]
+
+    def spmv_hot(self, a_hot: DeviceCSR, hot_ids: torch.Tensor, val: torch.Tensor, x: torch.Tensor, mode="grid",
+                 tune: Tune | None = None, out: torch.Tensor | None = None, stream=None, stats: bool = False):
+        """y = A x in the hot-column layout from spmv_prepare."""
+        y = out if out is not None else torch.empty(a_hot.n, dtype=torch.float32, device=a_hot.row_ptr.device)
+        st = Stats() if stats else None
+        ca = a_hot.c()
+        hot = int(hot_ids.numel())
+        _check(load_library().wc_spmv_hot(self._ptr, ctypes.byref(ca), hot, hot_ids.data_ptr() if hot else None,
+                                          val.data_ptr() if a_hot.m else None, x.data_ptr(), y.data_ptr(),
+                                          _mode(mode), ctypes.byref(tune) if tune else None, _stream_ptr(stream),
+                                          ctypes.byref(st) if st else None))
+        return (y, st.as_dict()) if stats else y
+
     def pagerank(self, in_graph: DeviceCSR, out_degree: torch.Tensor, iterations: int, damping: float = 0.85,
                  mode="grid", tune: Tune | None = None, out: torch.Tensor | None = None, stream=None,
                  stats: bool = False):
@@ -358,3 +425,24 @@ class Context:
     def tree_height(self, t: DeviceTree, mode="grid", tune: Tune | None = None, out=None, stream=None,
                     stats: bool = False):
         return self._tree(load_library().wc_tree_height, t, mode, tune, out, stream, stats)
+
+    def _tree_batch(self, fn, trees, mode, tune, outs, stream, stats):
+        k = len(trees)
+        outs = outs if outs is not None else [torch.empty(t.n, dtype=torch.int32, device=t.parent.device)
+                                              for t in trees]
+        ct = (CTree * k)(*[t.c() for t in trees])
+        co = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
+        st = Stats() if stats else None
+        _check(fn(self._ptr, k, ct, co, _mode(mode), ctypes.byref(tune) if tune else None, _stream_ptr(stream),
+                  ctypes.byref(st) if st else None))
+        return (outs, st.as_dict()) if stats else outs
+
+    def tree_descendants_batch(self, trees, mode="grid", tune: Tune | None = None, outs=None, stream=None,
+                               stats: bool = False):
+        """Descendant counts of every tree of a list of DeviceTrees, in one call."""
+        return self._tree_batch(load_library().wc_tree_descendants_batch, trees, mode, tune, outs, stream, stats)
+
+    def tree_height_batch(self, trees, mode="grid", tune: Tune | None = None, outs=None, stream=None,
+                          stats: bool = False):
+        """Heights of every tree of a list of DeviceTrees, in one call."""
+        return self._tree_batch(load_library().wc_tree_height_batch, trees, mode, tune, outs, stream, stats)

@@ -219,6 +219,14 @@ def batch_instances(count: int, degree: int = 16, lo_log2: float = 10.0, hi_log2
     return out
 
 
+def batch_trees(count: int, lo_log2: float = 4.0, hi_log2: float = 16.0, seed: int = SEED_TREE) -> list:
+    """`count` independent random trees (random_tree's generator) with node
+    counts log-uniform in [2^lo, 2^hi] (batch_sizes, stream 310); tree i uses the
+    64-bit seed folded from (seed, 311, i)."""
+    sizes = batch_sizes(count, lo_log2, hi_log2, seed, stream=310)
+    return [random_tree(max(1, int(n)), seed=int(_load().syn_rand(seed, 311, i))) for i, n in enumerate(sizes.tolist())]
+
+
 def serving_graph_sizes(count: int = 64, lo_log2: float = 14.0, hi_log2: float = 20.0) -> list:
     """Vertex counts round(2^(lo + (hi - lo) k / (count - 1))), k = 0..count-1."""
     if count == 1:

@@ -10,11 +10,15 @@ def test_buckets_follow_log2_size():
         [0, 0, 1, 1, 2, 2, 3, 3]
 
 
-def test_candidates_cover_every_mode_once_per_threshold():
+def test_candidates_cover_the_search_space_once():
     c = autotune.candidates()
-    assert {x["mode"] for x in c} == {"wave", "block", "grid"}
+    assert {x["mode"] for x in c} == {"flat", "wave", "block", "grid"}
+    assert len([x for x in c if x["mode"] == "flat"]) == 1
     assert len([x for x in c if x["mode"] == "grid"]) == len(autotune.THRESHOLDS) * len(autotune.ITEMS_PER_LANE)
-    assert len([x for x in c if x["mode"] == "wave"]) == len(autotune.THRESHOLDS)
+    for mode in ("wave", "block"):
+        assert len([x for x in c if x["mode"] == mode]) == len(autotune.THRESHOLDS)
+    keys = [(x["mode"], x["threshold"], x["items_per_lane"]) for x in c]
+    assert len(keys) == len(set(keys))
 
 
 def test_table_roundtrip_and_per_instance_lookup():

@@ -104,3 +104,39 @@ def test_counter_summary(tmp_path, monkeypatch):
     # dispatches, waves, VALU per wave, wave-cycles per wave, L2 hit rate, atomics per dispatch
     assert cells[1] == "2" and cells[3] == "200" and cells[4] == "40.00" and cells[6] == "40.00"
     assert cells[9] == "0.60" and cells[10] == "6"
+
+
+def test_mode_counter_summary(tmp_path, monkeypatch):
+    """Per-mode counters (the Figs. 8-10 analogue): lane utilization from the
+    summed VALU thread cycles, occupancy weighted by dispatch cycles, bytes per
+    call from the calibrated FETCH_SIZE plus WRITE_SIZE; kernels are grouped by
+    problem from their names."""
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    head = ("Correlation_Id,Dispatch_Id,Agent_Id,Queue_Id,Process_Id,Thread_Id,Grid_Size,Kernel_Id,Kernel_Name,"
+            "Workgroup_Size,LDS_Block_Size,Scratch_Size,VGPR_Count,Accum_VGPR_Count,SGPR_Count,Counter_Name,"
+            "Counter_Value,Start_Timestamp,End_Timestamp\n")
+
+    def row(disp, kernel, counter, value):
+        name = f"\"void wc::(anonymous namespace)::{kernel}<256>(wc::(anonymous namespace)::Args)\""
+        return f"1,{disp},A,1,1,1,512,1,{name},256,0,0,24,0,16,{counter},{value},0,1\n"
+    sq, fe, wr = tmp_path / "sq", tmp_path / "fe", tmp_path / "wr"
+    for d in (sq, fe, wr):
+        d.mkdir()
+    (sq / "run_counter_collection.csv").write_text(
+        head + row(1, "sssp_round", "SQ_THREAD_CYCLES_VALU", 3200) + row(1, "sssp_round", "SQ_ACTIVE_INST_VALU", 100)
+        + row(1, "sssp_round", "SQ_INSTS_VALU", 300) + row(1, "sssp_round", "GRBM_GUI_ACTIVE", 1000)
+        + row(1, "sssp_round", "MeanOccupancyPerCU", 10)
+        + row(2, "sssp_drain", "SQ_THREAD_CYCLES_VALU", 6400) + row(2, "sssp_drain", "SQ_ACTIVE_INST_VALU", 100)
+        + row(2, "sssp_drain", "GRBM_GUI_ACTIVE", 3000) + row(2, "sssp_drain", "MeanOccupancyPerCU", 20)
+        + row(3, "zero_stats", "SQ_INSTS_VALU", 99))
+    (fe / "run_counter_collection.csv").write_text(head + row(1, "sssp_round", "FETCH_SIZE", 1000))
+    (wr / "run_counter_collection.csv").write_text(head + row(1, "sssp_drain", "WRITE_SIZE", 1000))
+    bench.summarize_mode_counters({"wave": [str(sq), str(fe), str(wr)]}, "w", "cmd", "modes_w")
+    line = next(x for x in (tmp_path / "profiles" / "modes_w.md").read_text().splitlines()
+                if x.startswith("| sssp | wave"))
+    cells = [c.strip() for c in line.split("|")][1:-1]
+    # VALU per call 300 / 3; utilization (3200 + 6400) / (64 x 200) = 0.75;
+    # occupancy (10 x 1000 + 20 x 3000) / 4000 = 17.5; bytes (2 x 1000 + 1000) KiB / 3
+    assert cells[2] == "100" and cells[3] == "0.750" and cells[4] == "17.5"
+    assert cells[5] == f"{3000 * 1024 / 3 / 1e6:.1f}"

@@ -35,10 +35,12 @@ def test_results_same_alone_and_in_the_mix(ctx, resident):
     reqs = serve.poisson_requests(240, 20000.0, srcs, n_x=2, seed=9, tree_fraction=0.25, n_trees=len(trees))
     assert any(r.kind in serve.TREE_KINDS for r in reqs)
     say(f"serving {len(reqs)} requests")
-    srv = serve.Server(serve.GpuBackend(dev, trees=dtrees), workers=3, budget_bytes=64 << 20, max_slots=48,
-                       max_batch=16, keep_outputs=True)
+    be = serve.GpuBackend(dev, trees=dtrees, pool_bytes=64 << 10)
+    srv = serve.Server(be, workers=3, budget_bytes=64 << 20, max_slots=48, max_batch=16, keep_outputs=True)
     try:
         out = srv.run(reqs, time_limit=60)
+        # every pool growth went through admission (64 KiB pools: single requests need more)
+        assert sum(be.pool_grows(w.state) for w in srv.workers) == srv.grows >= 1
     finally:
         srv.close()
     assert all(r.error is None for r in out)
@@ -90,9 +92,12 @@ def test_full_resident_set_under_load(ctx):
     srcs = [np.flatnonzero(np.diff(g.row_ptr) > 0) for g, _, _, _ in host]
     reqs = serve.poisson_requests(300, 20000.0, srcs, n_x=4, seed=21)
     say(f"serving {len(reqs)} requests on the full resident set")
-    srv = serve.Server(serve.GpuBackend(dev), workers=4, max_slots=512, max_batch=64, keep_outputs=True)
+    be = serve.GpuBackend(dev)
+    srv = serve.Server(be, workers=4, max_slots=512, max_batch=64, keep_outputs=True)
     try:
         out = srv.run(reqs, time_limit=120)
+        assert sum(be.pool_grows(w.state) for w in srv.workers) == srv.grows
+        assert srv.admission.peak_used <= srv.admission.budget
     finally:
         srv.close()
     assert all(r.error is None for r in out)

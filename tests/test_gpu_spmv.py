@@ -139,6 +139,33 @@ def test_grid_overflow(ctx, c1):
         run(ctx, g, val, x, "grid", stats=True, threshold=4, buf_capacity=7, allow_fallback=-1)
 
 
+@pytest.mark.parametrize("mode", ["wave", "block"])
+def test_long_rows_handed_to_the_grid(ctx, c1, mode):
+    """Rows longer than one group's child can take (wave: 4 * 64 * items_per_lane
+    nonzeros, block: block_threads * items_per_lane) go to the global chunks that
+    the grid-wide drain sums: same bound, bitwise reproducible, the same rows
+    counted as buffered, and an undersized buffer falls back to the row's lane
+    (overflow flag; WC_EOVERFLOW when the fallback is refused)."""
+    g, val, x, y_ref, b = c1
+    lens = np.diff(g.row_ptr)
+    for tune in (dict(), dict(items_per_lane=1), dict(items_per_lane=1, block_threads=64),
+                 dict(items_per_lane=2, threshold=2)):
+        ipl, bt = tune.get("items_per_lane", 4), tune.get("block_threads", 256)
+        spill = 4 * 64 * ipl if mode == "wave" else bt * ipl
+        assert (lens > spill).any()
+        y1, st = run(ctx, g, val, x, mode, stats=True, **tune)
+        y2 = run(ctx, g, val, x, mode, **tune)
+        assert oracle.spmv_check(y_ref, b, y1) == (0, -1), tune
+        assert np.array_equal(y1.view(np.uint32), y2.view(np.uint32)), tune
+        assert st["items_buffered"] == oracle.count_heavy(lens, tune.get("threshold", 32))
+        assert st["overflowed"] == 0
+    y, st = run(ctx, g, val, x, mode, stats=True, items_per_lane=1, buf_capacity=5)
+    assert st["overflowed"] == 1 and oracle.spmv_check(y_ref, b, y) == (0, -1)
+    with pytest.raises(wc.WcError) as ei:
+        run(ctx, g, val, x, mode, stats=True, items_per_lane=1, buf_capacity=5, allow_fallback=-1)
+    assert ei.value.status == -3
+
+
 @pytest.fixture(scope="module")
 def c2_spmv():
     say("generating scale-22 matrix")

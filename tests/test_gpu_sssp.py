@@ -101,6 +101,61 @@ def test_grid_overflow_falls_back_and_can_fail(ctx, c1):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("mode", ["wave", "block"])
+def test_long_items_handed_to_the_grid(ctx, c1, mode):
+    """Vertices with more edges than one group's child keeps (wave: 4 chunks,
+    block: one chunk per wave) are handed on to the grid-wide drain of the
+    round: identical distances for several chunk sizes, and an undersized
+    buffer falls back to the writing lanes (overflow flag; WC_EOVERFLOW when the
+    fallback is refused)."""
+    g, w, ref = c1
+    dg, dw = upload(g, w)
+    deg = np.diff(g.row_ptr)
+    for tune in (dict(), dict(items_per_lane=1), dict(items_per_lane=1, block_threads=64), dict(threshold=2)):
+        ipl, bt = tune.get("items_per_lane", 4), tune.get("block_threads", 256)
+        spill = 4 * 64 * ipl if mode == "wave" else bt * ipl
+        assert (deg > spill).any()
+        d, st = ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(**tune), stats=True)
+        assert np.array_equal(dev_to_u32(d), ref), tune
+        assert st["overflowed"] == 0 and st["updates_buffered"] >= 1
+    d, st = ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(items_per_lane=1, buf_capacity=3), stats=True)
+    assert np.array_equal(dev_to_u32(d), ref) and st["overflowed"] == 1
+    with pytest.raises(wc.WcError) as ei:
+        ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(items_per_lane=1, buf_capacity=3, allow_fallback=-1),
+                 stats=True)
+    assert ei.value.status == -3
+
+
+@pytest.mark.parametrize("mode", ["wave", "block"])
+@pytest.mark.parametrize("alloc", [1, 2])
+def test_group_buffers_in_global_memory(ctx, c1, mode, alloc):
+    """The allocator comparison (Sec. V.A): each wave's or block's buffer in a
+    slice of the pre-allocated pool (1) or from device-side malloc, freed after
+    the child (2), instead of registers / LDS; identical distances (a malloc
+    that fails keeps the items in registers / LDS and only raises the flag)."""
+    g, w, ref = c1
+    dg, dw = upload(g, w)
+    for tune in (dict(), dict(threshold=1, block_threads=64), dict(block_threads=1024, items_per_lane=1)):
+        say(f"sssp buffer_alloc={alloc} mode={mode} tune={tune}")
+        d, st = ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(buffer_alloc=alloc, **tune), stats=True)
+        assert np.array_equal(dev_to_u32(d), ref), tune
+        if alloc == 1:
+            assert st["overflowed"] == 0
+
+
+def test_buffer_alloc_is_refused_where_it_does_not_apply(ctx, c1):
+    g, w, _ = c1
+    dg, dw = upload(g, w)
+    for mode, alloc in (("grid", 1), ("flat", 2), ("wave", 3), ("block", -1)):
+        with pytest.raises(wc.WcError) as ei:
+            ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(buffer_alloc=alloc))
+        assert ei.value.status == -1
+    with pytest.raises(wc.WcError):
+        ctx.spmv(dg, torch.zeros(g.m, device="cuda"), torch.zeros(g.n, device="cuda"), mode="wave",
+                 tune=wc.make_tune(buffer_alloc=1))
+    torch.cuda.synchronize()
+
+
 def test_persistent_driver_is_refused(ctx, c1):
     """The persistent co-resident driver is switched off (it hung in block mode
     and no cause has been shown); asking for it is an argument error."""

@@ -86,3 +86,14 @@ def test_tolerance_accepts_fp32_sums_and_rejects_planted_errors(c1_graph):
     bad = y32.copy()
     bad[r] = np.float32(y_ref[r] - float(val[e]) * float(x[g.col[e]]))
     assert oracle.spmv_check(y_ref, b, bad)[0] == 1
+
+
+def test_row_blocks_on_host_threads_give_the_same_result(c1_graph):
+    """spmv_f64_threads (the oracle timed on all host cores) computes every row
+    exactly as spmv_f64 does; only the rows run side by side."""
+    g, _ = c1_graph
+    val, x = synth.values(g.m), synth.vector_x(g.n)
+    y1, b1 = oracle.spmv_f64(g.row_ptr, g.col, val, x)
+    for threads in (1, 3, 8, 64):
+        y, b = oracle.spmv_f64_threads(g.row_ptr, g.col, val, x, threads)
+        assert np.array_equal(y.view(np.uint64), y1.view(np.uint64)) and np.array_equal(b, b1), threads

@@ -17,25 +17,41 @@ class FakeGraph:
 
 
 class FakeBackend:
-    """Each batch 'runs' for a fixed time; results are the request ids."""
+    """Each batch 'runs' for a fixed time; results are the request ids.  A
+    batch's workspace is the sum of its requests' (ws_of), every worker starts
+    with a pool of pool0 bytes."""
 
-    def __init__(self, graphs, run_s=0.002, fail_graph=None):
+    def __init__(self, graphs, run_s=0.002, fail_graph=None, pool0=1 << 30, ws_of=None):
         self.graphs = graphs
         self.run_s = run_s
         self.fail_graph = fail_graph
+        self.pool0 = pool0
+        self.ws_of = ws_of or (lambda r: 1000)
         self.lock = threading.Lock()
         self.concurrent = 0
         self.max_concurrent = 0
         self.batches = []
+        self.grown = []
 
     def free_bytes(self):
         return 1 << 40
 
     def worker_state(self):
-        return None
+        return {"pool": self.pool0}
 
     def close_state(self, state):
         pass
+
+    def pool_bytes(self, state):
+        return state["pool"]
+
+    def grow(self, state, nbytes):
+        with self.lock:
+            self.grown.append(nbytes)
+        state["pool"] = max(state["pool"], nbytes)
+
+    def workspace(self, batch):
+        return sum(self.ws_of(r) for r in batch)
 
     def allocate(self, r):
         r.out = None
@@ -163,3 +179,38 @@ def test_tree_requests_are_admitted_by_their_own_size():
         if r.kind in serve.TREE_KINDS:
             assert r.nbytes == serve.request_bytes(r.kind, be.trees[r.graph].n, 0)
     assert srv.admission.used == 0 and srv.admission.slots == 0
+
+
+def test_a_request_that_would_grow_a_pool_waits_for_memory():
+    """Budget 800 bytes; one worker whose pool holds 100.  r0 (output 300,
+    workspace 50) runs first; r1 (output 100) needs a 700-byte workspace, so
+    its worker must grow by 600: with r0's output still held that would be
+    300 + 100 + 600 > 800, so r1 stays queued until r0 is done, then the growth
+    is charged for good and r1 runs."""
+    gs = [FakeGraph(75, 10), FakeGraph(25, 10)]
+    reqs = [serve.Request(0, serve.SPMV, 0, 0, 0.0), serve.Request(1, serve.SPMV, 1, 0, 0.0)]
+    be = FakeBackend(gs, run_s=0.05, pool0=100, ws_of=lambda r: 50 if r.graph == 0 else 700)
+    srv = serve.Server(be, workers=1, budget_bytes=800, max_slots=8, max_batch=8, keep_outputs=True)
+    try:
+        out = srv.run(reqs, time_limit=30)
+    finally:
+        srv.close()
+    r0, r1 = out
+    assert r0.nbytes == 300 and r1.nbytes == 100
+    assert be.batches == [[0], [1]]          # cut to what the pool holds, then r1 alone
+    assert r1.t_start >= r0.t_done            # queued, not over-admitted
+    assert be.grown == [700] and srv.grows == 1
+    assert srv.admission.peak_used <= 800 and srv.admission.pool_growth == 600
+    assert srv.admission.used == 600          # the growth stays charged; outputs are released
+
+
+def test_a_growth_that_can_never_fit_is_refused_up_front():
+    gs = [FakeGraph(10, 10)]
+    reqs = [serve.Request(0, serve.SPMV, 0, 0, 0.0)]
+    be = FakeBackend(gs, pool0=100, ws_of=lambda r: 10_000)
+    srv = serve.Server(be, workers=2, budget_bytes=1000, max_slots=8)
+    try:
+        with pytest.raises(ValueError):
+            srv.run(reqs)
+    finally:
+        srv.close()

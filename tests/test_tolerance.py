@@ -9,7 +9,7 @@
 * A replay of the first PageRank sweep at the scale-22 hub (159,737 in-edges)
   in fp32: a plain running sum in one lane (the order flat mode used before the
   cascade) is off by more than 1e-4 relative to binary64, while the cascade
-  order of flat mode and the lane-strided order of wave mode stay within the
+  order of flat mode and the chunked order of wave mode stay within the
   derived bound.
 """
 import math
@@ -106,11 +106,16 @@ def test_spmv_bound_is_worst_case_on_the_scale22_graph(rmat22, mode):
 
 
 def test_row_depth_examples():
-    # the hub's 159,772 nonzeros: flat one lane; wave 2,497 per lane + butterfly;
-    # grid 313 chunks of 512 (8 per lane + butterfly), partials 5 per lane + butterfly
+    # the hub's 159,772 nonzeros: flat one lane; wave and block 625 chunks of 256
+    # (4 per lane + butterfly), partials 10 per lane + butterfly; grid 313 chunks
+    # of 512 (8 per lane + butterfly), partials 5 per lane + butterfly
     assert row_depth(159_772, "flat") == cascade_depth(159_772)
-    assert row_depth(159_772, "wave") == cascade_depth(2497) + 6
-    assert row_depth(159_772, "block") == cascade_depth(625) + 6 + 3
+    assert row_depth(159_772, "wave") == cascade_depth(4) + 6 + cascade_depth(10) + 6
+    assert row_depth(159_772, "block") == cascade_depth(4) + 6 + cascade_depth(10) + 6
+    # rows a wave keeps (up to 1,024) and a block keeps (up to 256 * 4)
+    assert row_depth(1024, "wave") == cascade_depth(16) + 6
+    assert row_depth(1025, "wave") == cascade_depth(4) + 6 + cascade_depth(1) + 6
+    assert row_depth(1024, "block") == cascade_depth(16) + 6
     assert row_depth(159_772, "grid") == cascade_depth(8) + 6 + cascade_depth(5) + 6
     assert row_depth(8, "grid") == cascade_depth(8) and row_depth(9, "grid") == cascade_depth(5) + 1
     assert row_depth(0, "wave") == 0
@@ -147,15 +152,22 @@ def test_pagerank_first_sweep_at_the_hub(rmat22):
         c.add(v)
     cascade, depth = c.total()
     assert depth <= cascade_depth(src.size)
-    lanes = np.zeros(64, F)  # wave order: lane l takes terms l, l + 64, ... (cascade each), then the butterfly
-    for lane in range(64):
-        cl = CascadeSim()
-        for v in contrib[lane::64]:
-            cl.add(v)
-        lanes[lane] = cl.total()[0]
-    for dist in (32, 16, 8, 4, 2, 1):
-        lanes = (lanes + lanes[np.arange(64) ^ dist]).astype(F)
-    wave = lanes[0]
+    def wave_sum(vals):
+        """64 lanes, lane l taking vals l, l + 64, ... (a cascade each), then the butterfly."""
+        lanes = np.zeros(64, F)
+        for lane in range(64):
+            cl = CascadeSim()
+            for v in vals[lane::64]:
+                cl.add(v)
+            lanes[lane] = cl.total()[0]
+        for dist in (32, 16, 8, 4, 2, 1):
+            lanes = (lanes + lanes[np.arange(64) ^ dist]).astype(F)
+        return lanes[0]
+
+    # wave order for a row this long: chunks of 64 * 4 terms, each a wave sum,
+    # then a wave sum of the chunk partials in chunk order
+    partials = np.array([wave_sum(contrib[c:c + 256]) for c in range(0, contrib.size, 256)], F)
+    wave = wave_sum(partials)
 
     assert rel(serial) > 1e-4  # the bound 1e-4 did not hold for the plain running sum
     assert rel(cascade) <= pagerank_rtol(1, in_len, "flat", n)

@@ -18,9 +18,10 @@ through, following the order the kernels use:
     lanes; still longer rows in chunks of 64 * ipl nonzeros (a cascade per lane
     plus a 64-lane butterfly), whose partials are summed lane-strided by one
     wave (a cascade plus a butterfly);
-  * wave mode: rows above the threshold lane-strided over 64 lanes;
+  * wave mode: rows above the threshold lane-strided over 64 lanes, up to
+    4 * 64 * ipl nonzeros; longer rows in chunks as in grid mode;
   * block mode: rows above the threshold by one wave up to block * ipl
-    nonzeros, longer rows lane-strided over the whole workgroup;
+    nonzeros; longer rows in chunks as in grid mode;
   * flat mode: the row's lane alone.
 """
 import math
@@ -71,18 +72,18 @@ def row_depth(length: int, mode: str, **tune) -> int:
         return 0
     if mode == "flat" or length <= T:
         return cascade_depth(length)
-    if mode == "wave":
-        return cascade_depth(math.ceil(length / 64)) + 6
-    if mode == "block":
-        if length <= B * ipl:
+    chunks = math.ceil(length / (64 * ipl))
+    chunked = cascade_depth(ipl) + 6 + cascade_depth(math.ceil(chunks / 64)) + 6
+    if mode in ("wave", "block"):
+        spill = 4 * 64 * ipl if mode == "wave" else B * ipl
+        if length <= spill:
             return cascade_depth(math.ceil(length / 64)) + 6
-        return cascade_depth(math.ceil(length / B)) + 6 + (B // 64 - 1)
+        return chunked
     # grid
     if length <= 64 * ipl:
         g = 1 << max(0, math.ceil(math.log2(math.ceil(length / ipl))))
         return cascade_depth(math.ceil(length / g)) + int(math.log2(g))
-    chunks = math.ceil(length / (64 * ipl))
-    return cascade_depth(ipl) + 6 + cascade_depth(math.ceil(chunks / 64)) + 6
+    return chunked
 
 
 def max_row_depth(row_lengths, mode: str, **tune) -> int:
