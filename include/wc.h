@@ -309,6 +309,32 @@ wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *graphs, const 
                         const int32_t *src, uint32_t *const *dist, const wc_mode *modes, const wc_tune *tunes,
                         int32_t graph_rounds, hipStream_t stream, wc_stats *stats);
 
+/* Size of the fixed device array that wc_spmv_noalloc uses as its workspace. */
+#define WC_SPMV_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* wc_spmv for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product, kernels and summation order as wc_spmv with the same mode and tune
+ * (so bit-identical results), but no context, no pool and no stats.  The
+ * grid-mode workspace lives in one fixed device array of
+ * WC_SPMV_NOALLOC_SCRATCH_BYTES per device, held from the first call on that
+ * device until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call.  Grid mode needs about 52 n + 20 m / (64 * items_per_lane)
+ * + 72 ceil(n / block_threads) bytes (n up to about 1.2 million at m = 16 n
+ * with the defaults); a call whose workspace could exceed the array returns
+ * WC_EINVAL before anything is enqueued, as do bad arguments and
+ * tune->driver != 0.  Flat mode uses no workspace; wave and block modes only
+ * for the rows they hand on to the grid (about 0.12 m bytes with the defaults).
+ * Runs on the calling thread's current device (hipSetDevice); `stream` must
+ * belong to it.  The call only enqueues; the caller synchronizes.  Every call
+ * on one device shares its array: calls whose stream work overlaps on one
+ * device (different streams or host threads without ordering between them)
+ * race and give undefined results; calls on one stream are ordered and safe.
+ * Nothing in the array needs to start at zero (every piece is written before
+ * it is read within a call). */
+wc_status wc_spmv_noalloc(const wc_csr *a, const float *val, const float *x, float *y, wc_mode mode,
+                          const wc_tune *tune, hipStream_t stream);
+
 /* Per-kernel timing.  When enabled, a HIP event is recorded on the launch
  * stream after every kernel the library launches on a context, and before the
  * first kernel of a call (and after any other stream work of the library), so

@@ -30,6 +30,8 @@
 // |y - y_ref| <= 1e-5 * sum |a_ij x_j| holds as a worst-case bound per row.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "wc_block.h"
@@ -983,4 +985,91 @@ extern "C" wc_status wc_spmv_hot(wc_ctx *ctx, const wc_csr *a_hot, int32_t hot, 
     st = spmv_launch(ctx, &p, stream);
     if (st != WC_OK) return st;
     return end_call(ctx, stream, stats, 1, p.cfg.fail_on_overflow);
+}
+
+// ---------------------------------------------------------------- SpMV without allocation
+//
+// wc_spmv_noalloc: the kernels of wc_spmv with their workspace in a fixed
+// device array instead of a context pool.  `scratch` is a host-side stand-in
+// for that array: host code only ever uses the device address that
+// hipGetSymbolAddress returns for it, taken once per device on the first call
+// made with that device current.
+
+static __device__ __align__(256) unsigned char scratch[WC_SPMV_NOALLOC_SCRATCH_BYTES];
+
+namespace wc {
+namespace {
+
+constexpr int kMaxDevices = 64;
+struct NoAllocDevice {
+    bool ready = false;
+    int num_cus = 0;
+    char *scratch = nullptr;  // device address of `scratch` on this device
+};
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kMaxDevices];
+
+// Workspace bound from n, m and the tune alone (the parent grid at its
+// largest, ceil(n / block)), so oversized calls are refused before any HIP
+// call is made.
+size_t spmv_noalloc_bound(const wc_csr *g, const SpmvPlan *p)
+{
+    SpmvPlan q = *p;
+    q.grid = (int)std::max<long long>(1, ((long long)g->n + q.cfg.block - 1) / q.cfg.block);
+    return spmv_workspace_bytes(&q) + padded(sizeof(DevStats));
+}
+
+}  // namespace
+}  // namespace wc
+
+extern "C" wc_status wc_spmv_noalloc(const wc_csr *g, const float *val, const float *x, float *y, wc_mode mode,
+                                     const wc_tune *tune, hipStream_t stream)
+{
+    if (!g) return fail(WC_EINVAL, "wc_spmv_noalloc: NULL matrix");
+    if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "wc_spmv_noalloc: bad mode");
+    if (g->n < 0 || g->m < 0) return fail(WC_EINVAL, "wc_spmv_noalloc: negative size");
+    if (g->n == 0) return WC_OK;
+    if (!g->row_ptr || !x || !y || (g->m > 0 && (!g->col || !val)))
+        return fail(WC_EINVAL, "wc_spmv_noalloc: NULL array");
+    if (tune && tune->driver != 0)
+        return fail(WC_EINVAL, "wc_spmv_noalloc: only the relaunch driver (driver = 0) applies");
+    // the tune and the size limit are checked before any device memory is
+    // touched; the compute-unit count only changes the drain grid, not the bound
+    SpmvPlan p;
+    wc_status st = spmv_shape(1, g, val, mode, tune, false, &p);
+    if (st != WC_OK) return st;
+    const size_t bound = spmv_noalloc_bound(g, &p);
+    if (bound > (size_t)WC_SPMV_NOALLOC_SCRATCH_BYTES)
+        return fail(WC_EINVAL, "wc_spmv_noalloc: the workspace (" + std::to_string(bound) +
+                                   " bytes) exceeds the fixed scratch of " +
+                                   std::to_string((size_t)WC_SPMV_NOALLOC_SCRATCH_BYTES) + " bytes");
+    int dev = 0;
+    WC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(WC_EINVAL, "wc_spmv_noalloc: device index out of range");
+    NoAllocDevice d;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        NoAllocDevice &slot = g_noalloc[dev];
+        if (!slot.ready) {
+            int cus = 0;
+            WC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            void *ptr = nullptr;
+            WC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return fail(WC_EHIP, "wc_spmv_noalloc: no device address for the scratch array");
+            slot.num_cus = cus;
+            slot.scratch = static_cast<char *>(ptr);
+            slot.ready = true;
+        }
+        d = slot;
+    }
+    st = spmv_shape(d.num_cus, g, val, mode, tune, false, &p);
+    if (st != WC_OK) return st;
+    char *end = spmv_carve(&p, d.scratch);
+    p.a.stats = reinterpret_cast<DevStats *>(end);  // written only on overflow, which a full-size buffer never has
+    p.a.x = x;
+    p.a.y = y;
+    st = spmv_launch(nullptr, &p, stream);
+    if (st != WC_OK) return st;
+    WC_HIP(hipGetLastError());
+    return WC_OK;
 }

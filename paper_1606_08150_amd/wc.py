@@ -22,7 +22,7 @@ STATUS = {0: "WC_OK", -1: "WC_EINVAL", -2: "WC_ENOMEM", -3: "WC_EOVERFLOW", -4: 
           1: "WC_PLANNED"}
 
 # C-ABI symbols declared in include/wc.h
-EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_spmv_prepare",
+EXPORTS = ("wc_ctx_create", "wc_ctx_destroy", "wc_sssp", "wc_bfs", "wc_spmv", "wc_spmv_noalloc", "wc_spmv_prepare",
            "wc_spmv_hot", "wc_pagerank",
            "wc_color", "wc_tree_descendants", "wc_tree_height", "wc_tree_descendants_batch", "wc_tree_height_batch",
            "wc_sssp_batch", "wc_ctx_set_timing", "wc_ctx_set_wait_limit", "wc_ctx_set_plan_only",
@@ -89,6 +89,8 @@ def load_library():
     lib.wc_bfs.argtypes = [vp, c.POINTER(CCsr), c.c_int32, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
     lib.wc_spmv.restype = c.c_int
     lib.wc_spmv.argtypes = [vp, c.POINTER(CCsr), vp, vp, vp, c.c_int, c.POINTER(Tune), vp, c.POINTER(Stats)]
+    lib.wc_spmv_noalloc.restype = c.c_int
+    lib.wc_spmv_noalloc.argtypes = [c.POINTER(CCsr), vp, vp, vp, c.c_int, c.POINTER(Tune), vp]
     lib.wc_spmv_prepare.restype = c.c_int
     lib.wc_spmv_prepare.argtypes = [vp, c.POINTER(CCsr), c.c_int32, vp, vp, vp]
     lib.wc_spmv_hot.restype = c.c_int
@@ -223,6 +225,18 @@ def _stream_ptr(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def spmv_noalloc(a: DeviceCSR, val: torch.Tensor, x: torch.Tensor, out: torch.Tensor, mode="grid",
+                 tune: Tune | None = None, stream=None) -> torch.Tensor:
+    """y = A x through wc_spmv_noalloc (no context, no device allocation in the
+    call): `out` (fp32[n], device) is written and returned.  Runs on the current
+    device; the caller synchronizes."""
+    ca = a.c()
+    _check(load_library().wc_spmv_noalloc(ctypes.byref(ca), val.data_ptr() if a.m else None, x.data_ptr(),
+                                          out.data_ptr(), _mode(mode), ctypes.byref(tune) if tune else None,
+                                          _stream_ptr(stream)))
+    return out
 
 
 class Context:

@@ -54,3 +54,21 @@ def test_default_tune_and_errors():
         assert e.status == -1
     else:
         raise AssertionError("unknown problem accepted")
+
+
+def test_spmv_noalloc_refuses_before_touching_the_device():
+    """The no-allocation SpMV checks its size limit and tune on the host, before
+    any HIP call (so this runs without a GPU; no pointer is dereferenced)."""
+    import ctypes
+    lib = wc.load_library()
+    dummy = 256  # never dereferenced: every call below is refused first
+    big = wc.CCsr(1 << 22, 1 << 26, dummy, dummy)
+    assert lib.wc_spmv_noalloc(ctypes.byref(big), dummy, dummy, dummy, wc.GRID, None, None) == -1
+    assert b"exceeds the fixed scratch" in lib.wc_last_error()
+    small = wc.CCsr(1000, 4000, dummy, dummy)
+    t = wc.make_tune(driver=2)
+    assert lib.wc_spmv_noalloc(ctypes.byref(small), dummy, dummy, dummy, wc.GRID, ctypes.byref(t), None) == -1
+    assert lib.wc_spmv_noalloc(ctypes.byref(small), dummy, dummy, dummy, 7, None, None) == -1
+    assert lib.wc_spmv_noalloc(ctypes.byref(small), None, dummy, dummy, wc.GRID, None, None) == -1
+    empty = wc.CCsr(0, 0, None, None)
+    assert lib.wc_spmv_noalloc(ctypes.byref(empty), None, None, None, wc.GRID, None, None) == 0
