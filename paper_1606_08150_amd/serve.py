@@ -372,7 +372,25 @@ class Server:
                 batch = [ready.popleft() for _ in range(min(self.max_batch, len(ready)))]
                 grow_to = self._fit_batch(wi, batch, ready)
                 if grow_to < 0:
-                    break  # waits for completions to free memory
+                    if len(idle) < len(self.workers):
+                        break  # waits for completions to free memory
+                    # nothing runs, so nothing will free memory: the requests
+                    # admitted after the first one give their outputs back
+                    # (they wait again) until its pool growth fits
+                    need = int(self.backend.workspace([ready[0]])) - self.pool[wi]
+                    while len(ready) > 1 and self.admission.used + need > self.admission.budget:
+                        r = ready.pop()
+                        self.admission.release(r.nbytes)
+                        r.out, r.t_admit = None, -1.0
+                        waiting.appendleft(r)
+                    if self.admission.used + need > self.admission.budget:
+                        r = ready.popleft()  # the budget left can never take it
+                        self.admission.release(r.nbytes)
+                        r.out, r.error = None, MemoryError(f"request {r.rid} needs a pool growth of {need} bytes, "
+                                                          "more than the budget left")
+                        r.t_start = r.t_done = self.clock()
+                        done += 1
+                    continue
                 idle.discard(wi)
                 self.workers[wi].inbox.put((batch, grow_to))
             # completions free memory and slots for the next admissions

@@ -214,3 +214,22 @@ def test_a_growth_that_can_never_fit_is_refused_up_front():
             srv.run(reqs)
     finally:
         srv.close()
+
+
+def test_admitted_requests_give_memory_back_when_a_growth_could_never_run():
+    """Budget 1000, one worker with a 100-byte pool.  r0 needs a 700-byte
+    workspace (growth 600); r1..r3 (output 200 each) arrive with it and are
+    admitted too, leaving no room for the growth while nothing runs.  The
+    later requests give their outputs back and wait, r0 grows the pool and
+    runs, then the others run in the grown pool."""
+    gs = [FakeGraph(25, 10), FakeGraph(50, 10)]
+    reqs = [serve.Request(0, serve.SPMV, 0, 0, 0.0)] + [serve.Request(i, serve.SPMV, 1, 0, 0.0) for i in (1, 2, 3)]
+    be = FakeBackend(gs, run_s=0.01, pool0=100, ws_of=lambda r: 700 if r.graph == 0 else 50)
+    srv = serve.Server(be, workers=1, budget_bytes=1000, max_slots=8, max_batch=8, keep_outputs=True)
+    try:
+        out = srv.run(reqs, time_limit=30)
+    finally:
+        srv.close()
+    assert all(r.error is None for r in out)
+    assert be.batches[0] == [0] and sorted(i for b in be.batches[1:] for i in b) == [1, 2, 3]
+    assert be.grown == [700] and srv.admission.peak_used <= 1000
