@@ -399,7 +399,7 @@ int64_t wc_per_buffer_size(int64_t total_thread, int64_t total_buff_var, int64_t
 /* KC_X of Sec. IV.E: (blocks, threads) downgraded to (ceil(blocks / x), threads). */
 void wc_kc_config(int64_t blocks, int64_t threads, int64_t x, int64_t *out_blocks, int64_t *out_threads);
 
-/* Fill `out` with the library's defaults for a problem ("sssp", "spmv", "tree", "color")
+/* Fill `out` with the library's defaults for a problem ("sssp", "bfs", "spmv", "tree", "color")
  * and mode, given the occupancy-derived resident workgroup count.  Returns
  * WC_EINVAL for an unknown problem or mode. */
 wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_blocks, wc_tune *out);

@@ -187,7 +187,7 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
     if (t.buffer_alloc < 0 || t.buffer_alloc > 2)
         return fail(WC_EINVAL, "buffer_alloc must be 0 (registers / LDS), 1 (pool) or 2 (device malloc)");
     if (t.buffer_alloc != 0 && strcmp(problem, "sssp"))
-        return fail(WC_EINVAL, "buffer_alloc exists for SSSP only");
+        return fail(WC_EINVAL, "buffer_alloc exists for SSSP only (and the frontier rounds of BFS)");
     out->buf_capacity = t.buf_capacity;
     out->buffer_alloc = t.buffer_alloc;
     return WC_OK;
@@ -364,7 +364,8 @@ void wc_kc_config(int64_t blocks, int64_t threads, int64_t x, int64_t *out_block
 wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_blocks, wc_tune *out)
 {
     if (!problem || !out) return fail(WC_EINVAL, "NULL argument");
-    if (strcmp(problem, "sssp") && strcmp(problem, "spmv") && strcmp(problem, "tree") && strcmp(problem, "color"))
+    if (strcmp(problem, "sssp") && strcmp(problem, "spmv") && strcmp(problem, "tree") && strcmp(problem, "color") &&
+        strcmp(problem, "bfs"))
         return fail(WC_EINVAL, std::string("unknown problem ") + problem);
     if (mode < WC_FLAT || mode > WC_GRID) return fail(WC_EINVAL, "mode must be flat, wave, block or grid");
     out->threshold = default_threshold(problem, mode);
@@ -378,8 +379,9 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     out->items_per_lane = 4;  // "const" of Sec. IV.E
     if (mode == WC_GRID && !strcmp(problem, "spmv")) out->items_per_lane = 8;
     // SSSP grid chunks of 128 edges: 1.7% faster than 256 on the scale-22 graph
-    // (4 x 20 calls each; the drain waves take two chunks per step)
-    if (mode == WC_GRID && !strcmp(problem, "sssp")) out->items_per_lane = 2;
+    // (4 x 20 calls each; the drain waves take two chunks per step); BFS's
+    // frontier rounds at grid level are the same kernels
+    if (mode == WC_GRID && (!strcmp(problem, "sssp") || !strcmp(problem, "bfs"))) out->items_per_lane = 2;
     // coloring rounds are short and bound by their dependent chain of loads and
     // atomics: 128-neighbour chunks in 256-thread groups measured fastest
     // (symmetric R-MAT graphs of scale 16 and 22)
@@ -387,6 +389,11 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     // tree items are child ranges: most nodes have a few children, and shorter
     // chunks split the few wide nodes over more waves (measured on 2^22 nodes)
     if (mode == WC_GRID && !strcmp(problem, "tree")) out->items_per_lane = 2;
+    // recursive BFS in wave and block modes (its packet queue): every packet
+    // costs its producer a release and its consumer an acquire, so calls are
+    // cut and packets filled four times coarser (scale-22 graph: 22.2 / 9.2 ms
+    // at 4, 13.6 / 5.5 ms at 16, wave / block)
+    if ((mode == WC_WAVE || mode == WC_BLOCK) && !strcmp(problem, "bfs")) out->items_per_lane = 16;
     out->driver = 0;
     out->allow_fallback = 0;
     out->buf_capacity = 0;

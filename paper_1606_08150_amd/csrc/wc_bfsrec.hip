@@ -16,9 +16,9 @@
 // concatenated edge ranges of the packet's calls with all its lanes.  A call is
 // an entry (u, level, first edge, end edge) of at most `chunk` edges: the call
 // of a vertex with more out-edges is handed on as several entries, written by
-// the wave straight to the global node list and published as packets of their
-// own, so a hub is spread over many groups (the child thread-count rule of
-// Sec. IV.E) instead of one.  An entry whose vertex has meanwhile been lowered
+// the wave straight to the global node list and published as packets of about
+// one group's share of work each, so a hub is spread over many groups (the
+// child thread-count rule of Sec. IV.E) instead of one.  An entry whose vertex has meanwhile been lowered
 // again is stale (a newer call exists) and is skipped.
 //
 // Termination: a count of outstanding packets (published, not finished).  The
@@ -58,19 +58,18 @@ struct BfsArgs {
     int want_stats;
 };
 
-// Publishes the entries nl[start, start + count) as packets of at most G
-// entries.  Called by ONE lane, after the entries were written by the wave
-// (the release fence orders them before the packets).
-template <int G>
-__device__ void publish_entries(const BfsArgs &a, int start, int count, StatAcc &acc)
+// Publishes the entries nl[start, start + count) as packets of at most
+// `per` entries.  Called by ONE lane, after the entries were written by the
+// wave (the release fence orders them before the packets).
+__device__ void publish_entries(const BfsArgs &a, int start, int count, int per, StatAcc &acc)
 {
     if (count <= 0) return;
-    const int packets = (count + G - 1) / G;
+    const int packets = (count + per - 1) / per;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     atomic_add_dev(a.outstanding, packets);
     const int slot = atomic_add_dev(a.pq_tail, packets);
     for (int p = 0; p < packets; ++p) {
-        const int s = start + p * G, k = min(G, count - p * G);
+        const int s = start + p * per, k = min(per, count - p * per);
         if ((long long)slot + p < a.pq_cap)
             __hip_atomic_store(&a.pq[slot + p], ((long long)s << 32) | (long long)k, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -80,7 +79,9 @@ __device__ void publish_entries(const BfsArgs &a, int start, int count, StatAcc 
 
 // Appends the calls of the wave's lanes that hold nch > 1 entries (vertices
 // with more than `chunk` out-edges) to the node list and publishes them as
-// packets of their own.  Every lane of the wave calls this.
+// packets of their own, each carrying about a group's share of work
+// (work_cap edges), so that a hub's edges spread over many groups.  Every
+// lane of the wave calls this.
 template <int G>
 __device__ void hand_on_big_calls(const BfsArgs &a, int u, uint32_t lvl, int beg, int end, int nch, StatAcc &acc)
 {
@@ -102,7 +103,7 @@ __device__ void hand_on_big_calls(const BfsArgs &a, int u, uint32_t lvl, int beg
     }
     if (lane_id() == 0) {
         const long long fit = std::min<long long>((long long)base + total, a.nl_cap) - base;
-        publish_entries<G>(a, base, (int)std::max<long long>(fit, 0), acc);
+        publish_entries(a, base, (int)std::max<long long>(fit, 0), max(1, a.work_cap / a.chunk), acc);
     }
 }
 
@@ -153,7 +154,7 @@ __device__ void flush_calls(const BfsArgs &a, BfsLds<G> &s, StatAcc &acc)
         if (t == 0) {
             const long long fit = std::min<long long>((long long)base + k, a.nl_cap) - base;
             if (fit < k) a.stats->overflowed = 1;
-            publish_entries<G>(a, base, (int)std::max<long long>(fit, 0), acc);
+            publish_entries(a, base, (int)std::max<long long>(fit, 0), G, acc);
         }
         gsync<G>();
     }

@@ -7,12 +7,11 @@
 //           elements l, l+64, ..., then a fixed butterfly reduction.
 //   block - thread-ordered LDS buffer, then the workgroup barrier; the buffered
 //           rows are shared out to the block's waves, one wave per row.
-//   In both, a buffered row too long for one group's child (more than
-//   4 * 64 * items_per_lane nonzeros for a wave, BLOCK * items_per_lane for a
-//   block) is handed on as chunks to a global buffer that the grid-mode drain
-//   spreads over the whole grid after the parent (the KC_X rule of Sec. IV.E
-//   gives a warp's or block's child many blocks); its chunk partials are
-//   combined in chunk order.
+//   In both, a buffered row too long for one group's child (more than one
+//   chunk, 64 * items_per_lane nonzeros) is handed on as chunks to a global
+//   buffer that the grid-mode drain spreads over the whole grid after the
+//   parent (the KC_X rule of Sec. IV.E gives a warp's or block's child many
+//   blocks); its chunk partials are combined in chunk order.
 //   grid  - global buffers and a grid-wide barrier (kernel boundary).  The
 //           child-work thread-count heuristic sizes the group of lanes that
 //           sums one buffered row: g = the power of two >= len / items_per_lane,
@@ -610,9 +609,9 @@ wc_status spmv_shape(int num_cus, const wc_csr *g, const float *val, wc_mode mod
     if (hot) resident = std::min(resident, resident_blocks_on(num_cus, p->ks.drain, cfg.block));
     const long long n = g->n, m = g->m;
     const int chunk = kWave * cfg.items_per_lane;
-    // wave and block modes hand rows longer than `spill` on as chunks: at most
-    // m / spill such rows, each with at most one partly filled chunk
-    const int spill = mode == WC_WAVE ? 4 * chunk : cfg.block * cfg.items_per_lane;
+    // wave and block modes hand rows longer than `spill` (one chunk) on as
+    // chunks: at most m / spill such rows, each with at most one partly filled chunk
+    const int spill = chunk;
     long long cap_full = n + m / chunk + 1, multi_full = n;
     if (mode == WC_WAVE || mode == WC_BLOCK) {
         cap_full = m / chunk + m / spill + 1;

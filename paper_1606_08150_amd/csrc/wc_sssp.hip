@@ -174,9 +174,10 @@ __device__ __forceinline__ void mark_active(const SsspArgs &a, int r, bool any)
 // Child thread-count heuristic of the wave and block modes (the KC_X rule of
 // Sec. IV.E: a warp's or block's consolidated child is launched with many
 // blocks, not just the parent group's threads).  An item of the wave's or
-// block's buffer with more than `spill` edges is handed on as chunks of the
-// round's global buffer, which the drain kernel after the parent spreads over
-// the whole grid, instead of occupying its own group for its whole edge list.
+// block's buffer with more than `spill` edges (one chunk) is handed on as
+// chunks of the round's global buffer, which the drain kernel after the
+// parent spreads over the whole grid, instead of occupying its own group for
+// its whole edge list.
 // Every lane of the wave calls this (nch = 0: nothing to hand on); one atomic
 // per wave reserves the slots and the wave writes each item's chunks together.
 // A chunk beyond the buffer's capacity is relaxed by the writing lane itself
@@ -699,7 +700,7 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     long long cap_full = n + m / chunk + 1;
     // wave and block modes hand on only vertices above `spill` edges, each at
     // most once per round: m / chunk + m / spill + 1 entries suffice
-    const int spill = mode == WC_WAVE ? 4 * chunk : (cfg.block / kWave) * chunk;
+    const int spill = chunk;
     if (mode == WC_WAVE || mode == WC_BLOCK) cap_full = m / chunk + m / spill + 1;
     long long cap = mode != WC_FLAT ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
     const int grid_cap = std::max(1, std::min(cfg.grid, resident));
@@ -724,7 +725,9 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
     a.n = (int)n;
     a.threshold = cfg.threshold;
     a.chunk = chunk;
-    // a wave's child keeps items of up to 4 chunks, a block's up to one chunk per wave
+    // a group's own child keeps items of up to one chunk (measured at scale 22:
+    // 4 chunks for a wave and one per wave for a block took 6.0 / 6.6 ms, one
+    // chunk 3.8 / 4.0 ms)
     a.spill = spill;
     a.host_ring = ctx->host_ring_dev;
     a.stats = ctx->dstats;
@@ -882,7 +885,7 @@ extern "C" wc_status wc_bfs(wc_ctx *ctx, const wc_csr *g, int32_t src, uint32_t 
     // wave and block modes: the recursion path (consolidated recursive calls)
     WC_HIP(hipSetDevice(ctx->device));
     Config cfg;
-    st = resolve_tune(ctx, "sssp", mode, tune, 1 << 20, &cfg);
+    st = resolve_tune(ctx, "bfs", mode, tune, 1 << 20, &cfg);
     if (st != WC_OK) return st;
     if (cfg.driver != 0) return fail(WC_EINVAL, "wc_bfs: drivers 2 and 3 are comparison variants of grid mode only");
     if (cfg.buffer_alloc != 0) return fail(WC_EINVAL, "wc_bfs: buffer_alloc does not apply to the recursion path");

@@ -42,6 +42,10 @@ def test_default_tune_and_errors():
     assert wc.default_tune("sssp", "block", 2048)["items_per_lane"] == 4
     assert wc.default_tune("sssp", "block", 2048)["block_threads"] == 256
     assert wc.default_tune("spmv", "grid", 1)["items_per_lane"] == 8
+    # BFS: grid rounds share SSSP's chunk, the recursion queue packs coarser
+    assert wc.default_tune("bfs", "grid", 1)["items_per_lane"] == 2
+    assert wc.default_tune("bfs", "wave", 1)["items_per_lane"] == 16
+    assert wc.default_tune("bfs", "block", 1)["items_per_lane"] == 16
     assert wc.default_tune("tree", "block", 100)["threshold"] == 0
     t = wc.default_tune("tree", "grid", 100)
     assert t["block_threads"] == 512 and t["items_per_lane"] == 2

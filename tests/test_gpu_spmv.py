@@ -141,9 +141,9 @@ def test_grid_overflow(ctx, c1):
 
 @pytest.mark.parametrize("mode", ["wave", "block"])
 def test_long_rows_handed_to_the_grid(ctx, c1, mode):
-    """Rows longer than one group's child can take (wave: 4 * 64 * items_per_lane
-    nonzeros, block: block_threads * items_per_lane) go to the global chunks that
-    the grid-wide drain sums: same bound, bitwise reproducible, the same rows
+    """Rows longer than one group's child can take (one chunk of
+    64 * items_per_lane nonzeros) go to the global chunks that the grid-wide
+    drain sums: same bound, bitwise reproducible, the same rows
     counted as buffered, and an undersized buffer falls back to the row's lane
     (overflow flag; WC_EOVERFLOW when the fallback is refused)."""
     g, val, x, y_ref, b = c1
@@ -151,7 +151,7 @@ def test_long_rows_handed_to_the_grid(ctx, c1, mode):
     for tune in (dict(), dict(items_per_lane=1), dict(items_per_lane=1, block_threads=64),
                  dict(items_per_lane=2, threshold=2)):
         ipl, bt = tune.get("items_per_lane", 4), tune.get("block_threads", 256)
-        spill = 4 * 64 * ipl if mode == "wave" else bt * ipl
+        spill = 64 * ipl
         assert (lens > spill).any()
         y1, st = run(ctx, g, val, x, mode, stats=True, **tune)
         y2 = run(ctx, g, val, x, mode, **tune)

@@ -103,8 +103,8 @@ def test_grid_overflow_falls_back_and_can_fail(ctx, c1):
 
 @pytest.mark.parametrize("mode", ["wave", "block"])
 def test_long_items_handed_to_the_grid(ctx, c1, mode):
-    """Vertices with more edges than one group's child keeps (wave: 4 chunks,
-    block: one chunk per wave) are handed on to the grid-wide drain of the
+    """Vertices with more edges than one group's child keeps (one chunk of
+    64 * items_per_lane edges) are handed on to the grid-wide drain of the
     round: identical distances for several chunk sizes, and an undersized
     buffer falls back to the writing lanes (overflow flag; WC_EOVERFLOW when the
     fallback is refused)."""
@@ -113,7 +113,7 @@ def test_long_items_handed_to_the_grid(ctx, c1, mode):
     deg = np.diff(g.row_ptr)
     for tune in (dict(), dict(items_per_lane=1), dict(items_per_lane=1, block_threads=64), dict(threshold=2)):
         ipl, bt = tune.get("items_per_lane", 4), tune.get("block_threads", 256)
-        spill = 4 * 64 * ipl if mode == "wave" else bt * ipl
+        spill = 64 * ipl
         assert (deg > spill).any()
         d, st = ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(**tune), stats=True)
         assert np.array_equal(dev_to_u32(d), ref), tune

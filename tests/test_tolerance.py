@@ -112,10 +112,9 @@ def test_row_depth_examples():
     assert row_depth(159_772, "flat") == cascade_depth(159_772)
     assert row_depth(159_772, "wave") == cascade_depth(4) + 6 + cascade_depth(10) + 6
     assert row_depth(159_772, "block") == cascade_depth(4) + 6 + cascade_depth(10) + 6
-    # rows a wave keeps (up to 1,024) and a block keeps (up to 256 * 4)
-    assert row_depth(1024, "wave") == cascade_depth(16) + 6
-    assert row_depth(1025, "wave") == cascade_depth(4) + 6 + cascade_depth(1) + 6
-    assert row_depth(1024, "block") == cascade_depth(16) + 6
+    # rows a wave or a block keeps: up to one chunk (64 * 4)
+    assert row_depth(256, "wave") == cascade_depth(4) + 6 == row_depth(256, "block")
+    assert row_depth(257, "wave") == cascade_depth(4) + 6 + cascade_depth(1) + 6
     assert row_depth(159_772, "grid") == cascade_depth(8) + 6 + cascade_depth(5) + 6
     assert row_depth(8, "grid") == cascade_depth(8) and row_depth(9, "grid") == cascade_depth(5) + 1
     assert row_depth(0, "wave") == 0

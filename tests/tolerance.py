@@ -18,10 +18,9 @@ through, following the order the kernels use:
     lanes; still longer rows in chunks of 64 * ipl nonzeros (a cascade per lane
     plus a 64-lane butterfly), whose partials are summed lane-strided by one
     wave (a cascade plus a butterfly);
-  * wave mode: rows above the threshold lane-strided over 64 lanes, up to
-    4 * 64 * ipl nonzeros; longer rows in chunks as in grid mode;
-  * block mode: rows above the threshold by one wave up to block * ipl
-    nonzeros; longer rows in chunks as in grid mode;
+  * wave and block modes: rows above the threshold lane-strided over one
+    wave's 64 lanes, up to 64 * ipl nonzeros (one chunk); longer rows in chunks
+    as in grid mode;
   * flat mode: the row's lane alone.
 """
 import math
@@ -75,7 +74,7 @@ def row_depth(length: int, mode: str, **tune) -> int:
     chunks = math.ceil(length / (64 * ipl))
     chunked = cascade_depth(ipl) + 6 + cascade_depth(math.ceil(chunks / 64)) + 6
     if mode in ("wave", "block"):
-        spill = 4 * 64 * ipl if mode == "wave" else B * ipl
+        spill = 64 * ipl
         if length <= spill:
             return cascade_depth(math.ceil(length / 64)) + 6
         return chunked
