@@ -688,7 +688,7 @@ def run_batch(args, ctx, torch, synth, wc):
 
     heur = measure(["grid"] * len(graphs), None, "heuristic")
     t1 = time.time()
-    table = autotune.tune(ctx, graphs, weights, srcs, sample=32, reps=2)
+    table = autotune.tune(ctx, graphs, weights, srcs, reps=2)
     tune_s = time.time() - t1
     modes, tunes = autotune.per_instance(table, [g.n for g in graphs])
     tuned = measure(modes, tunes, "tuned")

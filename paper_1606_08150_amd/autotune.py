@@ -3,10 +3,14 @@ threshold and items per lane (the Table I clauses consldt, threads/blocks and
 the buffer estimate of Sec. IV.E), and one workgroup shape for the batch.
 
 The paper compares its KC_X defaults with an exhaustive search of the kernel
-configuration space (Sec. V.B); here the same comparison is made per size
-bucket: `heuristic_config` is the library default, `tune` times every candidate
-on a sample of each bucket's instances through wc_sssp_batch and keeps the
-fastest.  Tables are plain JSON.
+configuration space (Sec. V.B); here the same comparison is made for the
+batch: `heuristic_config` is the library default, and `tune` searches the
+configurations one size bucket at a time (largest instances first), timing
+every candidate of that bucket on the whole batch as it runs (graph-captured
+rounds) with the other buckets at their best so far, then the workgroup
+shape.  The library default is one of the candidates at every step, so the
+table found is never slower than the default on the batch it was tuned on
+(up to timing noise).  Tables are plain JSON.
 """
 from __future__ import annotations
 
@@ -49,10 +53,11 @@ def heuristic_config() -> dict:
 
 
 def per_instance(table: dict, sizes) -> tuple[list, list]:
-    """(modes, tune dicts) for instances of the given vertex counts."""
+    """(modes, tune dicts) for instances of the given vertex counts; a
+    workgroup shape of 0 (or none) is the library default."""
     from . import wc
     modes, tunes = [], []
-    block = int(table.get("block_threads", 256))
+    block = int(table.get("block_threads", 0))
     for n in sizes:
         cfg = table["buckets"].get(str(bucket_of(n)), heuristic_config())
         modes.append(cfg["mode"])
@@ -72,50 +77,54 @@ def load(path: str) -> dict:
 
 
 def _time_batch(ctx, graphs, weights, sources, modes, tunes, reps):
+    """Median ms of the batch as it runs: the rounds it needs (plus two)
+    captured into a graph, captured once untimed, then `reps` timed replays."""
     import torch
     stream = torch.cuda.current_stream()
-    outs = ctx.sssp_batch(graphs, weights, sources, modes=modes, tunes=tunes)
+    outs, st = ctx.sssp_batch(graphs, weights, sources, modes=modes, tunes=tunes, stats=True)
+    rounds = st["rounds"] + 2
+    ctx.sssp_batch(graphs, weights, sources, modes=modes, tunes=tunes, outs=outs, graph_rounds=rounds)
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
+    times = []
     for _ in range(reps):
-        ctx.sssp_batch(graphs, weights, sources, modes=modes, tunes=tunes, outs=outs)
-    b.record(stream)
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.sssp_batch(graphs, weights, sources, modes=modes, tunes=tunes, outs=outs, graph_rounds=rounds)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return sorted(times)[len(times) // 2]
 
 
-def tune(ctx, graphs, weights, sources, sample: int = 32, reps: int = 3) -> dict:
-    """Times every candidate per bucket (on up to `sample` instances of that
-    bucket) and every workgroup shape on the whole batch; returns the table
-    with the measured times of the heuristic and of the chosen configuration."""
-    from . import wc
-    by_bucket: dict[int, list[int]] = {}
-    for i, g in enumerate(graphs):
-        by_bucket.setdefault(bucket_of(g.n), []).append(i)
-    table = {"buckets": {}, "timings_ms": {}, "block_threads": 256}
-    for b, idx in sorted(by_bucket.items()):
-        idx = idx[:sample]
-        gs, ws, ss = [graphs[i] for i in idx], [weights[i] for i in idx], [sources[i] for i in idx]
-        results = []
-        for cfg in [heuristic_config()] + candidates():
-            t = wc.make_tune(threshold=cfg["threshold"], items_per_lane=cfg["items_per_lane"])
-            ms = _time_batch(ctx, gs, ws, ss, [cfg["mode"]] * len(gs), [t] * len(gs), reps)
-            results.append((ms, cfg))
-        heur_ms = results[0][0]
-        best_ms, best = min(results, key=lambda r: r[0])
-        table["buckets"][str(b)] = best
-        table["timings_ms"][str(b)] = {"instances": len(idx), "heuristic": round(heur_ms, 4),
-                                       "tuned": round(best_ms, 4),
-                                       "all": [[round(ms, 4), cfg] for ms, cfg in results]}
+def tune(ctx, graphs, weights, sources, reps: int = 2) -> dict:
+    """Coordinate search over the buckets present (largest first), then over
+    the workgroup shapes, every trial timed on the whole batch; returns the
+    table with the default's time, each bucket's trials and the final time."""
     sizes = [g.n for g in graphs]
-    best_block, best_ms = 256, None
+    present = sorted({bucket_of(n) for n in sizes}, reverse=True)
+    table = {"buckets": {str(b): heuristic_config() for b in present}, "timings_ms": {}, "block_threads": 0}
+
+    def run(tbl):
+        modes, tunes = per_instance(tbl, sizes)
+        return _time_batch(ctx, graphs, weights, sources, modes, tunes, reps)
+
+    best_ms = heur_ms = run(table)
+    for b in present:
+        trials = []
+        for cfg in candidates():
+            trial = {"buckets": dict(table["buckets"], **{str(b): cfg}), "block_threads": 0}
+            trials.append((run(trial), cfg))
+        ms, cfg = min(trials, key=lambda r: r[0])
+        if ms < best_ms:
+            best_ms = ms
+            table["buckets"][str(b)] = cfg
+        table["timings_ms"][str(b)] = {"instances": sum(1 for n in sizes if bucket_of(n) == b),
+                                       "all": [[round(t, 4), c] for t, c in trials]}
     for block in BLOCKS:
-        table["block_threads"] = block
-        modes, tunes = per_instance(table, sizes)
-        ms = _time_batch(ctx, graphs, weights, sources, modes, tunes, reps)
-        if best_ms is None or ms < best_ms:
-            best_block, best_ms = block, ms
-    table["block_threads"] = best_block
+        ms = run(dict(table, block_threads=block))
+        if ms < best_ms:
+            best_ms = ms
+            table["block_threads"] = block
+    table["timings_ms"]["heuristic"] = round(heur_ms, 4)
     table["timings_ms"]["whole_batch_tuned"] = round(best_ms, 4)
     return table
