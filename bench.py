@@ -1125,6 +1125,32 @@ def main():
             oracle.spmv_f64_threads(g.row_ptr, g.col, val, x, threads)
         cpu["spmv_f64_all_threads_s"] = round((time.perf_counter() - t1) / 3, 4)
         cpu["spmv_f64_threads"] = threads
+        # the batch (C4 protocol: instances side by side, one per host thread):
+        # the first 128 instances of the 512-instance batch (counter-based
+        # generator: the same instances), one Dijkstra each
+        import concurrent.futures as cf
+        inst = synth.batch_instances(128)
+
+        def one(gw):
+            d_ = oracle.sssp_dijkstra(gw[0].row_ptr, gw[0].col, gw[1], 0)
+            return oracle.sssp_reached_edges(gw[0].row_ptr, d_)
+        t1 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            reached_b = sum(ex.map(one, inst))
+        dtb = time.perf_counter() - t1
+        cpu["batch_sample"] = {"instances": len(inst), "vertices": sum(gw[0].n for gw in inst),
+                               "edges": sum(gw[0].m for gw in inst), "s": round(dtb, 3),
+                               "gteps": round(reached_b / dtb / 1e9, 4), "threads": threads}
+        del inst
+        # trees: descendants and heights of the 2^22-node random tree, one core
+        tr = synth.random_tree(1 << 22)
+        t1 = time.perf_counter()
+        oracle.tree_descendants(tr.child_ptr, tr.child)
+        cpu["tree_desc_s"] = round(time.perf_counter() - t1, 3)
+        t1 = time.perf_counter()
+        oracle.tree_height(tr.child_ptr, tr.child)
+        cpu["tree_height_s"] = round(time.perf_counter() - t1, 3)
+        del tr
         cpu["host_cpu"] = host_cpu_model()
         cpu["host_threads"] = os.cpu_count()
 
