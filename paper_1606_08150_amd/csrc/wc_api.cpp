@@ -187,7 +187,7 @@ wc_status resolve_tune(wc_ctx *ctx, const char *problem, wc_mode mode, const wc_
     if (t.buffer_alloc < 0 || t.buffer_alloc > 2)
         return fail(WC_EINVAL, "buffer_alloc must be 0 (registers / LDS), 1 (pool) or 2 (device malloc)");
     if (t.buffer_alloc != 0 && strcmp(problem, "sssp"))
-        return fail(WC_EINVAL, "buffer_alloc exists for SSSP only (and the frontier rounds of BFS)");
+        return fail(WC_EINVAL, "buffer_alloc exists for SSSP only");
     out->buf_capacity = t.buf_capacity;
     out->buffer_alloc = t.buffer_alloc;
     return WC_OK;
@@ -394,6 +394,11 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     // cut and packets filled four times coarser (scale-22 graph: 22.2 / 9.2 ms
     // at 4, 13.6 / 5.5 ms at 16, wave / block)
     if ((mode == WC_WAVE || mode == WC_BLOCK) && !strcmp(problem, "bfs")) out->items_per_lane = 16;
+    // the trees' packet queue: packets of 64 x 32 (wave) or block x 32 (block)
+    // children; against 4, the 2^22-node random tree's heights took 2.4 instead
+    // of 2.9 ms (block) and the wide layered trees 0.24 / 2.5 instead of 0.49 /
+    // 3.1 ms (block / wave); from 8 to 64 the times vary within about 30%
+    if ((mode == WC_WAVE || mode == WC_BLOCK) && !strcmp(problem, "tree")) out->items_per_lane = 32;
     out->driver = 0;
     out->allow_fallback = 0;
     out->buf_capacity = 0;

@@ -75,7 +75,7 @@ struct TreeArgs {
     int *pq_tail;
     int *outstanding;
     unsigned long long *word;  // per internal node: (children not yet finished << 32) | folded value
-    int work_cap;        // flush a buffer once its nodes carry this many children
+    int work_cap;        // children per packet: a flush cuts its nodes into packets of about this many
     unsigned long long wait_ticks;  // bound of the packet queue's waits (100 MHz ticks)
     unsigned long long *host_ring;
     DevStats *stats;
@@ -464,12 +464,14 @@ struct QueueLds {
     int pk_beg[G];
     int pk_pre[G + 1];
     int buf[2 * G];
+    int buf_w[2 * G];   // children of each buffered node
+    int hpos[2 * G + 1];  // flush: first buffer entry of each packet, then the count
     int buf_cnt;
     int buf_work;
     int pk_start;
     int pk_count;
     int flag;
-    int pad;
+    int slot0;
     int scan_tmp[2 * (G / kWave) + 2];
 };
 
@@ -490,39 +492,83 @@ __device__ __forceinline__ void gsync()
 template <int G>
 __device__ __forceinline__ int gtid() { return G > kWave ? (int)threadIdx.x : lane_id(); }
 
-// Flush the group's buffer as packets of at most G nodes (one consolidated
-// dispatch each).
+// Exclusive scan of two ints over the group (one wave, or the whole block).
+template <int G>
+__device__ __forceinline__ void group_scan2(int x, int y, int *tmp, int &ex, int &ey, int &tx, int &ty)
+{
+    if constexpr (G > kWave) {
+        block_scan2<G>(x, y, tmp, ex, ey, tx, ty);
+    } else {
+        const int ix = wave_incl_scan(x), iy = wave_incl_scan(y);
+        ex = ix - x;
+        ey = iy - y;
+        tx = readlane(ix, kWave - 1);
+        ty = readlane(iy, kWave - 1);
+    }
+}
+
+// Flush the group's buffer: its nodes become packets (consolidated
+// dispatches) of at most G nodes carrying about work_cap children each: a
+// packet starts at a node where the children buffered before it cross a
+// multiple of work_cap, or where the node count crosses a multiple of G.  All
+// packets of one flush share one reservation of node-list slots, one of queue
+// slots and one count update, so that a group that finds many recursive calls
+// pays those round trips once, not once per packet.  Thread t holds buffer
+// entries t and t + G.
 template <int G>
 __device__ void flush_buffer(const TreeArgs &a, QueueLds<G> &s, StatAcc &acc)
 {
     const int cnt = s.buf_cnt;
     if (cnt == 0) return;
     const int t = gtid<G>();
-    for (int off = 0; off < cnt; off += G) {
-        const int k = min(G, cnt - off);
-        if (t == 0) s.pk_start = atomic_add_dev(a.nl_tail, k);
-        gsync<G>();
-        const int base = s.pk_start;
-        if (t < k) a.nl[base + t] = s.buf[off + t];
-        gsync<G>();
-        if (t == 0) {
-            // the nodes (and their post-work words) become visible before the
-            // packet does
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            atomic_add_dev(a.outstanding, 1);
-            const int slot = atomic_add_dev(a.pq_tail, 1);
-            __hip_atomic_store(&a.pq[slot], ((long long)base << 32) | (long long)k, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            if (a.want_stats) acc.items += k;
-        }
-        gsync<G>();
+    const int i0 = t, i1 = t + G;
+    const int w0 = i0 < cnt ? s.buf_w[i0] : 0, w1 = i1 < cnt ? s.buf_w[i1] : 0;
+    int pre0, pre1, tw0, tw1;
+    group_scan2<G>(w0, w1, s.scan_tmp, pre0, pre1, tw0, tw1);
+    pre1 += tw0;
+    const int cap = a.work_cap;
+    // key(i) = before(i) / cap + i / G never decreases; a packet starts where it changes
+    bool h0 = false, h1 = false;
+    if (i0 < cnt)
+        h0 = i0 == 0 || pre0 / cap + i0 / G != (pre0 - s.buf_w[i0 - 1]) / cap + (i0 - 1) / G;
+    if (i1 < cnt) h1 = pre1 / cap + i1 / G != (pre1 - s.buf_w[i1 - 1]) / cap + (i1 - 1) / G;
+    int p0, p1, np0, np1;
+    group_scan2<G>(h0 ? 1 : 0, h1 ? 1 : 0, s.scan_tmp, p0, p1, np0, np1);
+    p1 += np0;
+    const int npk = np0 + np1;
+    if (h0) s.hpos[p0] = i0;
+    if (h1) s.hpos[p1] = i1;
+    if (t == 0) {
+        s.hpos[npk] = cnt;
+        s.pk_start = atomic_add_dev(a.nl_tail, cnt);
+        s.slot0 = atomic_add_dev(a.pq_tail, npk);
+        atomic_add_dev(a.outstanding, npk);
+        if (a.want_stats) acc.items += cnt;
     }
+    gsync<G>();
+    const int base = s.pk_start, slot0 = s.slot0;
+    if (i0 < cnt) a.nl[base + i0] = s.buf[i0];
+    if (i1 < cnt) a.nl[base + i1] = s.buf[i1];
+    gsync<G>();
+    // each packet's first node publishes it; the release makes the group's
+    // node-list entries (and the nodes' post-work words) visible first
+    if (h0)
+        __hip_atomic_store(&a.pq[slot0 + p0], ((long long)(base + i0) << 32) | (long long)(s.hpos[p0 + 1] - i0),
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (h1)
+        __hip_atomic_store(&a.pq[slot0 + p1], ((long long)(base + i1) << 32) | (long long)(s.hpos[p1 + 1] - i1),
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    gsync<G>();
     if (t == 0) {
         s.buf_cnt = 0;
         s.buf_work = 0;
     }
     gsync<G>();
 }
+
+// A group flushes its buffer once it holds G nodes or this many packets' worth
+// of children (more packets per flush, fewer round trips).
+constexpr int kFlushPackets = 8;
 
 template <int OP, int G, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
@@ -615,7 +661,10 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
             if constexpr (G > kWave) {
                 int pos, dummy2, add, work;
                 block_scan2<G>(cf > 0 ? 1 : 0, cf, s.scan_tmp, pos, dummy2, add, work);
-                if (cf > 0) s.buf[s.buf_cnt + pos] = c;
+                if (cf > 0) {
+                    s.buf[s.buf_cnt + pos] = c;
+                    s.buf_w[s.buf_cnt + pos] = cf;
+                }
                 gsync<G>();
                 if (t == 0) {
                     s.buf_cnt += add;
@@ -624,7 +673,10 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
             } else {
                 uint64_t m = __ballot(cf > 0);
                 int work = wave_sum_i(cf);
-                if (cf > 0) s.buf[s.buf_cnt + rank_in(m)] = c;
+                if (cf > 0) {
+                    s.buf[s.buf_cnt + rank_in(m)] = c;
+                    s.buf_w[s.buf_cnt + rank_in(m)] = cf;
+                }
                 gsync<G>();
                 if (t == 0) {
                     s.buf_cnt += __builtin_popcountll(m);
@@ -650,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void tree_queue(TreeArgs a)
                 }
             }
             gsync<G>();
-            if (s.buf_cnt >= G || s.buf_work >= a.work_cap) flush_buffer<G>(a, s, acc);
+            if (s.buf_cnt >= G || s.buf_work >= kFlushPackets * a.work_cap) flush_buffer<G>(a, s, acc);
         }
         flush_buffer<G>(a, s, acc);
         // this dispatch is finished (its own follow-up packets are already counted)

@@ -46,6 +46,8 @@ def test_default_tune_and_errors():
     assert wc.default_tune("bfs", "grid", 1)["items_per_lane"] == 2
     assert wc.default_tune("bfs", "wave", 1)["items_per_lane"] == 16
     assert wc.default_tune("bfs", "block", 1)["items_per_lane"] == 16
+    assert wc.default_tune("tree", "wave", 1)["items_per_lane"] == 32
+    assert wc.default_tune("tree", "grid", 1)["items_per_lane"] == 2
     assert wc.default_tune("tree", "block", 100)["threshold"] == 0
     t = wc.default_tune("tree", "grid", 100)
     assert t["block_threads"] == 512 and t["items_per_lane"] == 2

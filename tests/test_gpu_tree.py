@@ -116,6 +116,28 @@ def test_bookkeeping(ctx, small_tree):
     assert st["items_buffered"] == 0
 
 
+def test_flush_cuts_packets_by_children(ctx):
+    """A queue-mode flush cuts the group's buffered nodes into packets of about
+    work_cap children (64 * items_per_lane for a wave) published together: on a
+    wide layered tree (every internal node has 128..256 children) a 64-child cap
+    makes every node a packet of its own, so the dispatches are exactly the
+    internal nodes, and a larger cap packs one or two nodes per packet."""
+    t = synth.layered_tree(3, 128, 256, 0.5, seed=81)
+    d = oracle.tree_descendants(t.child_ptr, t.child)
+    h = oracle.tree_height(t.child_ptr, t.child)
+    internal = int((np.diff(t.child_ptr) > 0).sum())
+    for mode in ("wave", "block"):
+        for tune in (dict(), dict(items_per_lane=1), dict(block_threads=1024), dict(block_threads=64, items_per_lane=64)):
+            got, st = run(ctx, t, "desc", mode, stats=True, **tune)
+            assert np.array_equal(got, d), (mode, tune)
+            assert st["items_buffered"] == internal - 1, (mode, tune)
+            assert np.array_equal(run(ctx, t, "height", mode, **tune), h), (mode, tune)
+    _, st = run(ctx, t, "desc", "wave", stats=True, items_per_lane=1)
+    assert st["dispatches"] == internal
+    _, st = run(ctx, t, "desc", "wave", stats=True, items_per_lane=4)
+    assert internal / 2 <= st["dispatches"] <= internal
+
+
 def test_repeat_runs_queue_modes(ctx, small_tree):
     t, d, h = small_tree
     for _ in range(10):
