@@ -390,10 +390,10 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     // chunks split the few wide nodes over more waves (measured on 2^22 nodes)
     if (mode == WC_GRID && !strcmp(problem, "tree")) out->items_per_lane = 2;
     // recursive BFS in wave and block modes (its packet queue): every packet
-    // costs its producer a release and its consumer an acquire, so calls are
-    // cut and packets filled four times coarser (scale-22 graph: 22.2 / 9.2 ms
-    // at 4, 13.6 / 5.5 ms at 16, wave / block)
-    if ((mode == WC_WAVE || mode == WC_BLOCK) && !strcmp(problem, "bfs")) out->items_per_lane = 16;
+    // costs its consumer an acquire, so calls are cut and packets filled eight
+    // times coarser (scale-22 graph, wave / block: 13.8 / 5.7 ms at 8, 10.4 /
+    // 4.4 ms at 16, 8.9 / 3.8 ms at 32, 9.1 / 4.0 ms at 64)
+    if ((mode == WC_WAVE || mode == WC_BLOCK) && !strcmp(problem, "bfs")) out->items_per_lane = 32;
     // the trees' packet queue: packets of 64 x 32 (wave) or block x 32 (block)
     // children; against 4, the 2^22-node random tree's heights took 2.4 instead
     // of 2.9 ms (block) and the wide layered trees 0.24 / 2.5 instead of 0.49 /

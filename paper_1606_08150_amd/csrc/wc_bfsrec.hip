@@ -44,7 +44,7 @@ struct BfsArgs {
     int n;
     int src;
     int chunk;           // edges per call entry
-    int work_cap;        // flush the group buffer once its entries carry this many edges
+    int work_cap;        // edges per packet: a flush cuts its entries into packets of about this many
     int4 *nl;            // call entries (vertex, level, first edge, end edge)
     long long nl_cap;
     int *nl_tail;
@@ -65,13 +65,15 @@ __device__ void publish_entries(const BfsArgs &a, int start, int count, int per,
 {
     if (count <= 0) return;
     const int packets = (count + per - 1) / per;
+    // one release fence for all the packets: the stores after it are ordered
+    // behind the entries
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     atomic_add_dev(a.outstanding, packets);
     const int slot = atomic_add_dev(a.pq_tail, packets);
     for (int p = 0; p < packets; ++p) {
         const int s = start + p * per, k = min(per, count - p * per);
         if ((long long)slot + p < a.pq_cap)
-            __hip_atomic_store(&a.pq[slot + p], ((long long)s << 32) | (long long)k, __ATOMIC_RELEASE,
+            __hip_atomic_store(&a.pq[slot + p], ((long long)s << 32) | (long long)k, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
     if (a.want_stats) acc.items += count;
@@ -114,6 +116,7 @@ struct BfsLds {
     int pk_pre[G + 1]; // exclusive prefix of their edge counts
     uint32_t pk_lvl[G];
     int4 buf[2 * G];   // the group's buffer of small calls
+    int hpos[2 * G + 1];  // flush: first buffer entry of each packet, then the count
     int buf_cnt;
     int buf_work;
     int pk_start;
@@ -136,34 +139,93 @@ __device__ __forceinline__ void gsync()
 template <int G>
 __device__ __forceinline__ int gtid() { return G > kWave ? (int)threadIdx.x : lane_id(); }
 
-// Flushes the group's buffer of small calls as one packet (one consolidated
-// dispatch).  All threads of the group call it.
+// Exclusive scan of two ints over the group (one wave, or the whole block).
+template <int G>
+__device__ __forceinline__ void group_scan2(int x, int y, int *tmp, int &ex, int &ey, int &tx, int &ty)
+{
+    if constexpr (G > kWave) {
+        block_scan2<G>(x, y, tmp, ex, ey, tx, ty);
+    } else {
+        const int ix = wave_incl_scan(x), iy = wave_incl_scan(y);
+        ex = ix - x;
+        ey = iy - y;
+        tx = readlane(ix, kWave - 1);
+        ty = readlane(iy, kWave - 1);
+    }
+}
+
+// Flushes the group's buffer of small calls as packets (consolidated
+// dispatches) of at most G entries carrying about work_cap edges each: a
+// packet starts at an entry where the edges buffered before it cross a
+// multiple of work_cap, or every G entries.  All packets of one flush share
+// one reservation of entry slots, one release fence and one reservation of
+// queue slots.  Thread t holds buffer entries t and t + G; all threads of the
+// group call it.
 template <int G>
 __device__ void flush_calls(const BfsArgs &a, BfsLds<G> &s, StatAcc &acc)
 {
     const int cnt = s.buf_cnt;
     if (cnt == 0) return;
     const int t = gtid<G>();
-    for (int off = 0; off < cnt; off += G) {
-        const int k = min(G, cnt - off);
-        if (t == 0) s.pk_start = atomic_add_dev(a.nl_tail, k);
-        gsync<G>();
-        const int base = s.pk_start;
-        if (t < k && (long long)base + t < a.nl_cap) a.nl[base + t] = s.buf[off + t];
-        gsync<G>();
-        if (t == 0) {
-            const long long fit = std::min<long long>((long long)base + k, a.nl_cap) - base;
-            if (fit < k) a.stats->overflowed = 1;
-            publish_entries(a, base, (int)std::max<long long>(fit, 0), G, acc);
-        }
-        gsync<G>();
+    const int i0 = t, i1 = t + G;
+    const int w0 = i0 < cnt ? s.buf[i0].w - s.buf[i0].z : 0, w1 = i1 < cnt ? s.buf[i1].w - s.buf[i1].z : 0;
+    int pre0, pre1, tw0, tw1;
+    group_scan2<G>(w0, w1, s.scan_tmp, pre0, pre1, tw0, tw1);
+    pre1 += tw0;
+    const int cap = a.work_cap;
+    // key(i) = before(i) / cap + i / G never decreases; a packet starts where it changes
+    bool h0 = false, h1 = false;
+    if (i0 < cnt) {
+        const int wp = i0 > 0 ? s.buf[i0 - 1].w - s.buf[i0 - 1].z : 0;
+        h0 = i0 == 0 || pre0 / cap + i0 / G != (pre0 - wp) / cap + (i0 - 1) / G;
     }
+    if (i1 < cnt) {
+        const int wp = s.buf[i1 - 1].w - s.buf[i1 - 1].z;
+        h1 = pre1 / cap + i1 / G != (pre1 - wp) / cap + (i1 - 1) / G;
+    }
+    int p0, p1, np0, np1;
+    group_scan2<G>(h0 ? 1 : 0, h1 ? 1 : 0, s.scan_tmp, p0, p1, np0, np1);
+    p1 += np0;
+    const int npk = np0 + np1;
+    if (h0) s.hpos[p0] = i0;
+    if (h1) s.hpos[p1] = i1;
     if (t == 0) {
+        s.hpos[npk] = cnt;
+        s.pk_start = atomic_add_dev(a.nl_tail, cnt);
+    }
+    gsync<G>();
+    const int base = s.pk_start;
+    if (i0 < cnt && (long long)base + i0 < a.nl_cap) a.nl[base + i0] = s.buf[i0];
+    if (i1 < cnt && (long long)base + i1 < a.nl_cap) a.nl[base + i1] = s.buf[i1];
+    gsync<G>();
+    if (t == 0) {
+        // entries beyond the list's end are dropped (the overflow flag makes the
+        // host recompute the levels); only packets with entries are published
+        const int fit = (int)std::max<long long>(0, std::min<long long>((long long)base + cnt, a.nl_cap) - base);
+        if (fit < cnt) a.stats->overflowed = 1;
+        int npub = 0;
+        while (npub < npk && s.hpos[npub] < fit) ++npub;
+        if (npub > 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomic_add_dev(a.outstanding, npub);
+            const int slot = atomic_add_dev(a.pq_tail, npub);
+            for (int p = 0; p < npub; ++p) {
+                const int k = min(s.hpos[p + 1], fit) - s.hpos[p];
+                if ((long long)slot + p < a.pq_cap)
+                    __hip_atomic_store(&a.pq[slot + p], ((long long)(base + s.hpos[p]) << 32) | (long long)k,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (a.want_stats) acc.items += fit;
+        }
         s.buf_cnt = 0;
         s.buf_work = 0;
     }
     gsync<G>();
 }
+
+// A group flushes its buffer once it holds G calls or this many packets' worth
+// of edges (more packets per flush, fewer round trips).
+constexpr int kFlushPackets = 8;
 
 __global__ void bfs_rec_init(BfsArgs a, long long pq_cap)
 {
@@ -311,7 +373,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_rec_queue(BfsArgs a)
                 }
             }
             gsync<G>();
-            if (s.buf_cnt >= G || s.buf_work >= a.work_cap) flush_calls<G>(a, s, acc);
+            if (s.buf_cnt >= G || s.buf_work >= kFlushPackets * a.work_cap) flush_calls<G>(a, s, acc);
         }
         flush_calls<G>(a, s, acc);
         // this dispatch is finished (its own follow-up packets are already counted)
