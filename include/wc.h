@@ -98,12 +98,19 @@ typedef struct {
 typedef struct {
     int32_t threshold;      /* items with more than this much work are buffered (the
                                THRESHOLD of Fig. 1(b)); <= 0: per-problem default */
-    int32_t block_threads;  /* workgroup size: 64, 128, 256, 512 or 1024; <= 0: 256 */
+    int32_t block_threads;  /* workgroup size: 64, 128, 256, 512 or 1024; <= 0: the
+                               default of wc_default_tune (512 at grid level except
+                               coloring, 256 otherwise) */
     int32_t grid_blocks;    /* workgroups of the moldable drain/persistent grid;
                                <= 0: resident maximum from the occupancy query (KC_1) */
     int32_t items_per_lane; /* the "const" of the Sec. IV.E buffer-size estimate: work
                                items per drain lane; grid-level chunks hold
-                               64 * items_per_lane elements; <= 0: 4 */
+                               64 * items_per_lane elements, queue-mode packets
+                               (BFS, trees) about 64 * items_per_lane (wave) or
+                               block_threads * items_per_lane (block) children;
+                               at most 64; <= 0: the default of wc_default_tune
+                               (4; grid level 2, 8 for SpMV; 32 in the queue
+                               modes) */
     int32_t driver;         /* 0: one launch per round/level (host relaunch);
                                1: reserved for a persistent co-resident launch: not
                                   available, every entry point refuses it with
@@ -175,9 +182,10 @@ wc_status wc_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src, 
  * A visit of v is a recursive call whose children are the neighbours it brings
  * to a lower level (parallel recursion, Sec. II.B).
  *   WC_WAVE, WC_BLOCK: the recursion path.  The recursive calls a wave
- *     (workgroup) makes go into its buffer; a full buffer is one consolidated
- *     dispatch, a packet of a device-wide queue that any group of a persistent
- *     grid processes (no grid-wide barrier).  The call of a vertex with more
+ *     (workgroup) makes go into its buffer; a full buffer is flushed as
+ *     consolidated dispatches, packets of about 64 * items_per_lane (wave) or
+ *     block_threads * items_per_lane (block) edges in a device-wide queue that
+ *     any group of a persistent grid processes (no grid-wide barrier).  The call of a vertex with more
  *     than 64 * items_per_lane out-edges is split into packets of its own, so
  *     a hub is spread over many groups.  Waits for packets are bounded
  *     (WC_ETIMEOUT).  A call list too small (tune->buf_capacity entries; by
@@ -261,7 +269,14 @@ wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio, int32_t *
 /* Tree descendants (recursion of Fig. 1(c)): desc[v] = number of proper
  * descendants of v.  A node with children is a recursive call whose work is
  * consolidated per `mode`; a leaf gets 0; the post-work folds each child c
- * into its parent as 1 + desc[c]. */
+ * into its parent as 1 + desc[c].
+ *   WC_FLAT, WC_GRID: level-synchronous (one launch per level, a graph of all
+ *     levels replayed by a repeated call), the folds by one bottom-up pass per level.
+ *   WC_WAVE, WC_BLOCK: no grid-wide barrier: a persistent grid whose groups
+ *     flush the calls they find as packets of about 64 * items_per_lane (wave)
+ *     or block_threads * items_per_lane (block) children into a device-wide
+ *     queue; a node's post-work runs when its last child finishes.  Waits for
+ *     packets are bounded (WC_ETIMEOUT). */
 wc_status wc_tree_descendants(wc_ctx *ctx, const wc_tree *t, int32_t *desc, wc_mode mode, const wc_tune *tune,
                               hipStream_t stream, wc_stats *stats);
 
