@@ -754,6 +754,16 @@ def run_serving(args, torch, synth, wc):
 
 
 def main():
+    if "--summarize-kernel-stats" in sys.argv:
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--summarize-kernel-stats", action="store_true")
+        sp.add_argument("--stats-csv", required=True)
+        sp.add_argument("--workload", required=True)
+        sp.add_argument("--command", required=True)
+        sp.add_argument("--out-name", required=True)
+        a = sp.parse_args()
+        summarize_kernel_stats(a.stats_csv, a.workload, a.command, a.out_name)
+        return
     if "--summarize-counters" in sys.argv:
         sp = argparse.ArgumentParser()
         sp.add_argument("--summarize-counters", action="store_true")
