@@ -339,7 +339,7 @@ wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *graphs, const 
  * with the defaults); a call whose workspace could exceed the array returns
  * WC_EINVAL before anything is enqueued, as do bad arguments and
  * tune->driver != 0.  Flat mode uses no workspace; wave and block modes only
- * for the rows they hand on to the grid (about 0.12 m bytes with the defaults).
+ * for the rows they hand on to the grid (about 0.22 m bytes with the defaults).
  * Runs on the calling thread's current device (hipSetDevice); `stream` must
  * belong to it.  The call only enqueues; the caller synchronizes.  Every call
  * on one device shares its array: calls whose stream work overlaps on one
