@@ -7,7 +7,8 @@
 // ("work"); a heavy one is inserted into the consolidation buffer of its mode
 // and relaxed by the consolidated child ("process_neighbors"):
 //   wave  - the wave's ballot mask is the buffer; the whole wave then relaxes
-//           each buffered vertex's edges, 64 lanes side by side (no barrier).
+//           the concatenated edge ranges of its buffered vertices, 64 lanes
+//           side by side (no barrier).
 //   block - thread-ordered LDS buffer; after the workgroup barrier the block
 //           relaxes the concatenated edge ranges of all buffered vertices, each
 //           thread taking every BLOCK-th edge (a multi-thread child wrapped in a
@@ -122,14 +123,6 @@ __device__ __forceinline__ int relax_lane(const SsspArgs &a, int beg, int end, u
     return upd;
 }
 
-// The wave cooperatively relaxes edges [beg, end) of one vertex (uniform arguments).
-__device__ __forceinline__ int relax_wave(const SsspArgs &a, int beg, int end, uint32_t du, int next)
-{
-    int upd = 0;
-    for (int b = beg; b < end; b += kWave * kUnroll) upd += relax_batch<true>(a, b + lane_id(), kWave, end, du, next);
-    return upd;
-}
-
 // Two chunks of the grid buffer at once (uniform arguments): each lane keeps
 // 2 * kUnroll edges in flight.  The chunks' source distances are read after
 // their edges are requested (they may have improved since the vertex was
@@ -206,6 +199,73 @@ __device__ __forceinline__ int spill_chunks(const SsspArgs &a, int r, int u, int
     return upd;
 }
 
+// The consolidated child of a wave (G = 64) or a block (G = BLOCK) over its
+// buffer of nb items: item i holds edges [beg_i, beg_i + deg_i) of a vertex at
+// distance du_i, and pre_i is the exclusive prefix of the degrees (total in
+// all).  The group relaxes the concatenated edge ranges, G * kUnroll edges per
+// step, thread t taking flattened edges t, t + G, ...: each thread finds the
+// item of its edge with a cursor that only moves forward, so the lanes stay
+// busy however the degrees are spread over the items.
+template <int G>
+__device__ __forceinline__ int relax_items(const SsspArgs &a, const int *ibeg, const uint32_t *idu, const int *ipre,
+                                           int nb, int total, int t, int next)
+{
+    int upd = 0, it = 0;
+    for (int j0 = t; j0 < total; j0 += G * kUnroll) {
+        int v[kUnroll];
+        uint32_t nd[kUnroll], dv[kUnroll];
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+            const int j = j0 + q * G;
+            v[q] = -1;
+            nd[q] = 0;
+            if (j < total) {
+                while (it + 1 < nb && ipre[it + 1] <= j) ++it;
+                const int e = ibeg[it] + (j - ipre[it]);
+                v[q] = a.col[e];
+                nd[q] = add_sat(idu[it], weight(a, e));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) dv[q] = v[q] >= 0 ? a.dist[v[q]] : 0u;
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q)
+            if (v[q] >= 0) upd += relax_loaded<true>(a, v[q], nd[q], dv[q], next);
+    }
+    return upd;
+}
+
+// relax_items over a buffer in global memory: item i is (beg, du, pre, 0).
+template <int G>
+__device__ __forceinline__ int relax_items_global(const SsspArgs &a, const int4 *gb, int nb, int total, int t,
+                                                  int next)
+{
+    int upd = 0, it = 0;
+    for (int j0 = t; j0 < total; j0 += G * kUnroll) {
+        int v[kUnroll];
+        uint32_t nd[kUnroll], dv[kUnroll];
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+            const int j = j0 + q * G;
+            v[q] = -1;
+            nd[q] = 0;
+            if (j < total) {
+                while (it + 1 < nb && gb[it + 1].z <= j) ++it;
+                const int4 d = gb[it];
+                const int e = d.x + (j - d.z);
+                v[q] = a.col[e];
+                nd[q] = add_sat((uint32_t)d.y, weight(a, e));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) dv[q] = v[q] >= 0 ? a.dist[v[q]] : 0u;
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q)
+            if (v[q] >= 0) upd += relax_loaded<true>(a, v[q], nd[q], dv[q], next);
+    }
+    return upd;
+}
+
 // Buffers in global memory, for the allocator comparison of Sec. V.A: the
 // paper's consolidation buffers live in global memory and come either from a
 // pre-allocated pool or from the device's malloc.  Here the group writes its
@@ -218,9 +278,10 @@ __device__ __forceinline__ int4 *group_buffer(const SsspArgs &a, int slot, int i
     return static_cast<int4 *>(malloc((size_t)items * sizeof(int4)));
 }
 
-// Wave mode: items (begin, end, du) of the lanes in `mask` through a global buffer.
-__device__ __forceinline__ int wave_child_global(const SsspArgs &a, uint64_t mask, bool mine, int beg, int end,
-                                                 uint32_t du, int next, bool &done)
+// Wave mode: the items of the lanes in `mask` (pre: exclusive prefix of their
+// degrees, total in all) through a global buffer.
+__device__ __forceinline__ int wave_child_global(const SsspArgs &a, uint64_t mask, bool mine, int beg, int pre,
+                                                 int total, uint32_t du, int next, bool &done)
 {
     const int nb = __builtin_popcountll(mask);
     unsigned long long p = 0;
@@ -236,17 +297,28 @@ __device__ __forceinline__ int wave_child_global(const SsspArgs &a, uint64_t mas
         if (lane_id() == 0) a.stats->overflowed = 1;
         return 0;
     }
-    if (mine) buf[rank_in(mask)] = make_int4(beg, end, (int)du, 0);
+    if (mine) buf[rank_in(mask)] = make_int4(beg, (int)du, pre, 0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    int upd = 0;
-    for (int i = 0; i < nb; ++i) {
-        const int4 it = buf[i];
-        upd += relax_wave(a, __builtin_amdgcn_readfirstlane(it.x), __builtin_amdgcn_readfirstlane(it.y),
-                          (uint32_t)__builtin_amdgcn_readfirstlane(it.z), next);
-    }
+    const int upd = relax_items_global<kWave>(a, buf, nb, total, lane_id(), next);
     if (a.buffer_alloc == 2 && lane_id() == 0) free(buf);
     return upd;
+}
+
+// A wave's buffer in LDS (wave mode): up to 64 items per wave.
+template <int BLOCK>
+struct WaveBuf {
+    int beg[BLOCK / kWave][kWave];
+    uint32_t du[BLOCK / kWave][kWave];
+    int pre[BLOCK / kWave][kWave];
+};
+
+// One wave runs in lockstep; the fence keeps the compiler from moving the
+// wave's LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 template <int BLOCK>
@@ -262,7 +334,11 @@ struct BlockBuf {
 // Parent kernel of round r in flat, wave and block modes: thread i takes vertex
 // i (Fig. 1(b)); the vertices stamped r form the frontier.  Grid-stride windows
 // of BLOCK vertices; every thread of a block runs the same number of windows.
-template <int MODE, int BLOCK>
+// ALLOC: the instantiation with the global-memory buffers of the allocator
+// comparison (pool slices or device malloc); the device-malloc call needs so
+// many registers that it is kept out of the default kernels (which then run
+// 7 waves per SIMD instead of 4).
+template <int MODE, int BLOCK, bool ALLOC = false>
 __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
 {
     const int act = a.active[(r % 3) * kPad];
@@ -305,21 +381,34 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
         const bool mine = heavy && !spill;
 
         if constexpr (MODE == WC_WAVE) {
-            // insert_buffer = ballot; the mask is the wave's buffer; no barrier needed
-            uint64_t mask = __ballot(mine);
-            bool done = false;
-            if (a.buffer_alloc && mask) upd += wave_child_global(a, mask, mine, beg, end, du, next, done);
-            if (done) mask = 0;
-            while (mask) {
-                int b = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                upd += relax_wave(a, readlane(beg, b), readlane(end, b), readlane_u(du, b), next);
+            // insert_buffer = ballot: the mask is the wave's buffer and the lanes'
+            // ranks order it; no barrier is needed within one wave
+            const uint64_t mask = __ballot(mine);
+            if (mask) {
+                const int incl = wave_incl_scan(mine ? deg : 0);
+                const int total = readlane(incl, kWave - 1), pre = incl - (mine ? deg : 0);
+                bool done = false;
+                if constexpr (ALLOC) upd += wave_child_global(a, mask, mine, beg, pre, total, du, next, done);
+                if (!done) {
+                    __shared__ WaveBuf<BLOCK> wb;
+                    const int w = threadIdx.x / kWave;
+                    if (mine) {
+                        const int k = rank_in(mask);
+                        wb.beg[w][k] = beg;
+                        wb.du[w][k] = du;
+                        wb.pre[w][k] = pre;
+                    }
+                    wave_lds_sync();
+                    upd += relax_items<kWave>(a, wb.beg[w], wb.du[w], wb.pre[w], __builtin_popcountll(mask), total,
+                                              lane, next);
+                    wave_lds_sync();  // the next window rewrites the wave's entries
+                }
             }
         } else if constexpr (MODE == WC_BLOCK) {
             __shared__ BlockBuf<BLOCK> sb;
             int k, off, nb, total;
             block_scan2<BLOCK>(mine ? 1 : 0, mine ? deg : 0, sb.scan_tmp, k, off, nb, total);
-            if (a.buffer_alloc) {
+            if constexpr (ALLOC) {
                 // the buffer in global memory (allocator comparison); NULL: LDS
                 if (threadIdx.x == 0) {
                     sb.gbuf = nb ? group_buffer(a, blockIdx.x * (BLOCK + 1), nb + 1) : nullptr;
@@ -327,7 +416,7 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
                 }
                 __syncthreads();
             }
-            int4 *const gb = a.buffer_alloc ? sb.gbuf : nullptr;
+            int4 *const gb = ALLOC ? sb.gbuf : nullptr;
             if (mine) {
                 if (gb) {
                     gb[k] = make_int4(beg, (int)du, off, 0);
@@ -345,40 +434,12 @@ __global__ __launch_bounds__(BLOCK) void sssp_round(SsspArgs a, int r)
             // also when all of them were handed on to the grid
             if (a.want_stats && __syncthreads_or(heavy) && threadIdx.x == 0) acc.dispatches += 1;
             __syncthreads();  // the "synchronize" between inserts and the child
-            // the block relaxes the concatenated edge ranges, kUnroll edges per
-            // thread in flight: flattened index j -> (item, edge) by a cursor
-            int it = 0;
-            for (int j0 = threadIdx.x; j0 < total; j0 += BLOCK * kUnroll) {
-                int v[kUnroll];
-                uint32_t nd[kUnroll], dv[kUnroll];
-#pragma unroll
-                for (int q = 0; q < kUnroll; ++q) {
-                    const int j = j0 + q * BLOCK;
-                    v[q] = -1;
-                    nd[q] = 0;
-                    if (j < total) {
-                        if (gb) {
-                            while (it + 1 < nb && gb[it + 1].z <= j) ++it;
-                            const int4 d = gb[it];
-                            const int e = d.x + (j - d.z);
-                            v[q] = a.col[e];
-                            nd[q] = add_sat((uint32_t)d.y, weight(a, e));
-                        } else {
-                            while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
-                            const int e = sb.beg[it] + (j - sb.pre[it]);
-                            v[q] = a.col[e];
-                            nd[q] = add_sat(sb.du[it], weight(a, e));
-                        }
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kUnroll; ++q) dv[q] = v[q] >= 0 ? a.dist[v[q]] : 0u;
-#pragma unroll
-                for (int q = 0; q < kUnroll; ++q)
-                    if (v[q] >= 0) upd += relax_loaded<true>(a, v[q], nd[q], dv[q], next);
-            }
+            // the block relaxes the concatenated edge ranges of its items
+            if (ALLOC && gb) upd += relax_items_global<BLOCK>(a, gb, nb, total, threadIdx.x, next);
+            else upd += relax_items<BLOCK>(a, sb.beg, sb.du, sb.pre, nb, total, threadIdx.x, next);
             __syncthreads();  // LDS buffer is reused by the next window
-            if (gb && a.buffer_alloc == 2 && threadIdx.x == 0) free(gb);
+            if constexpr (ALLOC)
+                if (gb && a.buffer_alloc == 2 && threadIdx.x == 0) free(gb);
         }
         if (a.want_stats) {
             acc.updates += upd_inline + upd;
@@ -635,14 +696,20 @@ struct KernelSet {
 };
 
 template <int BLOCK>
-KernelSet pick_block(wc_mode mode)
+KernelSet pick_block(wc_mode mode, bool alloc)
 {
     const void *drain = reinterpret_cast<const void *>(&sssp_drain<BLOCK, false>);
     const void *drain_stamp = reinterpret_cast<const void *>(&sssp_drain<BLOCK, true>);
     switch (mode) {
     case WC_FLAT: return {reinterpret_cast<const void *>(&sssp_round<WC_FLAT, BLOCK>), nullptr};
-    case WC_WAVE: return {reinterpret_cast<const void *>(&sssp_round<WC_WAVE, BLOCK>), drain_stamp};
-    case WC_BLOCK: return {reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK>), drain_stamp};
+    case WC_WAVE:
+        return {alloc ? reinterpret_cast<const void *>(&sssp_round<WC_WAVE, BLOCK, true>)
+                      : reinterpret_cast<const void *>(&sssp_round<WC_WAVE, BLOCK>),
+                drain_stamp};
+    case WC_BLOCK:
+        return {alloc ? reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK, true>)
+                      : reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK>),
+                drain_stamp};
     default: return {reinterpret_cast<const void *>(&sssp_round_grid2<BLOCK>), drain};
     }
 }
@@ -653,14 +720,14 @@ const char *round_name(wc_mode mode)
     return names[mode];
 }
 
-KernelSet pick(wc_mode mode, int block)
+KernelSet pick(wc_mode mode, int block, bool alloc = false)
 {
     switch (block) {
-    case 64: return pick_block<64>(mode);
-    case 128: return pick_block<128>(mode);
-    case 512: return pick_block<512>(mode);
-    case 1024: return pick_block<1024>(mode);
-    default: return pick_block<256>(mode);
+    case 64: return pick_block<64>(mode, alloc);
+    case 128: return pick_block<128>(mode, alloc);
+    case 512: return pick_block<512>(mode, alloc);
+    case 1024: return pick_block<1024>(mode, alloc);
+    default: return pick_block<256>(mode, alloc);
     }
 }
 
@@ -689,8 +756,8 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
         return fail(WC_EINVAL, "drivers 2 and 3 are comparison variants of grid mode only");
     if (cfg.buffer_alloc != 0 && mode != WC_WAVE && mode != WC_BLOCK)
         return fail(WC_EINVAL, "buffer_alloc applies to the wave and block modes only");
-    if (cfg.block != block) {
-        ks = pick(mode, cfg.block);
+    if (cfg.block != block || cfg.buffer_alloc != 0) {
+        ks = pick(mode, cfg.block, cfg.buffer_alloc != 0);
         resident = resident_blocks(ctx, ks.round, cfg.block);
     }
     const long long n = g->n, m = g->m;
