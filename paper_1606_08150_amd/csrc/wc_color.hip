@@ -15,7 +15,7 @@
 // A queued vertex's release loop is the nested work; one with more than
 // `threshold` neighbours is consolidated per mode:
 //   wave  - the wave's ballot mask is the buffer; the wave walks each buffered
-//           vertex's neighbours 64 at a time (no barrier).
+//           vertex's neighbours 64 x kUnroll at a time (no barrier).
 //   block - thread-ordered LDS buffer; after the barrier the block walks the
 //           concatenated neighbour ranges.
 //   grid  - global buffer of (vertex, neighbour range) chunks drained by a
@@ -159,12 +159,38 @@ __device__ __forceinline__ int release_range(const ColorArgs &a, int first, int 
     return rel;
 }
 
-// One flagged neighbour w (block-level drain, one edge per thread).
-__device__ __forceinline__ int release_one(const ColorArgs &a, int w, int color_next, const Next &nx, int &readied)
+// The consolidated child of a block (G = BLOCK) over its buffer of nb
+// vertices: vertex i releases along rcol[beg_i, beg_i + deg_i),
+// pre_i being the exclusive prefix of the degrees (total in all).  The group
+// walks the concatenated ranges, G * kUnroll edges per step, thread t taking
+// flattened edges t, t + G, ...; a cursor that only moves forward finds each
+// edge's vertex.  Returns the number of releases.
+template <int G>
+__device__ __forceinline__ int release_items(const ColorArgs &a, const int *ibeg, const int *ipre, int nb, int total,
+                                             int t, int color_next, const Next &nx, int &readied)
 {
-    const bool ready = w >= 0 && atomic_add_dev(&a.wait[w], -1) == 1;
-    push_ready<false>(a, ready, w, color_next, nx, readied);
-    return w >= 0 ? 1 : 0;
+    int rel = 0, it = 0;
+    for (int j0 = t; j0 < total; j0 += G * kUnroll) {
+        int w[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            const int j = j0 + k * G;
+            w[k] = kNoRelease;
+            if (j < total) {
+                while (it + 1 < nb && ipre[it + 1] <= j) ++it;
+                w[k] = a.rcol[ibeg[it] + (j - ipre[it])];
+            }
+        }
+        int old[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            old[k] = w[k] >= 0 ? atomic_add_dev(&a.wait[w[k]], -1) : 0;
+            rel += w[k] >= 0 ? 1 : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) push_ready<false>(a, old[k] == 1, w[k], color_next, nx, readied);
+    }
+    return rel;
 }
 
 template <int BLOCK>
@@ -211,6 +237,9 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
         }
         if (member && !heavy) acc.updates += release_range<false>(a, beg, 1, end, r + 1, nx, readied);
         if constexpr (MODE == WC_WAVE) {
+            // the ballot mask is the wave's buffer; the wave walks each buffered
+            // vertex's range 64 x kUnroll neighbours at a time (walking the
+            // concatenated ranges measured 12% slower here)
             uint64_t mask = __ballot(heavy);
             while (mask) {
                 const int b = __builtin_ctzll(mask);
@@ -230,12 +259,7 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
                 if (a.want_stats && nb) acc.dispatches += 1;
             }
             __syncthreads();
-            int it = 0;
-            for (int j = threadIdx.x; j < total; j += BLOCK) {
-                while (it + 1 < nb && sb.pre[it + 1] <= j) ++it;
-                const int w = a.rcol[sb.beg[it] + (j - sb.pre[it])];
-                acc.updates_buffered += release_one(a, w, r + 1, nx, readied);
-            }
+            acc.updates_buffered += release_items<BLOCK>(a, sb.beg, sb.pre, nb, total, threadIdx.x, r + 1, nx, readied);
             __syncthreads();  // the LDS buffer is reused by the next window
         }
     }

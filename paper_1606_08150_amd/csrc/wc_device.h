@@ -73,6 +73,14 @@ __device__ __forceinline__ int atomic_load_dev(const int *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// One wave runs in lockstep; the fence keeps the compiler from moving the
+// wave's LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ---- wave-aggregated append ---------------------------------------------------------------------
 // Every active lane must call this (it issues a ballot).  Lanes with pred
 // receive distinct consecutive slots starting at the value *tail had; the

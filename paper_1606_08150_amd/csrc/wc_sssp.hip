@@ -313,14 +313,6 @@ struct WaveBuf {
     int pre[BLOCK / kWave][kWave];
 };
 
-// One wave runs in lockstep; the fence keeps the compiler from moving the
-// wave's LDS accesses across this point.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 template <int BLOCK>
 struct BlockBuf {
     int beg[BLOCK];
