@@ -155,7 +155,7 @@ def summarize_kernel_stats(stats_csv, workload, command, out_name):
 
 def static_resources(kernels):
     """{kernel: (VGPRs, scratch B/lane, waves per SIMD, LDS B/block)} of the 512-thread
-    instantiations, from hipcc's kernel-resource-usage remarks on the sources."""
+    instantiations the timed path runs, from hipcc's kernel-resource-usage remarks on the sources."""
     import re
     import subprocess
     csrc = os.path.join(ROOT, "paper_1606_08150_amd", "csrc")
@@ -170,7 +170,9 @@ def static_resources(kernels):
             m = re.search(r"Function Name: (\S+)", line)
             if m:
                 name = m.group(1)
-                cur = next((k for k in kernels if f"{len(k)}{k}ILi512E" in name), None)
+                # the instantiation the timed path runs: every bool parameter
+                # (stamps, stats, hot columns) false
+                cur = next((k for k in kernels if f"{len(k)}{k}ILi512E" in name and "Lb1E" not in name), None)
                 if cur:
                     out[cur] = {}
                 continue

@@ -328,8 +328,9 @@ __global__ __launch_bounds__(kCols * kWave) void spmv_scan(SpmvArgs a, int nbloc
 }
 
 // Parent pass of grid mode: light rows inline, heavy rows written into their
-// bin at the offsets the scan gave this block.
-template <int BLOCK>
+// bin at the offsets the scan gave this block.  STATS: the instantiation that
+// counts work for wc_stats (without it no counters are kept live).
+template <int BLOCK, bool STATS>
 __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
 {
     __shared__ int cur[kCols], binoff[kBins], cnt[kCols];
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
         }
         const int len = end - beg;
         const bool heavy = len > a.threshold;
-        if (a.want_stats) count_stats(acc, len, heavy, false);
+        if (STATS) count_stats(acc, len, heavy, false);
         if (valid && !heavy) a.y[r] = dot_strided_u<2 * kUnroll>(a, beg, 1, end);
         int bin = -1, local = 0, nch = 0, mlocal = 0;
         if (heavy) {
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
         __syncthreads();
         if (threadIdx.x < kCols) cur[threadIdx.x] += cnt[threadIdx.x];
     }
-    if (a.want_stats) stat_flush(a.stats, acc);
+    if (STATS) stat_flush(a.stats, acc);
 }
 
 // Consolidated child of grid mode.  Wave tasks: for bin b (g = 2^b lanes per
@@ -549,10 +550,11 @@ struct SpmvKernels {
 };
 
 template <int BLOCK>
-SpmvKernels pick_block(wc_mode mode, bool hot)
+SpmvKernels pick_block(wc_mode mode, bool hot, bool stats)
 {
     SpmvKernels k{nullptr, reinterpret_cast<const void *>(&spmv_classify<BLOCK>),
-                  reinterpret_cast<const void *>(&spmv_parent_grid<BLOCK>),
+                  stats ? reinterpret_cast<const void *>(&spmv_parent_grid<BLOCK, true>)
+                        : reinterpret_cast<const void *>(&spmv_parent_grid<BLOCK, false>),
                   hot ? reinterpret_cast<const void *>(&spmv_drain<BLOCK, true>)
                       : reinterpret_cast<const void *>(&spmv_drain<BLOCK, false>),
                   reinterpret_cast<const void *>(&spmv_combine<BLOCK>)};
@@ -565,14 +567,14 @@ SpmvKernels pick_block(wc_mode mode, bool hot)
     return k;
 }
 
-SpmvKernels pick(wc_mode mode, int block, bool hot)
+SpmvKernels pick(wc_mode mode, int block, bool hot, bool stats)
 {
     switch (block) {
-    case 64: return pick_block<64>(mode, hot);
-    case 128: return pick_block<128>(mode, hot);
-    case 512: return pick_block<512>(mode, hot);
-    case 1024: return pick_block<1024>(mode, hot);
-    default: return pick_block<256>(mode, hot);
+    case 64: return pick_block<64>(mode, hot, stats);
+    case 128: return pick_block<128>(mode, hot, stats);
+    case 512: return pick_block<512>(mode, hot, stats);
+    case 1024: return pick_block<1024>(mode, hot, stats);
+    default: return pick_block<256>(mode, hot, stats);
     }
 }
 
@@ -596,13 +598,13 @@ wc_status spmv_shape(int num_cus, const wc_csr *g, const float *val, wc_mode mod
 {
     int block = (tune && tune->block_threads > 0) ? tune->block_threads : 256;
     p->mode = mode;
-    p->ks = pick(mode, block, hot);
+    p->ks = pick(mode, block, hot, want_stats);
     int resident = resident_blocks_on(num_cus, p->ks.parent, block);
     wc_status st = resolve_tune(nullptr, "spmv", mode, tune, resident, &p->cfg);
     if (st != WC_OK) return st;
     const Config &cfg = p->cfg;
     if (cfg.block != block) {
-        p->ks = pick(mode, cfg.block, hot);
+        p->ks = pick(mode, cfg.block, hot, want_stats);
         resident = resident_blocks_on(num_cus, p->ks.parent, cfg.block);
     }
     // the drain of the hot-column layout holds 64 KiB of LDS: its own residency

@@ -473,7 +473,9 @@ __device__ __forceinline__ int relax_lane2(const SsspArgs &a, int b0, int e0, ui
 // vertices of a window of 2 * BLOCK (u and u + BLOCK), with the loads of both
 // issued together: the parent is bound by the latency of its dependent loads
 // (frontier test, then CSR range and distance, then edges, then targets).
-template <int BLOCK>
+// STATS: the instantiation that counts work for wc_stats; without it the
+// kernel keeps no counters live and fits its registers without spilling.
+template <int BLOCK, bool STATS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void sssp_round_grid2(SsspArgs a,
                                                                                          int r)
 {
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
                 const int deg = end[k] - beg[k];
                 heavy[k] = deg > a.threshold;
                 nch[k] = heavy[k] ? (deg + a.chunk - 1) / a.chunk : 0;
-                if (a.want_stats) {
+                if (STATS) {
                     acc.edges += deg;
                     acc.buffered += heavy[k] ? deg : 0;
                     acc.items += heavy[k] ? 1 : 0;
@@ -544,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
             // work: light items relax inline
             const int upd_inline = relax_lane2(a, beg[0], heavy[0] ? beg[0] : end[0], du[0], beg[1],
                                                heavy[1] ? beg[1] : end[1], du[1], next);
-            if (a.want_stats) acc.updates += upd_inline;
+            if (STATS) acc.updates += upd_inline;
 #pragma unroll
             for (int k = 0; k < V; ++k)
                 if (end[k] > beg[k] && !heavy[k]) a.relaxed_at[u[k]] = du[k];
@@ -596,14 +598,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
                 }
             }
             __syncthreads();  // the LDS arrays are rewritten by the next window
-            if (a.want_stats) {
+            if (STATS) {
                 acc.updates += upd_over;
                 acc.updates_buffered += upd_over;
             }
             mark_active(a, r, upd_inline + upd_over > 0);
         }
     }
-    if (a.want_stats) stat_flush(a.stats, acc);
+    if (STATS) stat_flush(a.stats, acc);
 }
 
 // Consolidated child of grid-level consolidation: one wave per chunk, chunks
@@ -688,7 +690,7 @@ struct KernelSet {
 };
 
 template <int BLOCK>
-KernelSet pick_block(wc_mode mode, bool alloc)
+KernelSet pick_block(wc_mode mode, bool alloc, bool stats)
 {
     const void *drain = reinterpret_cast<const void *>(&sssp_drain<BLOCK, false>);
     const void *drain_stamp = reinterpret_cast<const void *>(&sssp_drain<BLOCK, true>);
@@ -702,7 +704,10 @@ KernelSet pick_block(wc_mode mode, bool alloc)
         return {alloc ? reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK, true>)
                       : reinterpret_cast<const void *>(&sssp_round<WC_BLOCK, BLOCK>),
                 drain_stamp};
-    default: return {reinterpret_cast<const void *>(&sssp_round_grid2<BLOCK>), drain};
+    default:
+        return {stats ? reinterpret_cast<const void *>(&sssp_round_grid2<BLOCK, true>)
+                      : reinterpret_cast<const void *>(&sssp_round_grid2<BLOCK, false>),
+                drain};
     }
 }
 
@@ -712,14 +717,14 @@ const char *round_name(wc_mode mode)
     return names[mode];
 }
 
-KernelSet pick(wc_mode mode, int block, bool alloc = false)
+KernelSet pick(wc_mode mode, int block, bool alloc = false, bool stats = false)
 {
     switch (block) {
-    case 64: return pick_block<64>(mode, alloc);
-    case 128: return pick_block<128>(mode, alloc);
-    case 512: return pick_block<512>(mode, alloc);
-    case 1024: return pick_block<1024>(mode, alloc);
-    default: return pick_block<256>(mode, alloc);
+    case 64: return pick_block<64>(mode, alloc, stats);
+    case 128: return pick_block<128>(mode, alloc, stats);
+    case 512: return pick_block<512>(mode, alloc, stats);
+    case 1024: return pick_block<1024>(mode, alloc, stats);
+    default: return pick_block<256>(mode, alloc, stats);
     }
 }
 
@@ -748,10 +753,8 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
         return fail(WC_EINVAL, "drivers 2 and 3 are comparison variants of grid mode only");
     if (cfg.buffer_alloc != 0 && mode != WC_WAVE && mode != WC_BLOCK)
         return fail(WC_EINVAL, "buffer_alloc applies to the wave and block modes only");
-    if (cfg.block != block || cfg.buffer_alloc != 0) {
-        ks = pick(mode, cfg.block, cfg.buffer_alloc != 0);
-        resident = resident_blocks(ctx, ks.round, cfg.block);
-    }
+    ks = pick(mode, cfg.block, cfg.buffer_alloc != 0, stats != nullptr);
+    resident = resident_blocks(ctx, ks.round, cfg.block);
     const long long n = g->n, m = g->m;
     const int chunk = kWave * cfg.items_per_lane;
     // Grid buffer: every frontier vertex (at most n per round) yields at most
