@@ -34,3 +34,33 @@ def test_table_roundtrip_and_per_instance_lookup():
     assert modes == ["wave", "grid", "grid"]
     assert [t.threshold for t in tunes] == [8, 32, 0]  # bucket 2 absent: the heuristic default
     assert {t.block_threads for t in tunes} == {512}
+
+
+class _G:
+    def __init__(self, n):
+        self.n = n
+
+
+def test_coordinate_search_finds_the_best_separable_table(monkeypatch):
+    """With a batch time that is a sum of per-instance costs, the search by
+    buckets (then workgroup shapes) lands on the cheapest configuration of every
+    bucket, and never reports a table slower than the default."""
+    best = {0: ("block", 4, 0), 1: ("grid", 16, 2), 3: ("wave", 8, 0)}
+
+    def cost(n, tune, mode):
+        b = autotune.bucket_of(n)
+        want = best.get(b, ("grid", 0, 0))
+        c = 1.0 if (mode, tune.threshold, tune.items_per_lane) == want else 2.0
+        return c + (0.0 if tune.block_threads in (0, 512) else 0.5)
+
+    def fake_time(ctx, graphs, weights, sources, modes, tunes, reps):
+        return sum(cost(g.n, t, m) for g, t, m in zip(graphs, tunes, modes))
+
+    monkeypatch.setattr(autotune, "_time_batch", fake_time)
+    graphs = [_G(n) for n in (1500, 2000, 5000, 9000, 70000, 200000)]
+    table = autotune.tune(None, graphs, [None] * len(graphs), [0] * len(graphs), reps=1)
+    for b, (mode, thr, ipl) in best.items():
+        assert table["buckets"][str(b)] == {"mode": mode, "threshold": thr, "items_per_lane": ipl}
+    assert "2" not in table["buckets"]  # no instance in that bucket: nothing searched
+    assert table["block_threads"] == 0
+    assert table["timings_ms"]["whole_batch_tuned"] == 6.0 < table["timings_ms"]["heuristic"]
