@@ -65,6 +65,7 @@ def parse():
     p.add_argument("--calibrate-copy-mb", type=int, default=0,
                    help="first run a plain device-to-device copy of this many MiB three times (a known-size "
                         "kernel for scaling hardware byte counters)")
+    p.add_argument("--jsonl", default=None, help="also append the result line to this JSONL file")
     return p.parse_args()
 
 
@@ -1205,9 +1206,14 @@ def main():
         "batch": batch,
         "serving": serving,
         "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
     }
     ctx.close()
-    print(json.dumps(out), flush=True)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.jsonl:
+        with open(args.jsonl, "a") as f:
+            f.write(line + "\n")
 
 
 if __name__ == "__main__":
