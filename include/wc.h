@@ -97,7 +97,10 @@ typedef struct {
  * "use the library's heuristic"; pass NULL for all defaults. */
 typedef struct {
     int32_t threshold;      /* items with more than this much work are buffered (the
-                               THRESHOLD of Fig. 1(b)); <= 0: per-problem default */
+                               THRESHOLD of Fig. 1(b)); <= 0: the default of
+                               wc_default_tune (8 for SSSP and SpMV and at grid
+                               level except coloring; 0 for the trees; 64 for
+                               coloring at grid level; 32 otherwise) */
     int32_t block_threads;  /* workgroup size: 64, 128, 256, 512 or 1024; <= 0: the
                                default of wc_default_tune (512 at grid level except
                                coloring, 256 otherwise) */
@@ -109,7 +112,8 @@ typedef struct {
                                (BFS, trees) about 64 * items_per_lane (wave) or
                                block_threads * items_per_lane (block) children;
                                at most 64; <= 0: the default of wc_default_tune
-                               (4; grid level 2, 8 for SpMV; 32 in the queue
+                               (4; grid level 2, 8 for SpMV; wave and block
+                               levels 2 for SSSP and SpMV, 32 in the queue
                                modes) */
     int32_t driver;         /* 0: one launch per round/level (host relaunch);
                                1: reserved for a persistent co-resident launch: not
@@ -339,7 +343,7 @@ wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *graphs, const 
  * with the defaults); a call whose workspace could exceed the array returns
  * WC_EINVAL before anything is enqueued, as do bad arguments and
  * tune->driver != 0.  Flat mode uses no workspace; wave and block modes only
- * for the rows they hand on to the grid (about 0.22 m bytes with the defaults).
+ * for the rows they hand on to the grid (about 0.44 m bytes with the defaults).
  * Runs on the calling thread's current device (hipSetDevice); `stream` must
  * belong to it.  The call only enqueues; the caller synchronizes.  Every call
  * on one device shares its array: calls whose stream work overlaps on one

@@ -140,8 +140,12 @@ static int default_threshold(const char *problem, wc_mode mode)
     if (mode == WC_FLAT) return INT_MAX;
     if (!strcmp(problem, "tree")) return 0;  // every node with children is a recursive call (Fig. 1(c))
     // grid level drains with lane groups sized to each item, so only very short
-    // items stay inline; wave and block levels drain with whole groups
+    // items stay inline; so do the wave- and block-level children of SSSP and
+    // SpMV (SpMV's rows go to lane groups; SSSP's edges are walked flattened).
+    // Scale-22 graph, items_per_lane 2, threshold 8 / 16 / 32: SSSP wave 2.27 /
+    // 2.36 / 2.46 ms, block 2.48 / 2.53 / 2.61 ms; SpMV wave 0.93 / 0.92 / 0.95 ms
     if (mode == WC_GRID && strcmp(problem, "color")) return 8;
+    if (!strcmp(problem, "sssp") || !strcmp(problem, "spmv")) return 8;
     // coloring at grid level buffers every readied vertex's range; the
     // threshold applies to its count pass, where lanes walk up to 64 entries
     if (mode == WC_GRID) return 64;
@@ -378,6 +382,14 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     out->grid_blocks = resident_blocks > 0 ? resident_blocks : 1;
     out->items_per_lane = 4;  // "const" of Sec. IV.E
     if (mode == WC_GRID && !strcmp(problem, "spmv")) out->items_per_lane = 8;
+    // SSSP and SpMV in wave and block modes: items longer than one chunk of
+    // 64 * items_per_lane go to the grid-wide drain, which balances them over
+    // the whole device; a group's own child keeps the rest.  Chunks of 128
+    // measured fastest (scale-22 graph, threshold 8, items_per_lane 1 / 2 / 4 /
+    // 8: SSSP wave 2.26 / 2.27 / 3.13 / 4.51 ms; SpMV wave 1.01 / 0.93 / 1.37 /
+    // 2.18 ms; block within 10% of wave)
+    if ((mode == WC_WAVE || mode == WC_BLOCK) && (!strcmp(problem, "sssp") || !strcmp(problem, "spmv")))
+        out->items_per_lane = 2;
     // SSSP grid chunks of 128 edges: 1.7% faster than 256 on the scale-22 graph
     // (4 x 20 calls each; the drain waves take two chunks per step); BFS's
     // frontier rounds at grid level are the same kernels

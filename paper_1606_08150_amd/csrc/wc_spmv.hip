@@ -3,11 +3,14 @@
 // One parent work item per row.  Prework reads the row's range; a row with
 // more than `threshold` nonzeros is inserted into the consolidation buffer of
 // its mode, a lighter row is summed inline by its lane ("work").
-//   wave  - ballot-mask buffer; the wave sums each buffered row, lane l taking
-//           elements l, l+64, ..., then a fixed butterfly reduction.
-//   block - thread-ordered LDS buffer, then the workgroup barrier; the buffered
-//           rows are shared out to the block's waves, one wave per row.
-//   In both, a buffered row too long for one group's child (more than one
+//   wave  - ballot-mask buffer; the wave sums its buffered rows.
+//   block - LDS buffer, then the workgroup barrier; the block's waves sum the
+//           buffered rows.
+//   In both, the child sizes its lanes per row as grid mode does (below): g =
+//   the power of two >= len / items_per_lane lanes per row, lane l of a group
+//   taking elements l, l+g, ..., then a fixed butterfly over the group; the
+//   rows of one g go 64 / g to a wave step.  A buffered row too long for one
+//   group's child (more than one
 //   chunk, 64 * items_per_lane nonzeros) is handed on as chunks to a global
 //   buffer that the grid-mode drain spreads over the whole grid after the
 //   parent (the KC_X rule of Sec. IV.E gives a warp's or block's child many
@@ -144,10 +147,12 @@ __device__ __forceinline__ int bin_of(int len, int ipl)
 
 template <int BLOCK>
 struct SpmvBlockBuf {
-    int row[BLOCK];
+    int row[BLOCK];  // buffered rows, laid out by bin
     int beg[BLOCK];
     int end[BLOCK];
-    int scan_tmp[2 * (BLOCK / kWave)];
+    int cnt[kBins + 1];   // rows per bin; [kBins]: heavy rows (work counters)
+    int off[kBins];       // first row of each bin
+    int task[kBins + 1];  // first task of each bin; [kBins]: task count
 };
 
 __device__ __forceinline__ void count_stats(StatAcc &acc, int len, bool heavy, bool wave_dispatch)
@@ -220,32 +225,72 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent(SpmvArgs a)
         }
         const bool mine = heavy && !spill;
 
+        // the child: the scope's buffered rows grouped by bin, g = 2^b lanes
+        // per row (the smallest group that covers the row at items_per_lane
+        // nonzeros a lane), 64 / g rows a wave step
+        const int bin = mine ? bin_of(len, a.ipl) : -1;
         if constexpr (MODE == WC_WAVE) {
-            uint64_t mask = __ballot(mine);
-            while (mask) {
-                int b = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                float s = dot_wave(a, readlane(beg, b), readlane(end, b));
-                if (lane == 0) a.y[base + (threadIdx.x & ~(kWave - 1)) + b] = s;
+            const int wbase = base + (threadIdx.x & ~(kWave - 1));
+            for (int b = 0; b < kBins; ++b) {
+                const uint64_t m = __ballot(bin == b);
+                if (!m) continue;
+                // lane k learns which lane holds the bin's k-th row: the
+                // members go to slots 0..cnt-1, the others after them, so the
+                // permutation writes every lane once
+                const int cnt = __popcll(m);
+                const int to = bin == b ? rank_in(m) : cnt + rank_in(~m);
+                const int src = __builtin_amdgcn_ds_permute(to << 2, lane);
+                const int g = 1 << b, sub = lane & (g - 1);
+                for (int i0 = 0; i0 < cnt; i0 += kWave >> b) {
+                    const int i = i0 + (lane >> b);
+                    const int from = __shfl(src, i < cnt ? i : 0, kWave);
+                    const int rb = __shfl(beg, from, kWave), re = __shfl(end, from, kWave);
+                    float s = dot_strided(a, i < cnt ? rb + sub : 0, g, i < cnt ? re : 0);
+                    s = group_sum(s, g);
+                    if (i < cnt && sub == 0) a.y[wbase + from] = s;
+                }
             }
         } else if constexpr (MODE == WC_BLOCK) {
             __shared__ SpmvBlockBuf<BLOCK> sb;
             constexpr int NW = BLOCK / kWave;
-            int k, dummy, nb, nh;
-            block_scan2<BLOCK>(mine ? 1 : 0, heavy ? 1 : 0, sb.scan_tmp, k, dummy, nb, nh);
-            if (mine) {
-                sb.row[k] = r;
-                sb.beg[k] = beg;
-                sb.end[k] = end;
+            // per-bin insert positions: a row's sum depends only on its own
+            // range and g, not on where it sits, so LDS atomics may order a bin
+            if (threadIdx.x <= kBins) sb.cnt[threadIdx.x] = 0;
+            __syncthreads();
+            const int k = bin >= 0 ? atomicAdd(&sb.cnt[bin], 1) : 0;
+            if (a.want_stats && heavy) atomicAdd(&sb.cnt[kBins], 1);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int o = 0, t = 0;
+                for (int b = 0; b < kBins; ++b) {
+                    sb.off[b] = o;
+                    sb.task[b] = t;
+                    o += sb.cnt[b];
+                    t += (sb.cnt[b] + (kWave >> b) - 1) / (kWave >> b);
+                }
+                sb.task[kBins] = t;
+                if (a.want_stats && sb.cnt[kBins]) acc.dispatches += 1;
             }
-            if (threadIdx.x == 0 && a.want_stats && nh) acc.dispatches += 1;
+            __syncthreads();
+            if (bin >= 0) {
+                const int q = sb.off[bin] + k;
+                sb.row[q] = r;
+                sb.beg[q] = beg;
+                sb.end[q] = end;
+            }
             __syncthreads();  // the "synchronize" between inserts and the child
-            // one wave per row, rows dealt round-robin to the waves
-            const int wid = threadIdx.x / kWave;
-            for (int it = wid; it < nb; it += NW) {
-                const int rb = sb.beg[it], re = sb.end[it];
-                float s = dot_wave(a, rb, re);
-                if (lane == 0) a.y[sb.row[it]] = s;
+            // tasks of 64 / g rows of one bin, dealt round-robin to the waves
+            const int total = sb.task[kBins];
+            for (int t = threadIdx.x / kWave; t < total; t += NW) {
+                int b = 0;
+                while (b + 1 < kBins && sb.task[b + 1] <= t) ++b;
+                const int g = 1 << b, sub = lane & (g - 1);
+                const int i = (t - sb.task[b]) * (kWave >> b) + (lane >> b);
+                const bool ok = i < sb.cnt[b];
+                const int q = sb.off[b] + (ok ? i : 0);
+                float s = dot_strided(a, ok ? sb.beg[q] + sub : 0, g, ok ? sb.end[q] : 0);
+                s = group_sum(s, g);
+                if (ok && sub == 0) a.y[sb.row[q]] = s;
             }
             __syncthreads();  // LDS buffer is reused by the next window
         }

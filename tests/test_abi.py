@@ -39,8 +39,12 @@ def test_host_helpers_match_oracle():
 def test_default_tune_and_errors():
     t = wc.default_tune("sssp", "grid", 2048)
     assert t["grid_blocks"] == 2048 and t["items_per_lane"] == 2 and t["block_threads"] == 512
-    assert wc.default_tune("sssp", "block", 2048)["items_per_lane"] == 4
-    assert wc.default_tune("sssp", "block", 2048)["block_threads"] == 256
+    # SSSP and SpMV wave and block levels: short items inline, chunks of 128
+    for problem in ("sssp", "spmv"):
+        for mode in ("wave", "block"):
+            t = wc.default_tune(problem, mode, 2048)
+            assert (t["threshold"], t["items_per_lane"], t["block_threads"]) == (8, 2, 256)
+    assert wc.default_tune("bfs", "wave", 1)["threshold"] == 32
     assert wc.default_tune("spmv", "grid", 1)["items_per_lane"] == 8
     # BFS: grid rounds share SSSP's chunk, the recursion queue packs coarser
     assert wc.default_tune("bfs", "grid", 1)["items_per_lane"] == 2

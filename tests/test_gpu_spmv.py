@@ -150,14 +150,14 @@ def test_long_rows_handed_to_the_grid(ctx, c1, mode):
     lens = np.diff(g.row_ptr)
     for tune in (dict(), dict(items_per_lane=1), dict(items_per_lane=1, block_threads=64),
                  dict(items_per_lane=2, threshold=2)):
-        ipl, bt = tune.get("items_per_lane", 4), tune.get("block_threads", 256)
+        ipl, bt = tune.get("items_per_lane", 2), tune.get("block_threads", 256)
         spill = 64 * ipl
         assert (lens > spill).any()
         y1, st = run(ctx, g, val, x, mode, stats=True, **tune)
         y2 = run(ctx, g, val, x, mode, **tune)
         assert oracle.spmv_check(y_ref, b, y1) == (0, -1), tune
         assert np.array_equal(y1.view(np.uint32), y2.view(np.uint32)), tune
-        assert st["items_buffered"] == oracle.count_heavy(lens, tune.get("threshold", 32))
+        assert st["items_buffered"] == oracle.count_heavy(lens, tune.get("threshold", 8))
         assert st["overflowed"] == 0
     y, st = run(ctx, g, val, x, mode, stats=True, items_per_lane=1, buf_capacity=5)
     assert st["overflowed"] == 1 and oracle.spmv_check(y_ref, b, y) == (0, -1)

@@ -112,7 +112,7 @@ def test_long_items_handed_to_the_grid(ctx, c1, mode):
     dg, dw = upload(g, w)
     deg = np.diff(g.row_ptr)
     for tune in (dict(), dict(items_per_lane=1), dict(items_per_lane=1, block_threads=64), dict(threshold=2)):
-        ipl, bt = tune.get("items_per_lane", 4), tune.get("block_threads", 256)
+        ipl, bt = tune.get("items_per_lane", 2), tune.get("block_threads", 256)
         spill = 64 * ipl
         assert (deg > spill).any()
         d, st = ctx.sssp(dg, dw, 0, mode=mode, tune=wc.make_tune(**tune), stats=True)

@@ -106,15 +106,23 @@ def test_spmv_bound_is_worst_case_on_the_scale22_graph(rmat22, mode):
 
 
 def test_row_depth_examples():
-    # the hub's 159,772 nonzeros: flat one lane; wave and block 625 chunks of 256
-    # (4 per lane + butterfly), partials 10 per lane + butterfly; grid 313 chunks
-    # of 512 (8 per lane + butterfly), partials 5 per lane + butterfly
+    # the hub's 159,772 nonzeros: flat one lane; wave and block (defaults) 1,249
+    # chunks of 128 (2 per lane + butterfly), partials 20 per lane + butterfly;
+    # with items_per_lane 4, 625 chunks of 256 and partials 10 per lane; grid 313
+    # chunks of 512 (8 per lane + butterfly), partials 5 per lane + butterfly
     assert row_depth(159_772, "flat") == cascade_depth(159_772)
-    assert row_depth(159_772, "wave") == cascade_depth(4) + 6 + cascade_depth(10) + 6
-    assert row_depth(159_772, "block") == cascade_depth(4) + 6 + cascade_depth(10) + 6
-    # rows a wave or a block keeps: up to one chunk (64 * 4)
-    assert row_depth(256, "wave") == cascade_depth(4) + 6 == row_depth(256, "block")
-    assert row_depth(257, "wave") == cascade_depth(4) + 6 + cascade_depth(1) + 6
+    assert row_depth(159_772, "wave") == cascade_depth(2) + 6 + cascade_depth(20) + 6
+    assert row_depth(159_772, "block") == cascade_depth(2) + 6 + cascade_depth(20) + 6
+    assert row_depth(159_772, "wave", items_per_lane=4) == cascade_depth(4) + 6 + cascade_depth(10) + 6
+    # rows a wave or a block keeps: above the threshold (8) and up to one chunk
+    # (64 * 2), by the group of g lanes that covers the row at 2 nonzeros a lane
+    # (40 nonzeros: 32 lanes); with items_per_lane 4, 16 lanes
+    assert row_depth(8, "wave") == cascade_depth(8)
+    assert row_depth(128, "wave") == cascade_depth(2) + 6 == row_depth(128, "block")
+    assert row_depth(40, "wave") == cascade_depth(2) + 5 == row_depth(40, "block")
+    assert row_depth(40, "wave", items_per_lane=4) == cascade_depth(3) + 4
+    assert row_depth(256, "wave", items_per_lane=4, threshold=32) == cascade_depth(4) + 6
+    assert row_depth(129, "wave") == cascade_depth(2) + 6 + cascade_depth(1) + 6
     assert row_depth(159_772, "grid") == cascade_depth(8) + 6 + cascade_depth(5) + 6
     assert row_depth(8, "grid") == cascade_depth(8) and row_depth(9, "grid") == cascade_depth(5) + 1
     assert row_depth(0, "wave") == 0
@@ -163,9 +171,10 @@ def test_pagerank_first_sweep_at_the_hub(rmat22):
             lanes = (lanes + lanes[np.arange(64) ^ dist]).astype(F)
         return lanes[0]
 
-    # wave order for a row this long: chunks of 64 * 4 terms, each a wave sum,
-    # then a wave sum of the chunk partials in chunk order
-    partials = np.array([wave_sum(contrib[c:c + 256]) for c in range(0, contrib.size, 256)], F)
+    # wave order for a row this long: chunks of 64 * 2 terms (the default
+    # items_per_lane), each a wave sum, then a wave sum of the chunk partials in
+    # chunk order
+    partials = np.array([wave_sum(contrib[c:c + 128]) for c in range(0, contrib.size, 128)], F)
     wave = wave_sum(partials)
 
     assert rel(serial) > 1e-4  # the bound 1e-4 did not hold for the plain running sum

@@ -18,9 +18,9 @@ through, following the order the kernels use:
     lanes; still longer rows in chunks of 64 * ipl nonzeros (a cascade per lane
     plus a 64-lane butterfly), whose partials are summed lane-strided by one
     wave (a cascade plus a butterfly);
-  * wave and block modes: rows above the threshold lane-strided over one
-    wave's 64 lanes, up to 64 * ipl nonzeros (one chunk); longer rows in chunks
-    as in grid mode;
+  * wave and block modes: rows above the threshold and up to 64 * ipl
+    nonzeros (one chunk) by lane groups sized as in grid mode; longer rows in
+    chunks as in grid mode;
   * flat mode: the row's lane alone.
 """
 import math
@@ -32,8 +32,8 @@ SPMV_RTOL = 1e-5  # the required per-row bound: |y - y_ref| <= 1e-5 * sum |a_ij 
 
 DEFAULTS = {  # the library's default tune per mode (wc_default_tune)
     "flat": dict(threshold=None, block_threads=256, items_per_lane=4),
-    "wave": dict(threshold=32, block_threads=256, items_per_lane=4),
-    "block": dict(threshold=32, block_threads=256, items_per_lane=4),
+    "wave": dict(threshold=8, block_threads=256, items_per_lane=2),
+    "block": dict(threshold=8, block_threads=256, items_per_lane=2),
     "grid": dict(threshold=8, block_threads=512, items_per_lane=8),
 }
 
@@ -73,12 +73,8 @@ def row_depth(length: int, mode: str, **tune) -> int:
         return cascade_depth(length)
     chunks = math.ceil(length / (64 * ipl))
     chunked = cascade_depth(ipl) + 6 + cascade_depth(math.ceil(chunks / 64)) + 6
-    if mode in ("wave", "block"):
-        spill = 64 * ipl
-        if length <= spill:
-            return cascade_depth(math.ceil(length / 64)) + 6
-        return chunked
-    # grid
+    # wave, block and grid: a row up to one chunk is summed by the g-lane group
+    # that covers it at ipl nonzeros a lane
     if length <= 64 * ipl:
         g = 1 << max(0, math.ceil(math.log2(math.ceil(length / ipl))))
         return cascade_depth(math.ceil(length / g)) + int(math.log2(g))
