@@ -63,6 +63,20 @@ def test_tune_sweep_and_repeats(ctx, c1_pr, mode, tune):
         assert np.array_equal(again.view(np.uint32), first.view(np.uint32))
 
 
+def test_same_order_in_every_consolidated_mode(ctx, c1_pr):
+    """The in-edge sums follow one order per (threshold, items_per_lane) in
+    wave, block and grid modes (as for SpMV) and the per-sweep kernels do not
+    depend on the mode, so ten sweeps give bitwise the same ranks in the three
+    modes, within the bound of each."""
+    g, dg, od, t, refs = c1_pr
+    for tune in (dict(threshold=8, items_per_lane=2), dict(threshold=2, items_per_lane=8)):
+        tt = wc.make_tune(**tune)
+        ranks = {m: ctx.pagerank(dg, od, 10, mode=m, tune=tt).cpu().numpy() for m in ("wave", "block", "grid")}
+        for m, r in ranks.items():
+            assert oracle.pagerank_check(refs[10], r, bound(t, 10, m, **tune)) == (0, -1), (m, tune)
+            assert np.array_equal(r.view(np.uint32), ranks["grid"].view(np.uint32)), (m, tune)
+
+
 def special_graphs():
     yield "single", synth.graph_from_edges(1, [])[0]
     yield "no_edges", synth.graph_from_edges(50, [])[0]

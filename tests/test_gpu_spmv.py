@@ -53,6 +53,30 @@ def test_tune_sweep_and_determinism(ctx, c1, mode, tune):
     assert np.array_equal(y1.view(np.uint32), y2.view(np.uint32))
 
 
+@pytest.mark.parametrize("tune", [dict(threshold=8, items_per_lane=2), dict(threshold=1, items_per_lane=1),
+                                  dict(threshold=32, items_per_lane=4), dict(threshold=3, items_per_lane=16)])
+def test_same_order_in_every_consolidated_mode(ctx, c1, tune):
+    """For a given threshold and items_per_lane, wave, block and grid modes sum
+    each row in one order: rows up to the threshold by their own lane, rows up
+    to one chunk (64 * items_per_lane) by the group of g = 2^ceil(log2(len /
+    items_per_lane)) lanes, longer rows in chunks whose partials are combined in
+    chunk order.  The workgroup size only moves rows between workgroups, so y
+    is bitwise the same in the three modes at every block_threads, and flat
+    mode (every row by its own lane) agrees on the rows up to the threshold."""
+    g, val, x, y_ref, b = c1
+    lens = np.diff(g.row_ptr)
+    y0 = run(ctx, g, val, x, "grid", **tune)
+    assert oracle.spmv_check(y_ref, b, y0) == (0, -1)
+    for mode in ("wave", "block", "grid"):
+        for bt in (64, 256, 1024):
+            y = run(ctx, g, val, x, mode, block_threads=bt, **tune)
+            assert np.array_equal(y.view(np.uint32), y0.view(np.uint32)), (mode, bt)
+    light = lens <= tune["threshold"]
+    assert light.any() and (~light).any()
+    yf = run(ctx, g, val, x, "flat")
+    assert np.array_equal(yf[light].view(np.uint32), y0[light].view(np.uint32))
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_edge_cases(ctx, mode):
     rng = np.random.default_rng(8)
