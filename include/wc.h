@@ -98,9 +98,10 @@ typedef struct {
 typedef struct {
     int32_t threshold;      /* items with more than this much work are buffered (the
                                THRESHOLD of Fig. 1(b)); <= 0: the default of
-                               wc_default_tune (8 for SSSP and SpMV and at grid
-                               level except coloring; 0 for the trees; 64 for
-                               coloring at grid level; 32 otherwise) */
+                               wc_default_tune (8 for SSSP and SpMV, at grid
+                               level except coloring and for coloring at block
+                               level; 0 for the trees; 64 for coloring at grid
+                               level; 32 otherwise) */
     int32_t block_threads;  /* workgroup size: 64, 128, 256, 512 or 1024; <= 0: the
                                default of wc_default_tune (512 at grid level except
                                coloring, 256 otherwise) */
@@ -113,8 +114,8 @@ typedef struct {
                                block_threads * items_per_lane (block) children;
                                at most 64; <= 0: the default of wc_default_tune
                                (4; grid level 2, 8 for SpMV; wave and block
-                               levels 2 for SSSP and SpMV, 32 in the queue
-                               modes) */
+                               levels 2 for SSSP and SpMV, 1 for coloring, 32
+                               in the queue modes) */
     int32_t driver;         /* 0: one launch per round/level (host relaunch);
                                1: reserved for a persistent co-resident launch: not
                                   available, every entry point refuses it with
@@ -260,7 +261,9 @@ wc_status wc_pagerank(wc_ctx *ctx, const wc_csr *in_graph, const int32_t *out_de
  * largest color of an outranking neighbour.  Computed data-driven: a vertex
  * colored in round r releases the neighbours it outranks, and one whose last
  * outranking neighbour that was is colored r + 1; the release loop of a vertex
- * with more than `threshold` neighbours is consolidated per `mode`.  color[n]
+ * with more than `threshold` neighbours is consolidated per `mode` (wave and
+ * block modes hand ranges longer than 64 * items_per_lane on to a grid-wide
+ * drain after each pass, as the other irregular loops do).  color[n]
  * (int32, device) is written entirely; prio[n] (uint32, device) is read only.
  * The colors do not depend on mode, tune or schedule.  stats->rounds = number
  * of colors.  Only the relaunch driver exists (tune->driver 0).  WC_EINVAL for

@@ -146,6 +146,10 @@ static int default_threshold(const char *problem, wc_mode mode)
     // 2.36 / 2.46 ms, block 2.48 / 2.53 / 2.61 ms; SpMV wave 0.93 / 0.92 / 0.95 ms
     if (mode == WC_GRID && strcmp(problem, "color")) return 8;
     if (!strcmp(problem, "sssp") || !strcmp(problem, "spmv")) return 8;
+    // coloring at block level: the block's child walks the concatenated
+    // ranges, so short ranges gain from it (symmetric R-MAT scale 16 / 22,
+    // chunks of 64: 12.4 / 96.6 ms at threshold 8, 16.1 / 106 ms at 32)
+    if (!strcmp(problem, "color") && mode == WC_BLOCK) return 8;
     // coloring at grid level buffers every readied vertex's range; the
     // threshold applies to its count pass, where lanes walk up to 64 entries
     if (mode == WC_GRID) return 64;
@@ -398,6 +402,11 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     // atomics: 128-neighbour chunks in 256-thread groups measured fastest
     // (symmetric R-MAT graphs of scale 16 and 22)
     if (mode == WC_GRID && !strcmp(problem, "color")) out->items_per_lane = 2;
+    // coloring in wave and block modes: ranges longer than one chunk go to the
+    // grid-wide drain of the pass or round; chunks of 64 measured fastest
+    // (symmetric R-MAT scale 16 / 22, wave at threshold 32: 20.5 / 114 ms at
+    // 64, 30.3 / 154 ms at 256)
+    if ((mode == WC_WAVE || mode == WC_BLOCK) && !strcmp(problem, "color")) out->items_per_lane = 1;
     // tree items are child ranges: most nodes have a few children, and shorter
     // chunks split the few wide nodes over more waves (measured on 2^22 nodes)
     if (mode == WC_GRID && !strcmp(problem, "tree")) out->items_per_lane = 2;

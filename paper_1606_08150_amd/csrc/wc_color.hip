@@ -18,15 +18,20 @@
 //           vertex's neighbours 64 x kUnroll at a time (no barrier).
 //   block - thread-ordered LDS buffer; after the barrier the block walks the
 //           concatenated neighbour ranges.
+//   In both, a buffered vertex with more than one chunk (64 * items_per_lane)
+//   of neighbours is handed on as chunks to a global buffer that a grid-wide
+//   drain walks right after the parent, one wave per chunk (the KC_X rule of
+//   Sec. IV.E: a warp's or block's child gets many blocks), in the count pass
+//   and in every round.
 //   grid  - global buffer of (vertex, neighbour range) chunks drained by a
 //           moldable grid after the kernel boundary, one wave per chunk.  The
 //           thread that readies a vertex buffers its range right away, so the
 //           drain of round r is also the parent of round r + 1: one kernel
 //           per round.
 //   flat  - every vertex walks all of its neighbours itself.
-// Outside grid mode every vertex is buffered (walked) regardless of the
-// threshold in the count pass and the rounds alike; in grid mode `threshold`
-// applies to the count pass, and every readied vertex's range is buffered.
+// Outside grid mode `threshold` applies in the count pass and the rounds
+// alike; in grid mode it applies to the count pass, and every readied
+// vertex's range is buffered.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -129,6 +134,34 @@ __device__ __forceinline__ void push_ready(const ColorArgs &a, bool ready, int w
     }
 }
 
+// Wave and block modes: the lanes with nch > 0 hand their vertex's range on
+// as chunks (v, begin, end, tag) of the global buffer, one reservation per
+// wave on `tail`; the wave writes each vertex's chunks together.  Returns
+// false on a lane whose chunks do not all fit (buffer full): its reserved
+// entries are marked empty and the lane walks the range itself (fallback).
+// Every lane of the wave calls this.
+__device__ __forceinline__ bool spill_chunks(const ColorArgs &a, int *tail, int v, int beg, int end, int nch, int tag)
+{
+    const int slot = wave_reserve_n(nch, tail);
+    const bool fits = nch > 0 && (long long)slot + nch <= a.chunk_cap;
+    uint64_t m = __ballot(fits);
+    while (m) {
+        const int b = __builtin_ctzll(m);
+        m &= m - 1;
+        const int s0 = readlane(slot, b), n0 = readlane(nch, b), rb = readlane(beg, b), re = readlane(end, b);
+        const int rv = readlane(v, b), rt = readlane(tag, b);
+        for (int c = lane_id(); c < n0; c += kWave) {
+            const int cb = rb + c * a.chunk;
+            a.chunks[s0 + c] = make_int4(rv, cb, min(re, cb + a.chunk), rt);
+        }
+    }
+    if (nch > 0 && !fits) {
+        for (long long c = slot; c < (long long)slot + nch && c < a.chunk_cap; ++c) a.chunks[c] = make_int4(v, 0, 0, 0);
+        a.stats->overflowed = 1;
+    }
+    return nch == 0 || fits;
+}
+
 // A vertex colored in round r releases the neighbours e = first + k * stride
 // < end of its row that it outranks (the count pass flagged the others in
 // rcol); a neighbour whose count reaches zero is readied with color r + 1.
@@ -210,6 +243,7 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
     const int size = a.qtail[(r % 3) * kPad];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.qtail[((r + 2) % 3) * kPad] = 0;
+        a.chunk_tail[((r + 2) % 3) * kPad] = 0;
         publish_host(a.host_ring, r % kHostRing, a.stats, size);
     }
     if (size == 0) return;
@@ -235,12 +269,21 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
             acc.items += heavy ? 1 : 0;
             if (MODE == WC_WAVE && __ballot(heavy) && lane == 0) acc.dispatches += 1;
         }
-        if (member && !heavy) acc.updates += release_range<false>(a, beg, 1, end, r + 1, nx, readied);
+        // buffered vertices with more than one chunk go to the round's drain
+        bool spill = heavy && deg > a.chunk, inline_walk = member && !heavy;
+        if (__ballot(spill)) {
+            const int v = spill ? q[i] : 0;
+            if (!spill_chunks(a, &a.chunk_tail[(r % 3) * kPad], v, beg, end, spill ? (deg + a.chunk - 1) / a.chunk : 0,
+                              0))
+                inline_walk = true;
+        }
+        const bool mine = heavy && !spill;
+        if (inline_walk) acc.updates += release_range<false>(a, beg, 1, end, r + 1, nx, readied);
         if constexpr (MODE == WC_WAVE) {
             // the ballot mask is the wave's buffer; the wave walks each buffered
             // vertex's range 64 x kUnroll neighbours at a time (walking the
             // concatenated ranges measured 12% slower here)
-            uint64_t mask = __ballot(heavy);
+            uint64_t mask = __ballot(mine);
             while (mask) {
                 const int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
@@ -249,19 +292,38 @@ __global__ __launch_bounds__(BLOCK) void color_round(ColorArgs a, int r)
             }
         } else if constexpr (MODE == WC_BLOCK) {
             int k, off, nb, total;
-            block_scan2<BLOCK>(heavy ? 1 : 0, heavy ? deg : 0, sb.scan_tmp, k, off, nb, total);
-            if (heavy) {
+            block_scan2<BLOCK>(mine ? 1 : 0, mine ? deg : 0, sb.scan_tmp, k, off, nb, total);
+            if (mine) {
                 sb.beg[k] = beg;
                 sb.pre[k] = off;
             }
-            if (threadIdx.x == 0) {
-                sb.pre[nb] = total;
-                if (a.want_stats && nb) acc.dispatches += 1;
-            }
+            if (a.want_stats && __syncthreads_or(heavy ? 1 : 0) && threadIdx.x == 0) acc.dispatches += 1;
+            if (threadIdx.x == 0) sb.pre[nb] = total;
             __syncthreads();
             acc.updates_buffered += release_items<BLOCK>(a, sb.beg, sb.pre, nb, total, threadIdx.x, r + 1, nx, readied);
             __syncthreads();  // the LDS buffer is reused by the next window
         }
+    }
+    if (a.want_stats) stat_flush(a.stats, acc);
+}
+
+// Wave and block modes: the chunks that round r's parent handed on, one wave
+// per chunk, right after the parent; readied vertices join round r + 1's queue.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void color_round_drain(ColorArgs a, int r)
+{
+    const int tail = a.chunk_tail[(r % 3) * kPad];
+    const int total = (long long)tail < a.chunk_cap ? tail : (int)a.chunk_cap;
+    if (total == 0) return;
+    const Next nx{(r & 1) ? a.queue0 : a.queue1, &a.qtail[((r + 1) % 3) * kPad], nullptr, nullptr};
+    const int gw = (blockIdx.x * BLOCK + threadIdx.x) / kWave;
+    const int nw = gridDim.x * (BLOCK / kWave);
+    int readied = 0;
+    StatAcc acc;
+    for (int c = gw; c < total; c += nw) {
+        const int4 d = a.chunks[c];
+        const int beg = __builtin_amdgcn_readfirstlane(d.y), end = __builtin_amdgcn_readfirstlane(d.z);
+        acc.updates_buffered += release_range<false>(a, beg + lane_id(), kWave, end, r + 1, nx, readied);
     }
     if (a.want_stats) stat_flush(a.stats, acc);
 }
@@ -369,8 +431,9 @@ struct CountLds {
 };
 
 // Count pass, the first irregular loop: wait[v] = neighbours that outrank v.
-// A row with more than `threshold` entries is consolidated per mode (grid:
-// its chunks are counted by color_count_drain, which adds to wait[v] = 0).
+// A row with more than `threshold` entries is consolidated per mode (grid,
+// and wave and block rows longer than one chunk: its chunks are counted by
+// color_count_drain, which adds to wait[v] = 0).
 template <int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void color_count(ColorArgs a)
 {
@@ -388,10 +451,20 @@ __global__ __launch_bounds__(BLOCK) void color_count(ColorArgs a)
         }
         const int deg = end - beg;
         const bool heavy = MODE != WC_FLAT && deg > a.threshold;
+        // wave and block modes: rows with more than one chunk go to the drain
+        const bool spill = (MODE == WC_WAVE || MODE == WC_BLOCK) && heavy && deg > a.chunk;
+        bool inline_count = member && !heavy;
+        if constexpr (MODE == WC_WAVE || MODE == WC_BLOCK) {
+            if (__ballot(spill) &&
+                !spill_chunks(a, &a.chunk_tail[2 * kPad], v, beg, end, spill ? (deg + a.chunk - 1) / a.chunk : 0,
+                              (int)pv))
+                inline_count = true;
+        }
+        const bool mine = heavy && !spill;
         int cnt = 0;
-        if (member && !heavy) cnt = count_range(a, v, pv, beg, 1, end);
+        if (inline_count) cnt = count_range(a, v, pv, beg, 1, end);
         if constexpr (MODE == WC_WAVE) {
-            uint64_t mask = __ballot(heavy);
+            uint64_t mask = __ballot(mine);
             while (mask) {
                 const int b = __builtin_ctzll(mask);
                 mask &= mask - 1;
@@ -401,8 +474,8 @@ __global__ __launch_bounds__(BLOCK) void color_count(ColorArgs a)
             }
         } else if constexpr (MODE == WC_BLOCK) {
             int k, off, nb, total;
-            block_scan2<BLOCK>(heavy ? 1 : 0, heavy ? deg : 0, sb.scan_tmp, k, off, nb, total);
-            if (heavy) {
+            block_scan2<BLOCK>(mine ? 1 : 0, mine ? deg : 0, sb.scan_tmp, k, off, nb, total);
+            if (mine) {
                 sb.v[k] = v;
                 sb.beg[k] = beg;
                 sb.p[k] = pv;
@@ -418,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void color_count(ColorArgs a)
                 if (count_edge(a, sb.v[it], sb.p[it], a.col[e], e)) atomicAdd(&sb.cnt[it], 1);
             }
             __syncthreads();
-            if (heavy) cnt = sb.cnt[k];
+            if (mine) cnt = sb.cnt[k];
             __syncthreads();  // the LDS buffer is reused by the next window
         } else if constexpr (MODE == WC_GRID) {
             if (__syncthreads_or(heavy ? 1 : 0)) {
@@ -449,7 +522,8 @@ __global__ __launch_bounds__(BLOCK) void color_count(ColorArgs a)
     }
 }
 
-// Grid mode: one wave per chunk of a long row adds its count to wait[v].
+// One wave per chunk of a buffered row (grid mode; wave and block modes: rows
+// longer than one chunk) adds its count to wait[v].
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void color_count_drain(ColorArgs a)
 {
@@ -521,13 +595,14 @@ __global__ __launch_bounds__(kSeedBlock) void color_seed(ColorArgs a)
 }
 
 struct ColorKernels {
-    const void *round, *count, *count_drain;
+    const void *round, *count, *count_drain, *round_drain;
 };
 
 template <int BLOCK>
 ColorKernels pick_block(wc_mode mode)
 {
-    ColorKernels k{nullptr, nullptr, reinterpret_cast<const void *>(&color_count_drain<BLOCK>)};
+    ColorKernels k{nullptr, nullptr, reinterpret_cast<const void *>(&color_count_drain<BLOCK>),
+                   reinterpret_cast<const void *>(&color_round_drain<BLOCK>)};
     switch (mode) {
     case WC_FLAT:
         k.round = reinterpret_cast<const void *>(&color_round<WC_FLAT, BLOCK>);
@@ -591,12 +666,16 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
     const long long n = g->n, m = g->m;
     const int chunk = kWave * cfg.items_per_lane;
     const bool grid_mode = mode == WC_GRID;
-    // every vertex has ceil(deg / chunk) <= deg / chunk + 1 chunks in the one
-    // round that colors it (and in the count pass), so n + m / chunk + 1
-    // entries per buffer never overflow
-    const long long cap_full = n + m / chunk + 1;
-    const long long cap = grid_mode ? (cfg.buf_capacity > 0 ? std::min(cfg.buf_capacity, cap_full) : cap_full) : 1;
-    const size_t need = 3 * padded(n * 4) + padded(m * 4) + 3 * padded(3 * kPad * 4) + 2 * padded(cap * 16);
+    // grid mode: every vertex has ceil(deg / chunk) <= deg / chunk + 1 chunks
+    // in the one round that colors it (and in the count pass), so n + m / chunk
+    // + 1 entries per buffer never overflow.  Wave and block modes buffer only
+    // vertices with more than one chunk of neighbours (ceil(deg / chunk) <
+    // 2 deg / chunk each), in the count pass or one round at a time.
+    const bool spills = mode == WC_WAVE || mode == WC_BLOCK;
+    const long long cap_full = grid_mode ? n + m / chunk + 1 : spills ? 2 * (m / chunk) + 1 : 1;
+    const long long cap = cfg.buf_capacity > 0 && mode != WC_FLAT ? std::min(cfg.buf_capacity, cap_full) : cap_full;
+    const size_t need = 3 * padded(n * 4) + padded(m * 4) + 3 * padded(3 * kPad * 4) +
+                        (grid_mode ? 2 : 1) * padded(cap * 16);
     st = pool_reserve(ctx, need, stream);
     if (st != WC_OK) return st;
     ColorArgs a;
@@ -630,7 +709,7 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
         st = launch(ctx, "color_reset", reinterpret_cast<const void *>(&color_reset), dim3(1), dim3(64), args,
                     stream);
         if (st == WC_OK) st = launch(ctx, "color_count", ks.count, dim3(grid), dim3(cfg.block), args, stream);
-        if (st == WC_OK && grid_mode)
+        if (st == WC_OK && mode != WC_FLAT)
             st = launch(ctx, "color_count_drain", ks.count_drain, dim3(dgrid), dim3(cfg.block), args, stream);
         const int sg = (int)std::min<long long>((n + kSeedBlock - 1) / kSeedBlock, 4096);
         const void *seed = grid_mode ? reinterpret_cast<const void *>(&color_seed<true>)
@@ -650,6 +729,8 @@ extern "C" wc_status wc_color(wc_ctx *ctx, const wc_csr *g, const uint32_t *prio
             clear_round_slot(ctx, launched);
             void *args[] = {&a, &launched};
             st = launch(ctx, names[mode], ks.round, dim3(grid_mode ? dgrid : grid), dim3(cfg.block), args, stream);
+            if (st == WC_OK && spills)
+                st = launch(ctx, "color_round_drain", ks.round_drain, dim3(dgrid), dim3(cfg.block), args, stream);
             if (st != WC_OK) return st;
             ++launched;
         }

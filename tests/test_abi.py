@@ -58,6 +58,10 @@ def test_default_tune_and_errors():
     t = wc.default_tune("color", "grid", 100)
     assert t["threshold"] == 64 and t["block_threads"] == 256 and t["items_per_lane"] == 2
     assert wc.default_tune("color", "wave", 100)["threshold"] == 32
+    # coloring in wave and block modes: chunks of 64, the block child from 8
+    for mode, thr in (("wave", 32), ("block", 8)):
+        t = wc.default_tune("color", mode, 100)
+        assert (t["threshold"], t["items_per_lane"]) == (thr, 1)
     try:
         wc.default_tune("nope", "grid", 1)
     except wc.WcError as e:

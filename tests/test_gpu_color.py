@@ -108,6 +108,29 @@ def test_buffer_overflow(ctx, c1_sym):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("mode", ["wave", "block"])
+def test_long_ranges_handed_to_the_grid(ctx, c1_sym, mode):
+    """Wave and block modes hand every buffered vertex with more than one chunk
+    (64 * items_per_lane) of neighbours on to a grid-wide drain, in the count
+    pass and in every round: exact for several chunk sizes and workgroup
+    sizes, and an undersized buffer falls back to the vertex's own lane
+    (overflow flag; WC_EOVERFLOW when the fallback is refused)."""
+    g, p, dg, dp, (ref, k) = c1_sym
+    deg = np.diff(g.row_ptr)
+    for tune in (dict(), dict(items_per_lane=4), dict(items_per_lane=1, block_threads=64),
+                 dict(items_per_lane=2, threshold=2), dict(items_per_lane=1, block_threads=1024)):
+        assert (deg > 64 * tune.get("items_per_lane", 1)).any()
+        got, st = run(ctx, dg, dp, mode, stats=True, **tune)
+        assert np.array_equal(got, ref), tune
+        assert st["rounds"] == k and st["overflowed"] == 0, tune
+    got, st = run(ctx, dg, dp, mode, stats=True, items_per_lane=1, buf_capacity=3)
+    assert np.array_equal(got, ref) and st["overflowed"] == 1
+    with pytest.raises(wc.WcError) as ei:
+        ctx.color(dg, dp, mode=mode, tune=wc.make_tune(items_per_lane=1, buf_capacity=3, allow_fallback=-1))
+    assert ei.value.status == -3
+    torch.cuda.synchronize()
+
+
 def test_invalid_arguments(ctx, c1_sym):
     g, p, dg, dp, _ = c1_sym
     with pytest.raises(wc.WcError):
