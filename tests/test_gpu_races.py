@@ -3,7 +3,9 @@ on one stream, with no host synchronization between them and each into its own
 output, all compared afterwards: SSSP against the oracle's distances, SpMV
 bitwise against its first result (and that one within the tolerance of the
 binary64 product), recursive BFS against the oracle's levels, and tree
-descendants in the packet-queue modes against the oracle."""
+descendants in the packet-queue modes against the oracle.  Coloring (whose
+calls wait for each round's count, but not for the call's last kernels) runs
+25 calls per mode the same way."""
 import numpy as np
 import pytest
 import torch
@@ -60,3 +62,19 @@ def test_queue_modes_back_to_back(ctx, c1_graph, mode):
     for k in range(REPS):
         assert np.array_equal(dev_to_u32(levels[k]), ref), k
         assert np.array_equal(descs[k].cpu().numpy(), dref), k
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_coloring_back_to_back(ctx, c1_graph, mode):
+    g = synth.symmetrize(c1_graph[0])
+    p = synth.priorities(g.n)
+    ref, _ = oracle.color_jp(g.row_ptr, g.col, p)
+    dg = wc.DeviceCSR.from_host(g.row_ptr, g.col)
+    dp = u32_to_dev(p)
+    say(f"races: {REPS // 4} coloring calls back to back, mode={mode}")
+    outs = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(REPS // 4)]
+    for o in outs:
+        ctx.color(dg, dp, mode=mode, out=o)
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), ref), k
