@@ -797,7 +797,17 @@ wc_status run_sssp(wc_ctx *ctx, const wc_csr *g, const uint32_t *w, int32_t src,
 
     const long long per_window = mode == WC_GRID ? 2LL * cfg.block : cfg.block;
     const int windows = (int)((n + per_window - 1) / per_window);
-    const int grid = std::max(1, std::min(std::min(cfg.grid, resident), windows));
+    // Wave and block modes launch the parent with a thread per vertex (one
+    // window per workgroup, as Fig. 1(b)'s parent) unless grid_blocks caps it:
+    // the hardware hands the windows to CUs as they free up, which evens out
+    // the windows dense with buffered vertices (scale-22 graph: wave 2.28 ->
+    // 2.12 ms, block 2.49 -> 2.19 ms against the resident grid).  The pool
+    // slices of the allocator comparison are per resident workgroup, so those
+    // runs keep the resident grid.
+    const bool own_grid = tune && tune->grid_blocks > 0;
+    int grid = std::max(1, std::min(std::min(cfg.grid, resident), windows));
+    if ((mode == WC_WAVE || mode == WC_BLOCK) && cfg.buffer_alloc == 0)
+        grid = std::max(1, own_grid ? std::min(cfg.grid, windows) : windows);
     const int dgrid = std::max(1, std::min(cfg.grid, resident));
     st = begin_call(ctx, stream, stats);
     if (st != WC_OK) return st;
