@@ -106,7 +106,10 @@ typedef struct {
                                default of wc_default_tune (512 at grid level except
                                coloring, 256 otherwise) */
     int32_t grid_blocks;    /* workgroups of the moldable drain/persistent grid;
-                               <= 0: resident maximum from the occupancy query (KC_1) */
+                               <= 0: resident maximum from the occupancy query (KC_1).
+                               SSSP and SpMV in wave and block modes launch their
+                               parent with one workgroup per block_threads items
+                               unless this caps it */
     int32_t items_per_lane; /* the "const" of the Sec. IV.E buffer-size estimate: work
                                items per drain lane; grid-level chunks hold
                                64 * items_per_lane elements, queue-mode packets
