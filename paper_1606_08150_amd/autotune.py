@@ -8,9 +8,13 @@ batch: `heuristic_config` is the library default, and `tune` searches the
 configurations one size bucket at a time (largest instances first), timing
 every candidate of that bucket on the whole batch as it runs (graph-captured
 rounds) with the other buckets at their best so far, then the workgroup
-shape.  The library default is one of the candidates at every step, so the
-table found is never slower than the default on the batch it was tuned on
-(up to timing noise).  Tables are plain JSON.
+shape.  The search starts from the best of the default and the tables that
+put every bucket at the wave or the block level (the buckets share one
+launch, whose shape depends on the levels present, so a table can pay off
+only when all buckets change together).  The library default is one of the
+candidates at every step, so the table found is never slower than the
+default on the batch it was tuned on (up to timing noise).  Tables are plain
+JSON.
 """
 from __future__ import annotations
 
@@ -109,6 +113,15 @@ def tune(ctx, graphs, weights, sources, reps: int = 2) -> dict:
         return _time_batch(ctx, graphs, weights, sources, modes, tunes, reps)
 
     best_ms = heur_ms = run(table)
+    uniform = {}
+    for mode in ("wave", "block"):
+        start = {"buckets": {str(b): {"mode": mode, "threshold": 0, "items_per_lane": 0} for b in present},
+                 "block_threads": 0}
+        ms = run(start)
+        uniform[mode] = round(ms, 4)
+        if ms < best_ms:
+            best_ms = ms
+            table["buckets"] = dict(start["buckets"])
     for b in present:
         trials = []
         for cfg in candidates():
@@ -126,5 +139,6 @@ def tune(ctx, graphs, weights, sources, reps: int = 2) -> dict:
             best_ms = ms
             table["block_threads"] = block
     table["timings_ms"]["heuristic"] = round(heur_ms, 4)
+    table["timings_ms"]["uniform"] = uniform
     table["timings_ms"]["whole_batch_tuned"] = round(best_ms, 4)
     return table

@@ -64,3 +64,21 @@ def test_coordinate_search_finds_the_best_separable_table(monkeypatch):
     assert "2" not in table["buckets"]  # no instance in that bucket: nothing searched
     assert table["block_threads"] == 0
     assert table["timings_ms"]["whole_batch_tuned"] == 6.0 < table["timings_ms"]["heuristic"]
+
+
+def test_uniform_start_reaches_a_joint_optimum(monkeypatch):
+    """Buckets that only pay off together (block level is cheap when every
+    instance runs at block level, dear otherwise): one bucket at a time from
+    the default cannot leave it, the uniform start can, and the search keeps
+    the joint table."""
+    def fake_time(ctx, graphs, weights, sources, modes, tunes, reps):
+        all_block = all(m == "block" for m in modes)
+        return sum((1.5 if all_block else 2.5) if m == "block" else 2.0 for m in modes)
+
+    monkeypatch.setattr(autotune, "_time_batch", fake_time)
+    graphs = [_G(n) for n in (1500, 5000, 20000, 200000)]
+    table = autotune.tune(None, graphs, [None] * len(graphs), [0] * len(graphs), reps=1)
+    assert {c["mode"] for c in table["buckets"].values()} == {"block"}
+    assert table["timings_ms"]["heuristic"] == 8.0
+    assert table["timings_ms"]["uniform"] == {"wave": 8.0, "block": 6.0}
+    assert table["timings_ms"]["whole_batch_tuned"] == 6.0
