@@ -59,6 +59,8 @@ def parse():
                    help="skip the comparison of the default configuration with exhaustive search")
     p.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
     p.add_argument("--serve-workers", type=int, default=4)
+    p.add_argument("--serve-sssp-mode", default="grid", choices=["flat", "wave", "block", "grid"],
+                   help="consolidation level of the serving section's batched SSSP requests")
     p.add_argument("--counter-run", default=None, choices=["flat", "wave", "block", "grid"],
                    help="only run SSSP, SpMV and tree descendants in this mode, 3 calls each (for rocprofv3 "
                         "counter passes per mode), then exit")
@@ -730,7 +732,7 @@ def run_serving(args, torch, synth, wc):
         return reached_cache[key]
 
     rows = []
-    backend = serve.GpuBackend(dev)
+    backend = serve.GpuBackend(dev, sssp_mode=args.serve_sssp_mode)
     srv = serve.Server(backend, workers=args.serve_workers, max_slots=512, max_batch=64)
     try:
         warm = serve.poisson_requests(200, 5000.0, srcs, n_x=4, seed=1)
@@ -749,7 +751,8 @@ def run_serving(args, torch, synth, wc):
         ctx.close()
     return {"workload": "Poisson arrivals, 50% SSSP (random source with out-edges) / 50% SpMV (4 resident x "
                         "per graph), 64 resident R-MAT graphs of 2^14..2^20 vertices, degree 16",
-            "workers": args.serve_workers, "graphs_vertices": sum(sizes), "requests_per_rate": args.serve_requests,
+            "workers": args.serve_workers, "sssp_mode": args.serve_sssp_mode, "graphs_vertices": sum(sizes),
+            "requests_per_rate": args.serve_requests,
             "admission": "outputs by exact tensor bytes; batch workspace from the library's plan-only mode "
                          "against each worker's pool; pool growth charged to the budget (half the free memory "
                          "measured after the workers' contexts exist)",
