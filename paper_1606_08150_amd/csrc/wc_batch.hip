@@ -184,6 +184,10 @@ __global__ __launch_bounds__(BLOCK) void batch_round(BatchArgs a, int r)
                 // own relaxations read it): nothing to do
                 if (a.relaxed_at[g] == du) end = beg;
                 mode = end - beg > d.threshold ? d.mode : WC_FLAT;
+                // a wave's or block's own child keeps items of up to one chunk;
+                // longer ones go to the grid-wide drain (the KC_X rule of
+                // Sec. IV.E: a warp's or block's child gets many blocks)
+                if ((mode == WC_WAVE || mode == WC_BLOCK) && end - beg > d.chunk) mode = WC_GRID;
                 // wave, block and inline work use this reading; grid chunks raise
                 // the value from 0 in the drain (or it stays du on overflow)
                 if (end > beg && mode != WC_GRID) a.relaxed_at[g] = du;
@@ -448,6 +452,12 @@ extern "C" wc_status wc_sssp_batch(wc_ctx *ctx, int32_t count, const wc_csr *gra
         vbase[i] = (int)total;
         total += g.n;
         if (mode == WC_GRID) cap += g.n + g.m / chunk + 1;
+        // wave and block levels hand vertices with more than one chunk of edges
+        // (at most 2 deg / chunk chunks each) to the grid path
+        if (mode == WC_WAVE || mode == WC_BLOCK) {
+            has[WC_GRID] = 1;
+            cap += 2 * (g.m / chunk) + 1;
+        }
         if (total > 0x7fffffffLL) return fail(WC_EINVAL, "wc_sssp_batch: more than 2^31 vertices in one batch");
     }
     vbase[count] = (int)total;
