@@ -454,6 +454,18 @@ __global__ __launch_bounds__(BLOCK) void spmv_parent_grid(SpmvArgs a)
     if (STATS) stat_flush(a.stats, acc);
 }
 
+// Grid mode with the buffers of an earlier product on the same matrix still in
+// place (PageRank's later sweeps): only the rows up to the threshold, summed
+// inline as spmv_parent_grid sums them; the binned rows and chunks are reused.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void spmv_light_rows(SpmvArgs a)
+{
+    for (int r = blockIdx.x * BLOCK + threadIdx.x; r < a.n; r += gridDim.x * BLOCK) {
+        const int beg = a.row_ptr[r], end = a.row_ptr[r + 1];
+        if (end - beg <= a.threshold) a.y[r] = dot_strided_u<2 * kUnroll>(a, beg, 1, end);
+    }
+}
+
 // Consolidated child of grid mode.  Wave tasks: for bin b (g = 2^b lanes per
 // row) a task is 64 / g consecutive rows of the bin; then one task per chunk.
 // Hot x values staged in LDS by the drain of the hot-column layout: 32 per
@@ -591,7 +603,7 @@ __global__ __launch_bounds__(256) void spmv_gather_hot(SpmvArgs a)
 }
 
 struct SpmvKernels {
-    const void *parent, *classify, *parent_grid, *drain, *combine;
+    const void *parent, *classify, *parent_grid, *drain, *combine, *light;
 };
 
 template <int BLOCK>
@@ -602,7 +614,8 @@ SpmvKernels pick_block(wc_mode mode, bool hot, bool stats)
                         : reinterpret_cast<const void *>(&spmv_parent_grid<BLOCK, false>),
                   hot ? reinterpret_cast<const void *>(&spmv_drain<BLOCK, true>)
                       : reinterpret_cast<const void *>(&spmv_drain<BLOCK, false>),
-                  reinterpret_cast<const void *>(&spmv_combine<BLOCK>)};
+                  reinterpret_cast<const void *>(&spmv_combine<BLOCK>),
+                  reinterpret_cast<const void *>(&spmv_light_rows<BLOCK>)};
     switch (mode) {
     case WC_FLAT: k.parent = reinterpret_cast<const void *>(&spmv_parent<WC_FLAT, BLOCK>); break;
     case WC_WAVE: k.parent = reinterpret_cast<const void *>(&spmv_parent<WC_WAVE, BLOCK>); break;
@@ -773,6 +786,20 @@ wc_status spmv_launch(wc_ctx *ctx, SpmvPlan *p, hipStream_t stream)
     return st;
 }
 
+// Grid mode, again on the same matrix with the buffers of the last spmv_launch
+// of this plan still in place (full-size buffers, so nothing overflowed): the
+// rows up to the threshold inline, then the drain and the combination of the
+// reused binned rows and chunks.  Same sums, in the same order, as spmv_launch.
+wc_status spmv_relaunch(wc_ctx *ctx, SpmvPlan *p, hipStream_t stream)
+{
+    const Config &cfg = p->cfg;
+    void *args[] = {&p->a};
+    wc_status st = launch(ctx, "spmv_light_rows", p->ks.light, dim3(p->grid), dim3(cfg.block), args, stream);
+    if (st == WC_OK) st = launch(ctx, "spmv_drain", p->ks.drain, dim3(p->dgrid), dim3(cfg.block), args, stream);
+    if (st == WC_OK) st = launch(ctx, "spmv_combine", p->ks.combine, dim3(p->dgrid), dim3(cfg.block), args, stream);
+    return st;
+}
+
 // ---------------------------------------------------------------- PageRank
 
 struct PrArgs {
@@ -927,10 +954,15 @@ extern "C" wc_status wc_pagerank(wc_ctx *ctx, const wc_csr *in_graph, const int3
     if (st != WC_OK) return st;
     void *args[] = {&q};
     st = launch(ctx, "pr_init", reinterpret_cast<const void *>(&pr_init), dim3(pgrid), dim3(kPrBlock), args, stream);
+    // grid mode: the in-edge structure is the same every sweep, so the binned
+    // rows and chunks of the first sweep serve the later ones (only when the
+    // buffers are full size, so that nothing overflowed, and without work
+    // counters, which count each sweep's binning)
+    const bool reuse = mode == WC_GRID && !stats && !(tune && tune->buf_capacity > 0);
     for (int it = 0; it < iterations && st == WC_OK; ++it) {
         st = launch(ctx, "pr_contrib", reinterpret_cast<const void *>(&pr_contrib), dim3(pgrid), dim3(kPrBlock), args,
                     stream);
-        if (st == WC_OK) st = spmv_launch(ctx, &p, stream);
+        if (st == WC_OK) st = reuse && it > 0 ? spmv_relaunch(ctx, &p, stream) : spmv_launch(ctx, &p, stream);
         if (st == WC_OK)
             st = launch(ctx, "pr_update", reinterpret_cast<const void *>(&pr_update), dim3(pgrid), dim3(kPrBlock),
                         args, stream);

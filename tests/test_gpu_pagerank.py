@@ -77,6 +77,25 @@ def test_same_order_in_every_consolidated_mode(ctx, c1_pr):
             assert np.array_equal(r.view(np.uint32), ranks["grid"].view(np.uint32)), (m, tune)
 
 
+def test_grid_sweeps_reuse_the_first_binning(ctx, c1_pr):
+    """Grid mode bins the in-edge rows in the first sweep and reuses the binned
+    rows and chunks in the later ones (full-size buffers, no work counters):
+    the ranks are bitwise those of the path that bins every sweep (a buffer
+    capacity given, or work counters on), for several tunes and sweep counts."""
+    g, dg, od, t, refs = c1_pr
+    for tune in (dict(), dict(threshold=1, items_per_lane=1), dict(block_threads=1024, items_per_lane=2)):
+        for k in (1, 2, 10):
+            reuse = ctx.pagerank(dg, od, k, mode="grid", tune=wc.make_tune(**tune) if tune else None)
+            rebin = ctx.pagerank(dg, od, k, mode="grid", tune=wc.make_tune(buf_capacity=1 << 40, **tune))
+            counted, _ = ctx.pagerank(dg, od, k, mode="grid", tune=wc.make_tune(**tune) if tune else None, stats=True)
+            torch.cuda.synchronize()
+            r0 = reuse.cpu().numpy()
+            assert oracle.pagerank_check(refs[10] if k == 10 else reference(g, t, k), r0,
+                                         bound(t, k, "grid", **tune)) == (0, -1), (tune, k)
+            for other in (rebin, counted):
+                assert np.array_equal(other.cpu().numpy().view(np.uint32), r0.view(np.uint32)), (tune, k)
+
+
 def special_graphs():
     yield "single", synth.graph_from_edges(1, [])[0]
     yield "no_edges", synth.graph_from_edges(50, [])[0]
