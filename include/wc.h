@@ -389,13 +389,18 @@ wc_status wc_ctx_set_plan_only(wc_ctx *ctx, int enable);
  * was last switched. */
 wc_status wc_ctx_planned_bytes(wc_ctx *ctx, size_t *bytes);
 
-/* Current pool size in bytes and the number of times the pool has grown
- * (a call that needs more than the pool drains the device and regrows it). */
+/* Current pool size in bytes and the number of times the pool has grown (a
+ * call that needs more than the pool replaces it by one of at least twice the
+ * size without waiting: calls still in flight keep the old pool, which stays
+ * allocated, with the context's captured graphs, until the context next drains
+ * the device: wc_ctx_set_timing or wc_ctx_destroy). */
 wc_status wc_ctx_pool_info(wc_ctx *ctx, size_t *pool_bytes, int64_t *grows);
 
-/* Grows the pool to at least `bytes` now (waits for the device first; captured
- * graphs of the context are dropped), so that later calls up to that size
- * never grow it while other work runs.  No-op when the pool is large enough. */
+/* Grows the pool to at least `bytes` now, so that later calls up to that size
+ * never grow it.  Does not wait for the device: the replaced pool and the
+ * context's captured graphs are retired as a growth inside a call retires them
+ * (see wc_ctx_pool_info), so until the context next drains the device both
+ * pools count against device memory.  No-op when the pool is large enough. */
 wc_status wc_ctx_reserve(wc_ctx *ctx, size_t bytes);
 
 /* Aggregate of the recorded launches of the index-th distinct kernel name (in

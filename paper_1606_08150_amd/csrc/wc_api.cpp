@@ -34,20 +34,41 @@ wc_status hip_fail(hipError_t e, const char *what)
     return WC_EHIP;
 }
 
+// A growth replaces the pool and drops the captured graphs (they hold pool
+// addresses) without waiting: calls in flight on any stream keep the old ones,
+// which are retired and released at the next drain of the device by the
+// context (no device-wide synchronization that would stall other contexts'
+// streams; the cost is the retired memory until then).
+static void retire_graphs(wc_ctx *ctx)
+{
+    if (ctx->graph_exec) ctx->retired_graphs.push_back(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+    ctx->graph_key = 0;
+    for (auto &tg : ctx->tree_graphs) {
+        if (tg.exec) ctx->retired_graphs.push_back(tg.exec);
+        tg = wc_ctx::TreeGraph{};
+    }
+}
+
+// After the device has been drained: frees what growths retired.
+static void release_retired(wc_ctx *ctx)
+{
+    for (char *p : ctx->retired_pools) (void)hipFree(p);
+    ctx->retired_pools.clear();
+    for (hipGraphExec_t g : ctx->retired_graphs) (void)hipGraphExecDestroy(g);
+    ctx->retired_graphs.clear();
+}
+
 static wc_status pool_alloc(wc_ctx *ctx, size_t bytes)
 {
-    if (ctx->pool) {
-        hipError_t e = hipFree(ctx->pool);
-        ctx->pool = nullptr;
-        ctx->pool_bytes = 0;
-        if (e != hipSuccess) return hip_fail(e, "hipFree(pool)");
-    }
-    hipError_t e = hipMalloc(&ctx->pool, bytes);
+    char *fresh = nullptr;
+    hipError_t e = hipMalloc(&fresh, bytes);
     if (e != hipSuccess) {
-        ctx->pool = nullptr;
         (void)hipGetLastError();
         return fail(WC_ENOMEM, "cannot allocate a device pool of " + std::to_string(bytes) + " bytes");
     }
+    if (ctx->pool) ctx->retired_pools.push_back(ctx->pool);
+    ctx->pool = fresh;
     ctx->pool_bytes = bytes;
     return WC_OK;
 }
@@ -58,22 +79,13 @@ wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream)
         ctx->planned = std::max(ctx->planned, bytes);
         return WC_PLANNED;
     }
+    (void)stream;
     ctx->pool_off = 0;
     if (bytes <= ctx->pool_bytes) return WC_OK;
     ++ctx->pool_grows;
-    // earlier calls may still be using the pool: drain before replacing it
-    WC_HIP(hipStreamSynchronize(stream));
-    WC_HIP(hipDeviceSynchronize());
-    size_t grow = ctx->pool_bytes * 2;
-    if (ctx->graph_exec) {
-        (void)hipGraphExecDestroy(ctx->graph_exec);
-        ctx->graph_exec = nullptr;
-        ctx->graph_key = 0;
-    }
-    for (auto &tg : ctx->tree_graphs) {
-        if (tg.exec) (void)hipGraphExecDestroy(tg.exec);
-        tg = wc_ctx::TreeGraph{};
-    }
+    // earlier calls may still be using the pool: it is retired, not freed
+    const size_t grow = ctx->pool_bytes * 2;
+    retire_graphs(ctx);
     return pool_alloc(ctx, bytes > grow ? bytes : grow);
 }
 
@@ -480,6 +492,7 @@ wc_status wc_ctx_set_timing(wc_ctx *ctx, int enable)
     WC_HIP(hipSetDevice(ctx->device));
     WC_HIP(hipDeviceSynchronize());
     recycle_records(ctx);
+    release_retired(ctx);
     ctx->timing = enable ? 1 : 0;
     return WC_OK;
 }
@@ -512,17 +525,8 @@ wc_status wc_ctx_reserve(wc_ctx *ctx, size_t bytes)
     if (!ctx) return fail(WC_EINVAL, "NULL context");
     if (bytes <= ctx->pool_bytes) return WC_OK;
     WC_HIP(hipSetDevice(ctx->device));
-    WC_HIP(hipDeviceSynchronize());
     ++ctx->pool_grows;
-    if (ctx->graph_exec) {
-        (void)hipGraphExecDestroy(ctx->graph_exec);
-        ctx->graph_exec = nullptr;
-        ctx->graph_key = 0;
-    }
-    for (auto &tg : ctx->tree_graphs) {
-        if (tg.exec) (void)hipGraphExecDestroy(tg.exec);
-        tg = wc_ctx::TreeGraph{};
-    }
+    retire_graphs(ctx);
     return pool_alloc(ctx, bytes);
 }
 
@@ -586,6 +590,7 @@ wc_status wc_ctx_destroy(wc_ctx *ctx)
     for (auto e : ctx->spare_events) (void)hipEventDestroy(e);
     ctx->spare_events.clear();
     if (ctx->pool) (void)hipFree(ctx->pool);
+    release_retired(ctx);
     if (ctx->host_ring) (void)hipHostFree(ctx->host_ring);
     if (ctx->dstats) (void)hipFree(ctx->dstats);
     if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);

@@ -73,6 +73,11 @@ struct wc_ctx {
     int plan_only = 0;
     size_t planned = 0;
     long long pool_grows = 0;
+    // pools and captured graphs replaced by a growth: calls still in flight on
+    // any stream may use them, so they are released only where the context
+    // drains the device anyway (wc_ctx_set_timing, wc_ctx_destroy)
+    std::vector<char *> retired_pools;
+    std::vector<hipGraphExec_t> retired_graphs;
     unsigned long long wait_ticks = 0;  // bound of every device-side wait, in 100 MHz ticks
     wc::DevStats *dstats = nullptr;  // device
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -116,7 +121,8 @@ wc_status hip_fail(hipError_t e, const char *what);
     } while (0)
 
 // Pool carving: reset at the start of each call, then take aligned slices.
-// Grows the pool (after draining the device) if a call needs more than it has.
+// Grows the pool if a call needs more than it has (the old pool is retired,
+// not freed: work in flight may still use it).
 // In plan-only mode it records `bytes` and returns WC_PLANNED instead, which
 // every caller passes straight up (nothing has been enqueued at that point).
 wc_status pool_reserve(wc_ctx *ctx, size_t bytes, hipStream_t stream);

@@ -16,8 +16,10 @@ to completion; a batch also needs its worker's consolidation workspace (the
 context pool), which the backend computes with the library's plan-only mode (the
 bytes the calls would carve, nothing enqueued).  A batch whose workspace exceeds
 its worker's pool is cut down; a single request that still needs a larger pool
-is dispatched only when the growth fits the remaining budget (pools never
-shrink, so growth is charged for good), otherwise it waits for memory to free.
+is dispatched only when the growth fits the remaining budget, otherwise it waits
+for memory to free.  A growth is charged its whole new pool, for good: the
+library keeps the replaced pool (calls in flight may still use it) for as long
+as the worker's context lives, and pools never shrink.
 The budget is measured after the workers' contexts (and their pools) exist.
 
 Only the scheduling lives here; every request's arithmetic runs in libwc.  The
@@ -88,7 +90,8 @@ class Admission:
         assert self.used >= 0 and self.slots >= 0
 
     def try_grow(self, nbytes: int) -> bool:
-        """Charges a pool growth for good (pools never shrink), if it fits."""
+        """Charges a pool growth for good (pools are never released while the
+        context lives), if it fits."""
         if self.used + nbytes > self.budget:
             return False
         self.used += nbytes
@@ -319,7 +322,7 @@ class Server:
             need = int(self.backend.workspace(batch))
         if need <= self.pool[wi]:
             return 0
-        if not self.admission.try_grow(need - self.pool[wi]):
+        if not self.admission.try_grow(need):  # the replaced pool stays allocated
             ready.appendleft(batch.pop())
             return -1
         self.pool[wi] = need
@@ -344,7 +347,8 @@ class Server:
             else:
                 g = self.backend.graphs[r.graph]
                 r.nbytes = request_bytes(r.kind, g.n, g.m)
-            growth = max(0, self._single_workspace(r) - largest_pool)
+            ws = self._single_workspace(r)
+            growth = ws if ws > largest_pool else 0  # a growth holds the whole new pool
             if not self.admission.fits_ever(r.nbytes + growth):
                 raise ValueError(f"request {r.rid} needs {r.nbytes + growth} bytes, more than the whole budget")
         self._t0 = time.perf_counter()

@@ -84,3 +84,46 @@ def test_reserve_grows_once(data):
         assert c.pool_info() == (3 << 20, 1)
     finally:
         c.close()
+
+
+def test_growth_while_calls_are_in_flight_on_other_streams():
+    """A growth does not wait for the device: calls still in flight keep the
+    replaced pool, which the context retires and releases when it next drains
+    the device.  One context with a 64 KiB pool; products and SSSP calls on
+    graphs of increasing size issued alternately on two side streams, each
+    stream ordered after the other's work (calls sharing a context must be
+    serialized) but with no host synchronization, so a call can grow the pool
+    while the one before still runs; every result matches the oracle."""
+    import oracle
+    from gpu_util import dev_to_u32, f32_to_dev, u32_to_dev
+    cases = []
+    for k, scale in enumerate((9, 11, 13, 15)):
+        g = synth.rmat_csr(scale, 16 << scale, seed=700 + k)
+        w = synth.weights(g.m, seed=710 + k)
+        val, x = synth.values(g.m, seed=720 + k), synth.vector_x(g.n, seed=730 + k)
+        y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, x)
+        d_ref = oracle.sssp_dijkstra(g.row_ptr, g.col, w, 0)
+        dg = wc.DeviceCSR.from_host(g.row_ptr, g.col)
+        cases.append(dict(dg=dg, dw=u32_to_dev(w), dv=f32_to_dev(val), dx=f32_to_dev(x),
+                          y=torch.full((g.n,), -5.0, dtype=torch.float32, device="cuda"),
+                          d=torch.full((g.n,), -5, dtype=torch.int32, device="cuda"), y_ref=y_ref, b=b, d_ref=d_ref))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    c = wc.Context(0, pool_bytes=1 << 16)
+    try:
+        say("growth: 4 products and 4 SSSP calls of growing size on two streams, no sync between them")
+        cur = 0
+        for k, cs in enumerate(cases):
+            for call in (lambda s: c.spmv(cs["dg"], cs["dv"], cs["dx"], mode="grid", out=cs["y"], stream=s),
+                         lambda s: c.sssp(cs["dg"], cs["dw"], 0, mode="wave", out=cs["d"], stream=s)):
+                nxt = 1 - cur
+                streams[nxt].wait_stream(streams[cur])  # serialized on the device, not on the host
+                call(streams[nxt])
+                cur = nxt
+        torch.cuda.synchronize()
+        for k, cs in enumerate(cases):
+            assert oracle.spmv_check(cs["y_ref"], cs["b"], cs["y"].cpu().numpy()) == (0, -1), k
+            assert np.array_equal(dev_to_u32(cs["d"]), cs["d_ref"]), k
+        assert c.pool_info()[1] >= 3
+    finally:
+        c.close()

@@ -184,9 +184,10 @@ def test_tree_requests_are_admitted_by_their_own_size():
 def test_a_request_that_would_grow_a_pool_waits_for_memory():
     """Budget 800 bytes; one worker whose pool holds 100.  r0 (output 300,
     workspace 50) runs first; r1 (output 100) needs a 700-byte workspace, so
-    its worker must grow by 600: with r0's output still held that would be
-    300 + 100 + 600 > 800, so r1 stays queued until r0 is done, then the growth
-    is charged for good and r1 runs."""
+    its worker must grow to 700, charged whole (the replaced pool stays
+    allocated): with r0's output still held that would be 300 + 100 + 700 >
+    800, so r1 stays queued until r0 is done, then the growth is charged for
+    good and r1 runs."""
     gs = [FakeGraph(75, 10), FakeGraph(25, 10)]
     reqs = [serve.Request(0, serve.SPMV, 0, 0, 0.0), serve.Request(1, serve.SPMV, 1, 0, 0.0)]
     be = FakeBackend(gs, run_s=0.05, pool0=100, ws_of=lambda r: 50 if r.graph == 0 else 700)
@@ -200,8 +201,8 @@ def test_a_request_that_would_grow_a_pool_waits_for_memory():
     assert be.batches == [[0], [1]]          # cut to what the pool holds, then r1 alone
     assert r1.t_start >= r0.t_done            # queued, not over-admitted
     assert be.grown == [700] and srv.grows == 1
-    assert srv.admission.peak_used <= 800 and srv.admission.pool_growth == 600
-    assert srv.admission.used == 600          # the growth stays charged; outputs are released
+    assert srv.admission.peak_used <= 800 and srv.admission.pool_growth == 700
+    assert srv.admission.used == 700          # the growth stays charged; outputs are released
 
 
 def test_a_growth_that_can_never_fit_is_refused_up_front():
@@ -218,7 +219,7 @@ def test_a_growth_that_can_never_fit_is_refused_up_front():
 
 def test_admitted_requests_give_memory_back_when_a_growth_could_never_run():
     """Budget 1000, one worker with a 100-byte pool.  r0 needs a 700-byte
-    workspace (growth 600); r1..r3 (output 200 each) arrive with it and are
+    workspace (a growth charged 700); r1..r3 (output 200 each) arrive with it and are
     admitted too, leaving no room for the growth while nothing runs.  The
     later requests give their outputs back and wait, r0 grows the pool and
     runs, then the others run in the grown pool."""
