@@ -104,7 +104,9 @@ typedef struct {
                                level; 32 otherwise) */
     int32_t block_threads;  /* workgroup size: 64, 128, 256, 512 or 1024; <= 0: the
                                default of wc_default_tune (512 at grid level except
-                               coloring, 256 otherwise) */
+                               coloring; the packet queues: 1024 for BFS and the
+                               trees at wave level, 512 for BFS at block level;
+                               256 otherwise) */
     int32_t grid_blocks;    /* workgroups of the moldable drain/persistent grid;
                                <= 0: resident maximum from the occupancy query (KC_1).
                                SSSP and SpMV in wave and block modes launch their

@@ -392,6 +392,16 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     // grid level: 512-thread workgroups measured fastest (scale-22 graph,
     // 2^22-node tree) except for coloring; everything else 256
     out->block_threads = mode == WC_GRID && strcmp(problem, "color") ? 512 : 256;
+    // the packet queues of recursive BFS and the trees (one persistent grid):
+    // larger workgroups measured faster, except for the trees at block level
+    // (scale-22 graph, BFS at 256 / 512 / 1024 threads: wave 9.02 / 8.97 /
+    // 8.50 ms, block 3.86 / 2.72 / 2.99 ms; 2^22-node random tree, descendants
+    // at wave level 3.01 / 2.92 / 2.65 ms, the 39.3M-node layered tree 2.55 /
+    // 2.39 / 2.15 ms; at block level 512 threads helped the descendants and
+    // slowed the heights)
+    if (!strcmp(problem, "bfs") && mode == WC_WAVE) out->block_threads = 1024;
+    if (!strcmp(problem, "bfs") && mode == WC_BLOCK) out->block_threads = 512;
+    if (!strcmp(problem, "tree") && mode == WC_WAVE) out->block_threads = 1024;
     // The drain grid of every mode is the resident maximum (KC_1 of Sec. IV.E):
     // wave- and block-level drains run inside the parent groups, which are
     // already resident, so no downgrade for concurrency is needed.

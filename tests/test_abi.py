@@ -45,6 +45,11 @@ def test_default_tune_and_errors():
             t = wc.default_tune(problem, mode, 2048)
             assert (t["threshold"], t["items_per_lane"], t["block_threads"]) == (8, 2, 256)
     assert wc.default_tune("bfs", "wave", 1)["threshold"] == 32
+    # the packet queues: larger workgroups
+    assert wc.default_tune("bfs", "wave", 1)["block_threads"] == 1024
+    assert wc.default_tune("bfs", "block", 1)["block_threads"] == 512
+    assert wc.default_tune("tree", "wave", 1)["block_threads"] == 1024
+    assert wc.default_tune("tree", "block", 1)["block_threads"] == 256
     assert wc.default_tune("spmv", "grid", 1)["items_per_lane"] == 8
     # BFS: grid rounds share SSSP's chunk, the recursion queue packs coarser
     assert wc.default_tune("bfs", "grid", 1)["items_per_lane"] == 2
