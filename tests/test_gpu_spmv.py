@@ -77,6 +77,34 @@ def test_same_order_in_every_consolidated_mode(ctx, c1, tune):
     assert np.array_equal(yf[light].view(np.uint32), y0[light].view(np.uint32))
 
 
+@pytest.mark.parametrize("tune", [dict(threshold=8, items_per_lane=2), dict(threshold=1, items_per_lane=1),
+                                  dict(threshold=32, items_per_lane=4)])
+def test_row_lengths_at_every_boundary(ctx, tune):
+    """Rows whose lengths sit on every boundary of the per-row order (the
+    threshold, each lane-group size g * items_per_lane, the chunk of
+    64 * items_per_lane and one past it), 40 rows of each length in shuffled
+    order so that every window mixes them: within the bound in every mode and
+    bitwise the same in wave, block and grid modes."""
+    rng = np.random.default_rng(91)
+    thr, ipl = tune["threshold"], tune["items_per_lane"]
+    lens = {0, 1, thr, thr + 1, 64 * ipl - 1, 64 * ipl, 64 * ipl + 1, 2 * 64 * ipl + 1, 1000}
+    for g in (1, 2, 4, 8, 16, 32, 64):
+        lens |= {g * ipl, g * ipl + 1}
+    row_lens = rng.permutation(np.repeat(sorted(x for x in lens if x >= 0), 40))
+    n = len(row_lens)
+    edges = [(r, int(c)) for r, ln in enumerate(row_lens) for c in rng.integers(0, n, ln)]
+    g, _ = synth.graph_from_edges(n, edges)
+    assert np.array_equal(np.diff(g.row_ptr), row_lens)
+    val, x = synth.values(g.m, seed=92), synth.vector_x(n, seed=93)
+    y_ref, b = oracle.spmv_f64(g.row_ptr, g.col, val, x)
+    ys = {}
+    for mode in MODES:
+        ys[mode] = run(ctx, g, val, x, mode, **tune)
+        assert oracle.spmv_check(y_ref, b, ys[mode]) == (0, -1), mode
+    for mode in ("wave", "block"):
+        assert np.array_equal(ys[mode].view(np.uint32), ys["grid"].view(np.uint32)), mode
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_edge_cases(ctx, mode):
     rng = np.random.default_rng(8)
