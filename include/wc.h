@@ -105,8 +105,8 @@ typedef struct {
     int32_t block_threads;  /* workgroup size: 64, 128, 256, 512 or 1024; <= 0: the
                                default of wc_default_tune (512 at grid level except
                                coloring; the packet queues: 1024 for BFS and the
-                               trees at wave level, 512 for BFS at block level;
-                               256 otherwise) */
+                               trees at wave level, 512 for BFS and the trees'
+                               descendants at block level; 256 otherwise) */
     int32_t grid_blocks;    /* workgroups of the moldable drain/persistent grid;
                                <= 0: resident maximum from the occupancy query (KC_1).
                                SSSP and SpMV in wave and block modes launch their
@@ -432,8 +432,9 @@ int64_t wc_per_buffer_size(int64_t total_thread, int64_t total_buff_var, int64_t
 void wc_kc_config(int64_t blocks, int64_t threads, int64_t x, int64_t *out_blocks, int64_t *out_threads);
 
 /* Fill `out` with the library's defaults for a problem ("sssp", "bfs", "spmv", "tree", "color")
- * and mode, given the occupancy-derived resident workgroup count.  Returns
- * WC_EINVAL for an unknown problem or mode. */
+ * and mode, given the occupancy-derived resident workgroup count ("tree" gives
+ * the heights' workgroup size; the descendants at block level use 512).
+ * Returns WC_EINVAL for an unknown problem or mode. */
 wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_blocks, wc_tune *out);
 
 #ifdef __cplusplus
