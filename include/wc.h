@@ -120,7 +120,7 @@ typedef struct {
                                at most 64; <= 0: the default of wc_default_tune
                                (4; grid level 2, 8 for SpMV; wave and block
                                levels 2 for SSSP and SpMV, 1 for coloring, 32
-                               in the queue modes) */
+                               in the queue modes, 64 for BFS at wave level) */
     int32_t driver;         /* 0: one launch per round/level (host relaunch);
                                1: reserved for a persistent co-resident launch: not
                                   available, every entry point refuses it with

@@ -437,6 +437,9 @@ wc_status wc_default_tune(const char *problem, wc_mode mode, int32_t resident_bl
     // times coarser (scale-22 graph, wave / block: 13.8 / 5.7 ms at 8, 10.4 /
     // 4.4 ms at 16, 8.9 / 3.8 ms at 32, 9.1 / 4.0 ms at 64)
     if ((mode == WC_WAVE || mode == WC_BLOCK) && !strcmp(problem, "bfs")) out->items_per_lane = 32;
+    // with 1024-thread groups at wave level, packets twice as coarse again
+    // (8.46 -> 8.13 ms; at block level 64 measured slower, 2.97 against 2.71 ms)
+    if (mode == WC_WAVE && !strcmp(problem, "bfs")) out->items_per_lane = 64;
     // the trees' packet queue: packets of 64 x 32 (wave) or block x 32 (block)
     // children; against 4, the 2^22-node random tree's heights took 2.4 instead
     // of 2.9 ms (block) and the wide layered trees 0.24 / 2.5 instead of 0.49 /

@@ -53,7 +53,7 @@ def test_default_tune_and_errors():
     assert wc.default_tune("spmv", "grid", 1)["items_per_lane"] == 8
     # BFS: grid rounds share SSSP's chunk, the recursion queue packs coarser
     assert wc.default_tune("bfs", "grid", 1)["items_per_lane"] == 2
-    assert wc.default_tune("bfs", "wave", 1)["items_per_lane"] == 32
+    assert wc.default_tune("bfs", "wave", 1)["items_per_lane"] == 64
     assert wc.default_tune("bfs", "block", 1)["items_per_lane"] == 32
     assert wc.default_tune("tree", "wave", 1)["items_per_lane"] == 32
     assert wc.default_tune("tree", "grid", 1)["items_per_lane"] == 2
